@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Throughput of the FOA step on one MI355X.
+
+Workload: the noisy_2p24x500 snapshot sequence (n = 2^24 rows, N = 500
+snapshots, 120 conjugate-pair modes with amplitudes over 1e0..1e-7, noise
+1e-8, FP32 snapshots), synthetic and generated on the GPU before timing.
+
+One step = one complete FOA run over all N snapshots (every push: partial
+beta column, three fused passes over the basis, reductions, commit), from
+q = 0.  The headline form stores the basis in FP32 with FP64 accumulation
+(CGS2); the plain FP64 form is timed on the same snapshots and reported
+beside it, with the FP32-vs-FP64 error and kappa_2.
+
+Output: one JSON line on stdout; progress on stderr.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+EPS32 = 2.0 ** -23
+
+
+def log(*a):
+    sys.stderr.write(" ".join(str(x) for x in a) + "\n")
+    sys.stderr.flush()
+
+
+def run_form(prec, X, n, N, warmup, steps, options):
+    import torch
+
+    from paper_1805_05821_amd import foa as F
+    from paper_1805_05821_amd.stream import FOAStream
+
+    s = FOAStream(n, N, prec=prec)
+    for k, v in options.items():
+        s.set_option(k, v)
+    for w in range(warmup):
+        s.reset()
+        s.push_all(X)
+        st, q = s.sync()
+        log(f"[{prec}] warmup {w + 1}/{warmup}: q={q} status={st}")
+    F.foa_profile(s.ctx)  # discard
+    s.set_option("profile", 1)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for k in range(steps):
+        s.reset()
+        s.push_all(X)
+        if k + 1 < steps:
+            st, q = s.sync()
+            log(f"[{prec}] step {k + 1}/{steps}: q={q}")
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    st, q = s.sync()
+    launches, kms, kbytes = F.foa_profile(s.ctx)
+    s.set_option("profile", 0)
+    H, B, q, m = s.state()
+    log(f"[{prec}] {steps} steps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), q={q}, "
+        f"row passes {launches} launches {kms:.1f} ms {kbytes / kms / 1e6:.1f} GB/s")
+    res = dict(ms_per_step=ms / steps, wall_s=wall, q=q, status=st, H=H, beta=B, m=m,
+               pass_launches=launches, pass_ms=kms, pass_bytes=kbytes)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(w, rows):
+    import numpy as np
+
+    import datagen
+    import oracle
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    X, _, _ = datagen.snapshots_numpy(w, n=rows, dtype="float32")
+    X64 = np.asfortranarray(X.astype(np.float64))
+    t0 = time.perf_counter()
+    st = oracle.foa_batch(X64)
+    t = time.perf_counter() - t0
+    scale = w.n / rows
+    return dict(value=w.N / (t * scale), unit="snapshots/s", cores=int(threads), kind="oracle",
+                sample=f"oracle FOA over all N={w.N} snapshots of the same workload at n={rows} rows "
+                       f"(1/{scale:g} of the rows), {t:.1f} s; time scaled linearly in n to n={w.n}",
+                seconds=t, q=st.q)
+
+
+def traffic_from_profiles(kind):
+    """Measured HBM bytes per row-pass launch recorded under profiles/ for the
+    current kernel source (None when absent or stale)."""
+    path = os.path.join(ROOT, "profiles", "row_pass_traffic.json")
+    if not os.path.exists(path):
+        return None
+    import hashlib
+
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1805_05821_amd", "csrc", "foa_kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("kernel_source_sha256") != digest:
+        return None
+    return rec.get(kind)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="noisy_2p24x500")
+    ap.add_argument("--n", type=int, default=None, help="override the row count (smaller trial runs)")
+    ap.add_argument("--N", type=int, default=None, help="override the snapshot count")
+    ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 form")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-rows", type=int, default=1 << 18)
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--prefetch", type=int, default=-1)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        log("bench.py measures the FOA step on one GPU only; runs on several GPUs are not "
+            "part of this build (the row-sharded design is described in DESIGN.md).")
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+
+    w = datagen.get_workload(args.workload)
+    if args.n:
+        w = w.with_n(args.n)
+    if args.N:
+        w = w.with_N(args.N)
+    n, N = w.n, w.N
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    X, lam, b = datagen.snapshots_torch(w, "cuda")
+    torch.cuda.synchronize()
+    log(f"generated X ({N} x {n}, {X.dtype}) in {time.perf_counter() - t0:.1f} s")
+
+    options = {"grid": args.grid}
+    if args.prefetch >= 0:
+        options["prefetch"] = args.prefetch
+    r32 = run_form("f32", X, n, N, args.warmup, args.steps, options)
+    r64 = None if args.no_f64 else run_form("f64", X, n, N, args.warmup, args.steps, options)
+
+    snaps = N / (r32["ms_per_step"] / 1e3)
+    achieved = r32["pass_bytes"] / (r32["pass_ms"] / 1e3) / 1e9
+    per_launch_bytes = r32["pass_bytes"] / max(r32["pass_launches"], 1)
+    per_launch_ms = r32["pass_ms"] / max(r32["pass_launches"], 1)
+    traffic = traffic_from_profiles("f32")
+    out = {
+        "metric": "FOA snapshots/s (n=2^24, N=500), FP32-CGS2 basis vs FP64 at stated error",
+        "value": round(snaps, 3),
+        "unit": "snapshots/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "accumulate_dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "N": N, "form": "fp32-basis-cgs2",
+                   "snapshots": "f32", "step": f"one full FOA run over {N} snapshots"},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "fused row pass (k_pass, modes A/B/C)",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "alg_bytes_per_launch": per_launch_bytes,
+            "avg_launch_ms": per_launch_ms,
+            "launches": r32["pass_launches"],
+        },
+        "hbm_gbs_step": round(r32["pass_bytes"] / args.steps / (r32["ms_per_step"] / 1e3) / 1e9, 1),
+    }
+    if r64 is not None:
+        m = min(r32["m"], r64["m"])
+        H32, H64 = r32["H"][:m, :m], r64["H"][:m, :m]
+        s = np.linalg.svd(r64["beta"][:m, :m], compute_uv=False)
+        kap = float(s[0] / s[-1])
+        eH = float(np.linalg.norm(H32 - H64, 2) / np.linalg.norm(H64, 2))
+        snaps64 = N / (r64["ms_per_step"] / 1e3)
+        out["f64_form"] = {
+            "value": round(snaps64, 3),
+            "unit": "snapshots/s",
+            "ms_per_step": round(r64["ms_per_step"], 3),
+            "achieved_gbs": round(r64["pass_bytes"] / (r64["pass_ms"] / 1e3) / 1e9, 1),
+        }
+        out["speedup_f32_vs_f64"] = round(snaps / snaps64, 3)
+        out["error_f32_vs_f64"] = {"rel_H_2norm": eH, "kappa2": kap, "bound_10_eps32_kappa": 10 * EPS32 * kap,
+                                   "within_bound": bool(eH <= 10 * EPS32 * kap)}
+    if not args.no_cpu:
+        log(f"cpu baseline: oracle on {args.cpu_rows} rows ...")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,79 @@
+// Host-side context of one FOA stream (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "foa.h"
+#include "foa_internal.h"
+
+namespace foa {
+
+// Byte offsets of the pieces of one stream's device workspace.
+struct Layout {
+  int64_t P = 0, n_pad = 0;
+  int ldg = 0, ldH = 0, ldB = 0;
+  size_t W = 0, w = 0, part = 0, partn = 0, H = 0, beta = 0, sigma = 0, bvec = 0, h = 0, s = 0;
+  size_t coefA = 0, coefB = 0, coefC = 0, st = 0, total = 0;
+};
+
+Layout make_layout(int64_t n, int n_max, foa_prec prec);
+
+}  // namespace foa
+
+struct foa_ctx_s {
+  int64_t n = 0;
+  int n_max = 0;
+  foa_prec prec = FOA_PREC_F64;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  int device = 0, cus = 0;
+  foa::Layout L;
+  // device pointers (inside ws)
+  void *W = nullptr;
+  double *w = nullptr, *part = nullptr, *partn = nullptr;
+  foa::SmallArgs sa{};
+  // launch configuration
+  int grid_auto = 0, grid_opt = 0;
+  bool prefetch = false;
+  double tol = 0.0;
+  // host view of the state
+  int q_host = 0;     // expected q (exact after a synchronising call)
+  int dev_status = 0; // device status at the last synchronising call
+  int pushes = 0;
+  bool is_view = false;
+  bool mirror_valid = false;
+  std::vector<double> hH, hB, hsigma;
+  // truncation (foa_truncate)
+  int trunc_r = 0;
+  std::vector<double> Ur;     // m x r, column-major
+  std::vector<double> hsv;    // singular values of beta_m
+  std::string err;
+  // row-pass timing (foa_profile)
+  bool profile = false;
+  struct EvPair { hipEvent_t a, b; double bytes; };
+  std::vector<EvPair> ev_pending;
+  std::vector<hipEvent_t> ev_free;
+  double prof_launches = 0, prof_ms = 0, prof_bytes = 0;
+};
+
+namespace foa {
+
+void bind_pointers(foa_ctx_s *c);
+foa_status set_err(foa_ctx_s *c, foa_status st, const char *fmt, ...);
+foa_status hip_err(foa_ctx_s *c, hipError_t e, const char *where);
+foa_status map_status(int s);
+foa_status sync_state(foa_ctx_s *c);
+foa_status refresh_mirror(foa_ctx_s *c);
+foa_status reset_device_state(foa_ctx_s *c);
+foa_status enqueue_push(foa_ctx_s *c, const void *x, bool x_f64);
+int projected_order(const foa_ctx_s *c);
+int pass_grid(const foa_ctx_s *c);
+foa_status collect_profile(foa_ctx_s *c);
+void release_events(foa_ctx_s *c);
+
+}  // namespace foa

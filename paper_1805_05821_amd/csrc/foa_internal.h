@@ -1,0 +1,101 @@
+// Internal declarations shared by the HIP kernels (foa_kernels.hip) and the
+// host side of the C ABI (foa_api.cpp).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace foa {
+
+// Rows per storage panel.  V lives in the workspace in "panel" layout: rows are
+// grouped in panels of PANEL rows; inside a panel the storage is column-major
+// with all n_max columns, so the first j columns of a panel are one contiguous
+// PANEL*j*sizeof(T) range and every wavefront load below reads 1 KiB contiguous.
+constexpr int PANEL = 64;
+
+// Device status codes (mirrors foa_status for the device-detected cases).
+constexpr int ST_ACTIVE = 0;
+constexpr int ST_INVARIANT = 1;
+constexpr int ST_NONFINITE = -4;
+constexpr int ST_ZERO = -8;
+
+// Device-resident scalar state of one stream.
+struct DevState {
+  int q;          // basis vectors committed
+  int status;     // ST_*
+  int pushes;     // snapshots offered (including ignored ones)
+  int pad0;
+  double xfro2;   // ||X_1^q||_F^2 of the committed snapshots
+  double xn2;     // ||x||^2 of the snapshot being pushed
+  double scaleA;  // 1 / beta_{q,q}: scale of step 9 for the next push
+  double tol;     // breakdown tolerance (relative to ||X||_F)
+  double hlast;   // last h_{j+1,j}
+  double pad1[3];
+};
+
+// Pass modes of the fused row kernel.
+enum PassMode : int {
+  PM_INIT = 0,  // q = 0: V(:,0) <- x, partial ||x||^2            (steps 2-3)
+  PM_A = 1,     // w <- (x - V c) * scale, partial V^T w, ||x||^2  (steps 9-10)
+  PM_B = 2,     // w <- w - V c, partial V^T w                     (steps 11-12)
+  PM_C = 3,     // w <- w - V c, V(:,j) <- w, partial ||w||^2      (steps 14-15)
+};
+
+struct PassArgs {
+  const void *W;        // V storage (panel layout), element type TV
+  const void *x;        // snapshot (PM_INIT / PM_A), element type TX
+  double *w;            // FP64 work vector, n_pad entries
+  const double *coef;   // update coefficients, j entries (sigma-scaled)
+  const DevState *st;   // status (read) and scaleA (read for PM_A)
+  double *part;         // column partials, layout part[c * ldg + block]
+  double *partn;        // norm partials, one per block
+  int64_t n;            // valid rows
+  int64_t P;            // panels
+  int j;                // active columns (basis size q)
+  int n_max;            // capacity (columns per panel)
+  int ldg;              // leading dimension of part (>= gridDim.x)
+};
+
+// Small-matrix pointers of one stream (FP64, column-major).
+struct SmallArgs {
+  DevState *st;
+  double *H;       // H_bar, ldH rows
+  double *beta;    // beta, ldB rows
+  double *sigma;   // per-column scale: v_c = sigma_c * stored column c
+  double *bvec;    // partial beta column of the current push (steps 5-8)
+  double *h;       // h_{1:j,j}
+  double *s;       // s_{1:j}
+  double *coefA;   // sigma o b
+  double *coefB;   // sigma o h
+  double *coefC;   // sigma o s
+  const double *part;
+  const double *partn;
+  int ldH, ldB;
+  int n_max;
+  int G;           // partial blocks of the preceding pass
+  int ldg;
+  int j;           // basis size before this push (host's expectation)
+};
+
+// ---- launchers (defined in foa_kernels.hip) --------------------------------
+// tv_f64: V stored in FP64; tx_f64: snapshot in FP64.
+hipError_t launch_pass(int mode, bool tv_f64, bool tx_f64, bool prefetch, int grid,
+                       const PassArgs &a, hipStream_t s);
+hipError_t launch_reduce(int mode, const SmallArgs &a, hipStream_t s);
+hipError_t launch_finalize(const SmallArgs &a, hipStream_t s);
+hipError_t launch_finalize_init(const SmallArgs &a, hipStream_t s);
+hipError_t launch_nextb(const SmallArgs &a, hipStream_t s);
+hipError_t launch_copy_basis(bool tv_f64, const void *W, const double *sigma, int64_t n,
+                             int n_max, int ncols, void *out, int64_t ld, bool out_f64,
+                             hipStream_t s);
+hipError_t launch_init_state(DevState *st, double tol, hipStream_t s);
+// Phi = W * B (B: k x r FP64 host-prepared, sigma folded in), panel-layout W.
+hipError_t launch_modes_gemm(bool tv_f64, const void *W, int64_t n, int n_max, int k,
+                             const void *B, int r, void *out, int64_t ld, bool out_f64,
+                             hipStream_t s);
+
+// Columns covered by one pass kernel instance with QW groups per wave.
+constexpr int cols_per_qw() { return 32; }
+int pick_qw(int j);  // smallest QW in {1,2,4,8,16} with 32*QW >= j
+
+}  // namespace foa

@@ -1,0 +1,548 @@
+// HIP kernels (gfx950) of one FOA push: Algorithm 1 steps 5-18 of
+// Anantharamu & Mahesh, restructured as three fused row passes over the basis.
+//
+// The paper's literal schedule sweeps V five times per snapshot (steps 9, 10,
+// 11, 12 and 14).  Each of steps (9,10), (11,12) and (14,15) is "apply a
+// row-local update with coefficients known before the pass, then reduce over
+// the rows", so one pass over V serves both halves; the two projections must
+// finish globally before the next update, so three sweeps is the minimum for
+// classical Gram-Schmidt with one reorthogonalisation.
+//
+//   pass A : w = (psi - V b) / beta_jj ; partial V^T w ; partial ||psi||^2
+//   reduce : h = V^T w                           (step 10)
+//   pass B : w = w - V h ; partial V^T w         (steps 11-12)
+//   reduce : s = V^T w ; h = h + s               (step 13)
+//   pass C : w = w - V s ; v_{j+1} <- w ; partial ||w||^2   (steps 14-15)
+//   finalize: h_{j+1,j} = ||w||, breakdown test, H_bar column, beta column
+//             (steps 15-18), then the next push's partial beta column
+//             (steps 5-8, eq. betacolumnupdate) in a small multi-block kernel.
+//
+// The basis is stored unnormalised: column c holds fl(w_c) and
+// v_c = sigma_c * column_c with sigma_c = 1 / h_{c,c-1} (sigma_1 = 1/beta_11).
+// Every coefficient vector handed to a pass is pre-multiplied by sigma and every
+// projection is post-multiplied by sigma, so step 15's division never needs its
+// own sweep over n.  All dot products, norms and small-matrix arithmetic are FP64.
+//
+// Reductions are deterministic: every partial sum has a fixed association
+// (per-lane register sums in panel order, butterfly within a wavefront, fixed
+// per-block order); no floating-point atomics are used.
+
+#include <math.h>
+
+#include "foa_internal.h"
+
+namespace foa {
+
+template <typename TV>
+struct Vec;
+template <>
+struct Vec<float> {
+  using T = float4;
+  static constexpr int EPL = 4;  // rows per lane per 16-byte load
+  __device__ static inline void unpack(const T &v, float (&o)[4]) {
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+};
+template <>
+struct Vec<double> {
+  using T = double2;
+  static constexpr int EPL = 2;
+  __device__ static inline void unpack(const T &v, double (&o)[2]) {
+    o[0] = v.x; o[1] = v.y;
+  }
+};
+
+// Wavefronts per workgroup of the row pass: with 32 * QW columns per
+// instance both precisions hold QW 16-byte tile fragments per lane.
+template <typename TV> struct PassNW;
+template <> struct PassNW<float> { static constexpr int value = 8; };
+template <> struct PassNW<double> { static constexpr int value = 16; };
+
+__device__ __forceinline__ double xor_shfl(double v, int m) { return __shfl_xor(v, m, 64); }
+
+// ---------------------------------------------------------------------------
+// Fused row pass.
+//
+// Work decomposition: one workgroup walks panels blockIdx.x, +gridDim.x, ...
+// Within a panel (64 rows x j columns), wavefront `wave` owns column groups
+// g*NW + wave (g < QW); a group is the 1 KiB contiguous block of CPW columns
+// read by one 16-byte load per lane.  Lane l holds rows EPL*(l % LPC) .. +EPL-1
+// of column (group start) + l / LPC.
+//   phase 1 (row sums  u_r = sum_c V_rc coef_c): per-lane FMA over its groups,
+//            butterfly over the lanes sharing rows, then across wavefronts
+//            through LDS in wavefront order;
+//   update  (wavefront 0, one row per lane): w_r = (y_r - u_r) * scale;
+//   phase 2 (column sums V^T w): per-lane FP64 accumulators that persist
+//            across panels; one butterfly per column at the end.
+// ---------------------------------------------------------------------------
+template <typename TV, typename TX, int QW, int MODE, bool PREF>
+__global__ __launch_bounds__(PassNW<TV>::value * 64) void k_pass(PassArgs a) {
+  constexpr int NW = PassNW<TV>::value;
+  using VT = typename Vec<TV>::T;
+  constexpr int EPL = Vec<TV>::EPL;
+  constexpr int LPC = 64 / EPL;  // lanes per 64-row column segment
+  constexpr int CPW = EPL;       // columns per wavefront load
+  constexpr int JCAP = QW * NW * CPW;
+  constexpr bool HAS_P1 = (MODE != PM_INIT);
+  constexpr bool HAS_P2 = (MODE == PM_A || MODE == PM_B);
+
+  __shared__ double s_coef[JCAP];
+  __shared__ double s_red[2][NW][PANEL];
+  __shared__ double s_w[PANEL];
+
+  if (a.st->status != ST_ACTIVE) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  // wavefront index made provably uniform so the panel base stays in SGPRs
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int cs = lane / LPC;
+  const int rg = lane % LPC;
+  const int j = a.j;
+
+  for (int c = tid; c < JCAP; c += NW * 64) s_coef[c] = (c < j) ? a.coef[c] : 0.0;
+  const double scale = (MODE == PM_A) ? a.st->scaleA : 1.0;
+  __syncthreads();
+
+  // Column of this lane in group g: cbase + g * GSTRIDE.
+  constexpr int GSTRIDE = NW * CPW;
+  const int cbase = wave * CPW + cs;
+
+  double acc[QW];
+#pragma unroll
+  for (int g = 0; g < QW; ++g) acc[g] = 0.0;
+  double nrm = 0.0;
+
+  const TV *Wb = static_cast<const TV *>(a.W);
+  const size_t pstride = (size_t)a.n_max * PANEL;
+  const int loff = lane * EPL;
+
+  TV t[QW][EPL];
+  TV tn[QW][EPL];
+
+  auto load_tile = [&](int64_t p, TV (&dst)[QW][EPL]) {
+    // wave-uniform base of this wavefront's first group in panel p
+    const TV *wb = Wb + (size_t)p * pstride + (size_t)(wave * CPW) * PANEL;
+#pragma unroll
+    for (int g = 0; g < QW; ++g) {
+      if (HAS_P1 && cbase + g * GSTRIDE < j) {
+        const VT v = *reinterpret_cast<const VT *>(wb + (size_t)g * GSTRIDE * PANEL + loff);
+        Vec<TV>::unpack(v, dst[g]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) dst[g][e] = TV(0);
+      }
+    }
+  };
+
+  int64_t p = blockIdx.x;
+  if (PREF && p < a.P) load_tile(p, t);
+  int par = 0;
+  for (; p < a.P; p += gridDim.x) {
+    const int64_t row = p * PANEL + lane;
+    double y = 0.0;
+    if (wave == 0) {
+      if (MODE == PM_INIT || MODE == PM_A) {
+        if (row < a.n) y = (double)static_cast<const TX *>(a.x)[row];
+      } else {
+        y = a.w[row];
+      }
+    }
+    if (PREF) {
+      const int64_t pn = p + gridDim.x;
+      if (pn < a.P) load_tile(pn, tn);
+    } else {
+      load_tile(p, t);
+    }
+
+    if (HAS_P1) {
+      double u[EPL];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) u[e] = 0.0;
+#pragma unroll
+      for (int g = 0; g < QW; ++g) {
+        const double cf = s_coef[cbase + g * GSTRIDE];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) u[e] = fma((double)t[g][e], cf, u[e]);
+      }
+#pragma unroll
+      for (int m = LPC; m < 64; m <<= 1) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) u[e] += xor_shfl(u[e], m);
+      }
+      if (cs == 0) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) s_red[par][wave][rg * EPL + e] = u[e];
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double us = 0.0;
+      if (HAS_P1) {
+#pragma unroll
+        for (int w2 = 0; w2 < NW; ++w2) us += s_red[par][w2][lane];
+      }
+      const double wv = (MODE == PM_A) ? (y - us) * scale : (y - us);
+      if (MODE == PM_A || MODE == PM_B) a.w[row] = wv;
+      if (MODE == PM_C || MODE == PM_INIT)
+        const_cast<TV *>(Wb)[(size_t)p * pstride + (size_t)j * PANEL + lane] = (TV)wv;
+      if (MODE == PM_A || MODE == PM_INIT) nrm = fma(y, y, nrm);
+      if (MODE == PM_C) nrm = fma(wv, wv, nrm);
+      if (HAS_P2) s_w[lane] = wv;
+    }
+    if (HAS_P2) {
+      __syncthreads();
+      double wr[EPL];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) wr[e] = s_w[rg * EPL + e];
+      if constexpr (sizeof(TV) == 4) {
+        // Keep only the FP32 tile live across the two phases: convert again
+        // here instead of holding the FP64 copies made in phase 1.
+#pragma unroll
+        for (int g = 0; g < QW; ++g) {
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(t[g][e]));
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < QW; ++g) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) acc[g] = fma((double)t[g][e], wr[e], acc[g]);
+      }
+    }
+    if (PREF) {
+#pragma unroll
+      for (int g = 0; g < QW; ++g) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) t[g][e] = tn[g][e];
+      }
+    }
+    par ^= 1;
+  }
+
+  if (HAS_P2) {
+#pragma unroll
+    for (int g = 0; g < QW; ++g) {
+      double v = acc[g];
+#pragma unroll
+      for (int m = 1; m < LPC; m <<= 1) v += xor_shfl(v, m);
+      const int c = cbase + g * GSTRIDE;
+      if (rg == 0 && c < j) a.part[(size_t)c * a.ldg + blockIdx.x] = v;
+    }
+  }
+  if (MODE != PM_B && wave == 0) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) nrm += xor_shfl(nrm, m);
+    if (lane == 0) a.partn[blockIdx.x] = nrm;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column reduction of the pass partials, one wavefront per column (fixed order:
+// lane-strided sums, then a butterfly).  MODE 1 (after pass A): h = sigma o t,
+// coefB = sigma o h, and the extra wavefront c == j reduces ||psi||^2.
+// MODE 2 (after pass B): s = sigma o t, h += s (step 13), coefC = sigma o s.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_reduce(SmallArgs a) {
+  if (a.st->status != ST_ACTIVE) return;
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c < a.j) {
+    const double *pc = a.part + (size_t)c * a.ldg;
+    double t = 0.0;
+    for (int g = lane; g < a.G; g += 64) t += pc[g];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) t += xor_shfl(t, m);
+    if (lane == 0) {
+      const double sg = a.sigma[c];
+      const double v = sg * t;
+      if (MODE == 1) {
+        a.h[c] = v;
+        a.coefB[c] = sg * v;
+      } else {
+        a.s[c] = v;
+        a.h[c] = a.h[c] + v;
+        a.coefC[c] = sg * v;
+      }
+    }
+  } else if (MODE == 1 && c == a.j) {
+    double t = 0.0;
+    for (int g = lane; g < a.G; g += 64) t += a.partn[g];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) t += xor_shfl(t, m);
+    if (lane == 0) a.st->xn2 = t;
+  }
+}
+
+__device__ double block_sum_256(double t, double *sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = t;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] = sh[tid] + sh[tid + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Steps 15-18 plus the breakdown rule; single workgroup.
+__global__ __launch_bounds__(256) void k_finalize(SmallArgs a) {
+  __shared__ double sh[256];
+  __shared__ int s_status;
+  DevState *st = a.st;
+  const int tid = threadIdx.x;
+  if (st->status != ST_ACTIVE) {
+    if (tid == 0) st->pushes += 1;
+    return;
+  }
+  const int j = a.j;
+  double t = 0.0;
+  for (int g = tid; g < a.G; g += 256) t += a.partn[g];
+  const double wn2 = block_sum_256(t, sh);
+  int bad = 0;
+  for (int i = tid; i < j; i += 256) bad |= !isfinite(a.h[i]);
+  bad = __syncthreads_or(bad);
+  const double bjj = a.beta[(size_t)(j - 1) * a.ldB + (j - 1)];
+  if (tid == 0) {
+    const double hn = sqrt(wn2);
+    const double xn2 = st->xn2;
+    int status = ST_ACTIVE;
+    if (bad || !isfinite(hn) || !isfinite(xn2)) {
+      status = ST_NONFINITE;
+    } else {
+      const double xf = st->xfro2 + xn2;
+      st->xfro2 = xf;
+      st->hlast = hn;
+      if (hn * bjj <= st->tol * sqrt(xf)) status = ST_INVARIANT;
+    }
+    s_status = status;
+  }
+  __syncthreads();
+  const int status = s_status;
+  if (status == ST_NONFINITE) {
+    if (tid == 0) {
+      st->status = ST_NONFINITE;
+      st->pushes += 1;
+    }
+    return;
+  }
+  for (int i = tid; i < j; i += 256) {
+    const double hi = a.h[i];
+    a.H[(size_t)(j - 1) * a.ldH + i] = hi;
+    a.beta[(size_t)j * a.ldB + i] = a.bvec[i] + hi * bjj;  // steps 16-18
+  }
+  if (tid == 0) {
+    if (status == ST_INVARIANT) {
+      a.H[(size_t)(j - 1) * a.ldH + j] = 0.0;
+      a.beta[(size_t)j * a.ldB + j] = 0.0;
+      st->status = ST_INVARIANT;
+    } else {
+      const double hn = st->hlast;
+      a.H[(size_t)(j - 1) * a.ldH + j] = hn;
+      a.beta[(size_t)j * a.ldB + j] = hn * bjj;
+      a.sigma[j] = 1.0 / hn;
+      st->q = j + 1;
+    }
+    st->pushes += 1;
+  }
+}
+
+// Steps 2-3 for the first snapshot.
+__global__ __launch_bounds__(256) void k_finalize_init(SmallArgs a) {
+  __shared__ double sh[256];
+  DevState *st = a.st;
+  const int tid = threadIdx.x;
+  if (st->status != ST_ACTIVE) {
+    if (tid == 0) st->pushes += 1;
+    return;
+  }
+  double t = 0.0;
+  for (int g = tid; g < a.G; g += 256) t += a.partn[g];
+  const double xn2 = block_sum_256(t, sh);
+  if (tid == 0) {
+    const double b11 = sqrt(xn2);
+    if (!isfinite(b11)) {
+      st->status = ST_NONFINITE;
+    } else if (b11 == 0.0) {
+      st->status = ST_ZERO;
+    } else {
+      a.beta[0] = b11;
+      a.sigma[0] = 1.0 / b11;
+      st->xfro2 = xn2;
+      st->q = 1;
+    }
+    st->pushes += 1;
+  }
+}
+
+// Steps 5-8 for the next push (J = q basis vectors):
+//   b_i = sum_{l = max(1, i-1)}^{J-1} h_{i,l} beta_{l,J}  (1-based), i = 1..J,
+// computed as 64 rows x 4 contiguous l-slices per block, slices combined in
+// order.  Also coefA = sigma o b and scaleA = 1 / beta_{J,J}.
+__global__ __launch_bounds__(256) void k_nextb(SmallArgs a) {
+  __shared__ double sh[4][64];
+  DevState *st = a.st;
+  if (st->status != ST_ACTIVE) return;
+  const int J = st->q;
+  const int r = threadIdx.x & 63;
+  const int sl = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + r;  // 0-based row
+  double t = 0.0;
+  if (i < J) {
+    const int lo = i > 0 ? i - 1 : 0;
+    const int hi = J - 1;  // exclusive upper bound (columns 0..J-2)
+    const int len = hi > lo ? hi - lo : 0;
+    const int a0 = lo + (len * sl) / 4;
+    const int a1 = lo + (len * (sl + 1)) / 4;
+    const double *bc = a.beta + (size_t)(J - 1) * a.ldB;
+    for (int l = a0; l < a1; ++l) t = fma(a.H[(size_t)l * a.ldH + i], bc[l], t);
+  }
+  sh[sl][r] = t;
+  __syncthreads();
+  if (sl == 0 && i < J) {
+    const double b = ((sh[0][r] + sh[1][r]) + sh[2][r]) + sh[3][r];
+    a.bvec[i] = b;
+    a.coefA[i] = a.sigma[i] * b;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->scaleA = 1.0 / a.beta[(size_t)(J - 1) * a.ldB + (J - 1)];
+}
+
+__global__ void k_init_state(DevState *st, double tol) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->q = 0;
+    st->status = ST_ACTIVE;
+    st->pushes = 0;
+    st->pad0 = 0;
+    st->xfro2 = 0.0;
+    st->xn2 = 0.0;
+    st->scaleA = 0.0;
+    st->tol = tol;
+    st->hlast = 0.0;
+  }
+}
+
+template <typename TV, typename TO>
+__global__ __launch_bounds__(256) void k_copy_basis(const TV *W, const double *sigma, int64_t n,
+                                                    int n_max, int ncols, TO *out, int64_t ld) {
+  const int c = blockIdx.y;
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n || c >= ncols) return;
+  const int64_t p = r / PANEL;
+  const double v = (double)W[((size_t)p * n_max + c) * PANEL + (r % PANEL)];
+  out[(size_t)c * ld + r] = (TO)(sigma[c] * v);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+int pick_qw(int j) {
+  if (j <= 32) return 1;
+  if (j <= 64) return 2;
+  if (j <= 128) return 4;
+  if (j <= 256) return 8;
+  return 16;
+}
+
+template <typename TV, typename TX, int MODE, bool PREF>
+static hipError_t launch_pass_q(int qw, int grid, const PassArgs &a, hipStream_t s) {
+  constexpr int NT = PassNW<TV>::value * 64;
+  switch (qw) {
+    case 1: hipLaunchKernelGGL((k_pass<TV, TX, 1, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pass<TV, TX, 2, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_pass<TV, TX, 4, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_pass<TV, TX, 8, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_pass<TV, TX, 16, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename TV, typename TX>
+static hipError_t launch_pass_m(int mode, bool pref, int grid, const PassArgs &a, hipStream_t s) {
+  const int qw = pick_qw(a.j);
+  switch (mode) {
+    case PM_INIT: return launch_pass_q<TV, TX, PM_INIT, false>(1, grid, a, s);
+    case PM_A:
+      // FP64 tiles of 16 groups leave no room for a second (prefetched) tile.
+      if (sizeof(TV) == 8 && qw >= 16) pref = false;
+      return pref ? launch_pass_q<TV, TX, PM_A, true>(qw, grid, a, s)
+                  : launch_pass_q<TV, TX, PM_A, false>(qw, grid, a, s);
+    case PM_B:
+      if (sizeof(TV) == 8 && qw >= 16) pref = false;
+      return pref ? launch_pass_q<TV, double, PM_B, true>(qw, grid, a, s)
+                  : launch_pass_q<TV, double, PM_B, false>(qw, grid, a, s);
+    default:
+      if (sizeof(TV) == 8 && qw >= 16) pref = false;
+      return pref ? launch_pass_q<TV, double, PM_C, true>(qw, grid, a, s)
+                  : launch_pass_q<TV, double, PM_C, false>(qw, grid, a, s);
+  }
+}
+
+hipError_t launch_pass(int mode, bool tv_f64, bool tx_f64, bool prefetch, int grid,
+                       const PassArgs &a, hipStream_t s) {
+  if (tv_f64) {
+    return tx_f64 ? launch_pass_m<double, double>(mode, prefetch, grid, a, s)
+                  : launch_pass_m<double, float>(mode, prefetch, grid, a, s);
+  }
+  return tx_f64 ? launch_pass_m<float, double>(mode, prefetch, grid, a, s)
+                : launch_pass_m<float, float>(mode, prefetch, grid, a, s);
+}
+
+hipError_t launch_reduce(int mode, const SmallArgs &a, hipStream_t s) {
+  const int waves = a.j + (mode == 1 ? 1 : 0);
+  const int blocks = (waves + 3) / 4;
+  if (mode == 1)
+    hipLaunchKernelGGL(k_reduce<1>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_reduce<2>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const SmallArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_init(const SmallArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_init, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_nextb(const SmallArgs &a, hipStream_t s) {
+  // J = q after the push is at most j + 1 (host expectation).
+  const int J = a.j + 1;
+  const int blocks = (J + 63) / 64;
+  hipLaunchKernelGGL(k_nextb, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(DevState *st, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_basis(bool tv_f64, const void *W, const double *sigma, int64_t n, int n_max,
+                             int ncols, void *out, int64_t ld, bool out_f64, hipStream_t s) {
+  if (ncols <= 0) return hipSuccess;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
+  if (tv_f64) {
+    if (out_f64)
+      hipLaunchKernelGGL((k_copy_basis<double, double>), grid, dim3(256), 0, s,
+                         (const double *)W, sigma, n, n_max, ncols, (double *)out, ld);
+    else
+      hipLaunchKernelGGL((k_copy_basis<double, float>), grid, dim3(256), 0, s,
+                         (const double *)W, sigma, n, n_max, ncols, (float *)out, ld);
+  } else {
+    if (out_f64)
+      hipLaunchKernelGGL((k_copy_basis<float, double>), grid, dim3(256), 0, s,
+                         (const float *)W, sigma, n, n_max, ncols, (double *)out, ld);
+    else
+      hipLaunchKernelGGL((k_copy_basis<float, float>), grid, dim3(256), 0, s,
+                         (const float *)W, sigma, n, n_max, ncols, (float *)out, ld);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace foa

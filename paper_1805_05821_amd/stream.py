@@ -1,0 +1,84 @@
+"""Convenience wrapper over the C ABI for one FOA stream: allocates the
+workspace as a torch uint8 tensor on the device and forwards every call to
+the functions of ``foa.py`` (argument marshalling only)."""
+
+import numpy as np
+
+from . import foa as F
+
+
+class FOAStream:
+    def __init__(self, n, n_max, prec="f64", device="cuda", stream=None, breakdown_tol=-1.0):
+        import torch
+
+        self.n = int(n)
+        self.n_max = int(n_max)
+        self.prec = F.FOA_PREC_F64 if prec in ("f64", F.FOA_PREC_F64) else F.FOA_PREC_F32
+        nbytes = F.foa_workspace_bytes(self.n, self.n_max, self.prec)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream
+        self.ctx = F.foa_init(self.n, self.n_max, self.prec, self.ws, nbytes, stream, breakdown_tol)
+
+    # pushes ---------------------------------------------------------------
+    def push(self, x):
+        return F.foa_push_snapshot(self.ctx, x)
+
+    def push_all(self, X):
+        """X: (N, n) tensor, one snapshot per row."""
+        for k in range(X.shape[0]):
+            F.foa_push_snapshot(self.ctx, X[k])
+
+    def push_block(self, X):
+        dt = F.FOA_F64 if str(X.dtype) == "torch.float64" else F.FOA_F32
+        return F.foa_push_block(self.ctx, X, X.stride(0), X.shape[0], dt)
+
+    # queries --------------------------------------------------------------
+    def sync(self):
+        return F.foa_sync(self.ctx)
+
+    def state(self):
+        return F.foa_get_state(self.ctx)
+
+    def basis(self, ncols=None, dtype=None):
+        """First ncols Arnoldi vectors as an (ncols, n) tensor (row k = v_{k+1})."""
+        import torch
+
+        if ncols is None:
+            _, ncols = self.sync()
+        dtype = dtype or torch.float64
+        out = torch.empty((max(ncols, 1), self.n), dtype=dtype, device=self.ws.device)
+        F.foa_copy_basis(self.ctx, out, self.n, F.FOA_F64 if dtype == torch.float64 else F.FOA_F32, ncols)
+        return out[:ncols]
+
+    def truncate(self, rel_tol=-1.0, r_force=0):
+        return F.foa_truncate(self.ctx, rel_tol, r_force)
+
+    def modes(self, m_max=None, phi=None, phi_cols=0, phi_dtype=F.FOA_F32):
+        m_max = m_max or self.n_max
+        ld = self.n if phi is not None else 0
+        return F.foa_modes(self.ctx, m_max, phi, ld, phi_cols, phi_dtype)
+
+    def indicators(self, m_max=None):
+        return F.foa_indicators(self.ctx, m_max or self.n_max)
+
+    def set_option(self, key, value):
+        return F.foa_set_option(self.ctx, key, value)
+
+    def reset(self):
+        return F.foa_reset(self.ctx)
+
+    def close(self):
+        if self.ctx is not None:
+            F.foa_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hbar_beta_numpy(stream):
+    H, B, q, m = stream.state()
+    return np.asarray(H), np.asarray(B), q, m
