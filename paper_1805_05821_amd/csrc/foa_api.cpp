@@ -61,6 +61,7 @@ Layout make_layout(int64_t n, int n_max, foa_prec prec) {
   L.coefB = take(vec);
   L.coefC = take(vec);
   L.st = take(sizeof(DevState));
+  L.mcoef = take((size_t)n_max * n_max * 8);
   L.total = off;
   return L;
 }
@@ -225,6 +226,7 @@ foa_status enqueue_push(foa_ctx_s *c, const void *x, bool x_f64) {
   if ((e = launch_nextb(sa, s)) != hipSuccess) return hip_err(c, e, "next b");
   c->q_host = j + 1;
   c->mirror_valid = false;
+  c->dmd.valid = false;
   return FOA_OK;
 }
 
@@ -275,7 +277,9 @@ foa_status reset_device_state(foa_ctx_s *c) {
   c->pushes = 0;
   c->mirror_valid = false;
   c->trunc_r = 0;
+  c->trunc_m = 0;
   c->Ur.clear();
+  c->dmd.valid = false;
   return FOA_OK;
 }
 

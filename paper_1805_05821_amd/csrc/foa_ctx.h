@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <complex>
 #include <cstdarg>
 #include <string>
 #include <vector>
@@ -17,7 +18,22 @@ struct Layout {
   int64_t P = 0, n_pad = 0;
   int ldg = 0, ldH = 0, ldB = 0;
   size_t W = 0, w = 0, part = 0, partn = 0, H = 0, beta = 0, sigma = 0, bvec = 0, h = 0, s = 0;
-  size_t coefA = 0, coefB = 0, coefC = 0, st = 0, total = 0;
+  size_t coefA = 0, coefB = 0, coefC = 0, st = 0, mcoef = 0, total = 0;
+};
+
+// Eigen-decomposition of the projected matrix and everything derived from it
+// (cached until the next push, reset or truncation change).
+struct DmdCache {
+  bool valid = false;
+  int m = 0;        // order of H_m
+  int r = 0;        // truncation rank (0: untruncated)
+  int k = 0;        // order of the eigenproblem (m or r)
+  std::vector<std::complex<double>> lam;   // k eigenvalues
+  std::vector<std::complex<double>> B;     // m x k: mode coefficients in the V_{1:m} basis
+  std::vector<std::complex<double>> coef;  // k coefficients of psi_1
+  std::vector<double> ind;                 // k error indicators
+  std::vector<int> is_real;                // k
+  std::vector<int> entries;                // eigen indices, one per real / pair, in mode order
 };
 
 Layout make_layout(int64_t n, int n_max, foa_prec prec);
@@ -50,6 +66,8 @@ struct foa_ctx_s {
   std::vector<double> hH, hB, hsigma;
   // truncation (foa_truncate)
   int trunc_r = 0;
+  int trunc_m = 0;            // m the truncation was computed for
+  foa::DmdCache dmd;
   std::vector<double> Ur;     // m x r, column-major
   std::vector<double> hsv;    // singular values of beta_m
   std::string err;

@@ -89,9 +89,11 @@ hipError_t launch_copy_basis(bool tv_f64, const void *W, const double *sigma, in
                              int n_max, int ncols, void *out, int64_t ld, bool out_f64,
                              hipStream_t s);
 hipError_t launch_init_state(DevState *st, double tol, hipStream_t s);
-// Phi = W * B (B: k x r FP64 host-prepared, sigma folded in), panel-layout W.
+// Phi = W * B for the panel-layout basis W (n x k used columns) and the
+// k x r FP64 coefficient matrix B (column-major, leading dimension k, sigma
+// already folded in); Phi is column-major with leading dimension ld.
 hipError_t launch_modes_gemm(bool tv_f64, const void *W, int64_t n, int n_max, int k,
-                             const void *B, int r, void *out, int64_t ld, bool out_f64,
+                             const double *B, int r, void *out, int64_t ld, bool out_f64,
                              hipStream_t s);
 
 // Columns covered by one pass kernel instance with QW groups per wave.

@@ -34,7 +34,8 @@ def _compare_f64(g, st, c=100.0):
     assert g["m"] == m
     kap = kappa_of(st.beta[:max(m, 1), :max(m, 1)]) if m > 0 else 1.0
     tol = c * EPS64 * max(kap, 1.0) * q
-    eH = rel(g["H"][:q + 1, :m], st.H[:q + 1, :m])
+    rows = min(q + 1, st.H.shape[0])
+    eH = rel(g["H"][:rows, :m], st.H[:rows, :m])
     bc = q + 1 if st.status == "invariant" else q
     eB = rel(g["beta"][:q, :bc], st.beta[:q, :bc])
     eV = np.abs(g["V"] - st.V[:, :q]).max()
