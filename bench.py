@@ -132,7 +132,21 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1 << 18)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--prefetch", type=int, default=-1)
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device-to-device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_calibration > 0:
+        import torch
+
+        nbytes = int(args.copy_calibration * (1 << 30)) // 4 * 4
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 3}), flush=True)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

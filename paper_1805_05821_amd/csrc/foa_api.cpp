@@ -270,7 +270,7 @@ foa_status refresh_mirror(foa_ctx_s *c) {
 }
 
 foa_status reset_device_state(foa_ctx_s *c) {
-  hipError_t e = launch_init_state(c->sa.st, c->tol, c->stream);
+  hipError_t e = launch_init_state(c->sa, c->tol, c->stream);
   if (e != hipSuccess) return hip_err(c, e, "init state");
   c->q_host = 0;
   c->dev_status = ST_ACTIVE;

@@ -410,7 +410,25 @@ __global__ __launch_bounds__(256) void k_nextb(SmallArgs a) {
   if (blockIdx.x == 0 && threadIdx.x == 0) st->scaleA = 1.0 / a.beta[(size_t)(J - 1) * a.ldB + (J - 1)];
 }
 
-__global__ void k_init_state(DevState *st, double tol) {
+// Reset of one stream: scalar state, and zeros in every small array (the
+// entries of H_bar below the subdiagonal and of beta below the diagonal are
+// never written by the push kernels and must read as zero).
+__global__ __launch_bounds__(256) void k_init_state(SmallArgs a, double tol) {
+  const size_t nH = (size_t)a.ldH * (a.n_max + 1), nB = (size_t)a.ldB * (a.n_max + 1);
+  const size_t nv = (size_t)a.n_max + 1;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nH; i += stride) a.H[i] = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nB; i += stride) a.beta[i] = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+    a.sigma[i] = 0.0;
+    a.bvec[i] = 0.0;
+    a.h[i] = 0.0;
+    a.s[i] = 0.0;
+    a.coefA[i] = 0.0;
+    a.coefB[i] = 0.0;
+    a.coefC[i] = 0.0;
+  }
+  DevState *st = a.st;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->q = 0;
     st->status = ST_ACTIVE;
@@ -518,8 +536,8 @@ hipError_t launch_nextb(const SmallArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_init_state(DevState *st, double tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, tol);
+hipError_t launch_init_state(const SmallArgs &a, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_state, dim3(64), dim3(256), 0, s, a, tol);
   return hipGetLastError();
 }
 

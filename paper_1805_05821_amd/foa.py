@@ -47,6 +47,13 @@ class FOAError(RuntimeError):
 
 
 def _load():
+    # torch ships its own HIP runtime under the same soname as the system one
+    # (libamdhip64.so.7).  Load torch first so the library binds to that one
+    # runtime: the streams and allocations it receives come from torch.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_1805_05821_amd.build` "

@@ -8,7 +8,7 @@ from . import foa as F
 
 
 class FOAStream:
-    def __init__(self, n, n_max, prec="f64", device="cuda", stream=None, breakdown_tol=-1.0):
+    def __init__(self, n, n_max, prec="f64", device="cuda", stream=None, breakdown_tol=-1.0, ws_fill=None):
         import torch
 
         self.n = int(n)
@@ -16,6 +16,8 @@ class FOAStream:
         self.prec = F.FOA_PREC_F64 if prec in ("f64", F.FOA_PREC_F64) else F.FOA_PREC_F32
         nbytes = F.foa_workspace_bytes(self.n, self.n_max, self.prec)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        if ws_fill is not None:  # tests: start from a workspace full of a given byte
+            self.ws.fill_(int(ws_fill))
         self.stream = stream
         self.ctx = F.foa_init(self.n, self.n_max, self.prec, self.ws, nbytes, stream, breakdown_tol)
 

@@ -44,6 +44,25 @@ def _compare_f64(g, st, c=100.0):
     return kap
 
 
+@pytest.mark.parametrize("n", [777, 2048, 20000])
+def test_f64_tight_well_conditioned(n):
+    """kappa_2(X) ~ 3: GPU and oracle agree to a few ulps scaled by q."""
+    from pins import _known_A, _krylov
+
+    A, psi1 = _known_A(n=n, seed=31)
+    X = _krylov(A, psi1, 30)
+    st = oracle.foa_batch(X, tol=0.0)
+    g = run_gpu(X, "f64", tol=0.0)
+    q, m = g["q"], g["m"]
+    assert q == st.q == 30
+    eH = np.abs(g["H"][:q, :m] - st.H[:q, :m]).max() / np.abs(st.H[:q, :m]).max()
+    eB = np.abs(g["beta"][:q, :q] - st.beta[:q, :q]).max() / np.abs(st.beta[:q, :q]).max()
+    eV = np.abs(g["V"] - st.V[:, :q]).max()
+    announce(f"relH={eH:.2e} relB={eB:.2e} maxV={eV:.2e}")
+    tol = 10 * q * EPS64
+    assert eH <= tol and eB <= tol and eV <= tol
+
+
 def test_exact_rank_recovers_eigenvalues():
     w = datagen.get_workload("exact_rank_4096x64")
     X, lam, _ = datagen.snapshots_numpy(w)
