@@ -169,7 +169,8 @@ const char *foa_last_error(foa_ctx ctx);
 
 /* Tuning knobs (tests and benchmarks): "grid" (workgroups of the row passes,
  * 0 = automatic), "prefetch" (0/1: register double buffering of the next
- * panel), "profile" (0/1: see foa_profile).  FOA_E_ARG for an unknown key. */
+ * panel), "nw" (8 or 16: wavefronts per row-pass workgroup for an FP32 basis),
+ * "profile" (0/1: see foa_profile).  FOA_E_ARG for an unknown key. */
 foa_status foa_set_option(foa_ctx ctx, const char *key, int64_t value);
 
 /* Timing of the row passes, enabled with foa_set_option(ctx, "profile", 1):

@@ -146,7 +146,7 @@ static hipError_t timed_pass(foa_ctx_s *c, int mode, bool v64, bool x64, bool pr
     e1 = take_event(c);
     if (e0 && e1) (void)hipEventRecord(e0, c->stream);
   }
-  hipError_t e = launch_pass(mode, v64, x64, pref, G, pa, c->stream);
+  hipError_t e = launch_pass(mode, v64, x64, pref, c->nw, G, pa, c->stream);
   if (c->profile && e0 && e1) {
     (void)hipEventRecord(e1, c->stream);
     c->ev_pending.push_back({e0, e1, alg_bytes});
@@ -339,7 +339,8 @@ foa_status foa_init(foa_ctx *out, int64_t n, int32_t n_max, foa_prec prec, void 
   c->device = dev;
   c->cus = cus;
   c->grid_auto = 2 * cus;
-  c->prefetch = prec == FOA_PREC_F32;
+  c->prefetch = true;  // register double buffering wherever the tile fits
+  c->nw = 8;           // FP32 basis: 8 wavefronts per row-pass workgroup
   c->tol = breakdown_tol < 0 ? (double)n_max * std::ldexp(1.0, -52) : breakdown_tol;
   bind_pointers(c);
   foa_status r = reset_device_state(c);
@@ -360,6 +361,11 @@ foa_status foa_set_option(foa_ctx c, const char *key, int64_t value) {
   }
   if (!std::strcmp(key, "prefetch")) {
     c->prefetch = value != 0;
+    return FOA_OK;
+  }
+  if (!std::strcmp(key, "nw")) {
+    if (value != 8 && value != 16) return set_err(c, FOA_E_ARG, "nw must be 8 or 16");
+    c->nw = (int)value;
     return FOA_OK;
   }
   if (!std::strcmp(key, "profile")) {

@@ -56,6 +56,7 @@ struct foa_ctx_s {
   // launch configuration
   int grid_auto = 0, grid_opt = 0;
   bool prefetch = false;
+  int nw = 16;  // wavefronts per row-pass workgroup (FP32 basis: 8 or 16)
   double tol = 0.0;
   // host view of the state
   int q_host = 0;     // expected q (exact after a synchronising call)

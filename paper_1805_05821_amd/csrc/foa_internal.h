@@ -79,7 +79,8 @@ struct SmallArgs {
 
 // ---- launchers (defined in foa_kernels.hip) --------------------------------
 // tv_f64: V stored in FP64; tx_f64: snapshot in FP64.
-hipError_t launch_pass(int mode, bool tv_f64, bool tx_f64, bool prefetch, int grid,
+// nw: wavefronts per workgroup for an FP32 basis (8 or 16; FP64 uses 16).
+hipError_t launch_pass(int mode, bool tv_f64, bool tx_f64, bool prefetch, int nw, int grid,
                        const PassArgs &a, hipStream_t s);
 hipError_t launch_reduce(int mode, const SmallArgs &a, hipStream_t s);
 hipError_t launch_finalize(const SmallArgs &a, hipStream_t s);
@@ -96,8 +97,6 @@ hipError_t launch_modes_gemm(bool tv_f64, const void *W, int64_t n, int n_max, i
                              const double *B, int r, void *out, int64_t ld, bool out_f64,
                              hipStream_t s);
 
-// Columns covered by one pass kernel instance with QW groups per wave.
-constexpr int cols_per_qw() { return 32; }
-int pick_qw(int j);  // smallest QW in {1,2,4,8,16} with 32*QW >= j
+int pick_qw(int j, int cols_per_qw);
 
 }  // namespace foa

@@ -34,31 +34,73 @@
 namespace foa {
 
 template <typename TV>
-struct Vec;
-template <>
-struct Vec<float> {
-  using T = float4;
-  static constexpr int EPL = 4;  // rows per lane per 16-byte load
-  __device__ static inline void unpack(const T &v, float (&o)[4]) {
-    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-  }
-};
-template <>
-struct Vec<double> {
-  using T = double2;
-  static constexpr int EPL = 2;
-  __device__ static inline void unpack(const T &v, double (&o)[2]) {
-    o[0] = v.x; o[1] = v.y;
-  }
+struct Vec {
+  static constexpr int EPL = 16 / sizeof(TV);  // rows per lane per 16-byte load
 };
 
-// Wavefronts per workgroup of the row pass: with 32 * QW columns per
-// instance both precisions hold QW 16-byte tile fragments per lane.
-template <typename TV> struct PassNW;
-template <> struct PassNW<float> { static constexpr int value = 8; };
-template <> struct PassNW<double> { static constexpr int value = 16; };
 
 __device__ __forceinline__ double xor_shfl(double v, int m) { return __shfl_xor(v, m, 64); }
+
+// ---------------------------------------------------------------------------
+// Buffer-resource helpers.  Every global access of the row pass is an
+// unconditional buffer load/store on a per-panel resource: the hardware range
+// check (offset >= num_records) returns 0 for loads and drops stores, which
+// masks dead columns, padded rows and idle lanes without branches, so the
+// compiler can count outstanding memory operations exactly and keep the
+// prefetched panel in flight across the compute of the current one.
+// ---------------------------------------------------------------------------
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kRsrcWord3 = 0x00020000;   // raw buffer, 32-bit data format (CDNA)
+constexpr unsigned kOOR = 0x80000000u;   // offset beyond every range used below
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ double buf_load_scalar(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ double buf_load_scalar<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load_scalar<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store_scalar(T v, __amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ void buf_store_scalar<float>(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void buf_store_scalar<double>(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+
+// Whole-vector bit casts only: casting a single element lvalue of an
+// ext_vector (e.g. __builtin_bit_cast(float, v.y)) reads element 0.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename TV>
+__device__ __forceinline__ void unpack16(const u32x4 &v, TV (&o)[16 / sizeof(TV)]);
+template <>
+__device__ __forceinline__ void unpack16<float>(const u32x4 &v, float (&o)[4]) {
+  const f32x4 f = __builtin_bit_cast(f32x4, v);
+  o[0] = f.x;
+  o[1] = f.y;
+  o[2] = f.z;
+  o[3] = f.w;
+}
+template <>
+__device__ __forceinline__ void unpack16<double>(const u32x4 &v, double (&o)[2]) {
+  const f64x2 d = __builtin_bit_cast(f64x2, v);
+  o[0] = d.x;
+  o[1] = d.y;
+}
 
 // ---------------------------------------------------------------------------
 // Fused row pass.
@@ -71,30 +113,33 @@ __device__ __forceinline__ double xor_shfl(double v, int m) { return __shfl_xor(
 //   phase 1 (row sums  u_r = sum_c V_rc coef_c): per-lane FMA over its groups,
 //            butterfly over the lanes sharing rows, then across wavefronts
 //            through LDS in wavefront order;
-//   update  (wavefront 0, one row per lane): w_r = (y_r - u_r) * scale;
+//   update  (every wavefront, 64/NW rows each): w_r = (y_r - u_r) * scale;
 //   phase 2 (column sums V^T w): per-lane FP64 accumulators that persist
 //            across panels; one butterfly per column at the end.
+// With PREF the next panel's tile is loaded while the current one is reduced.
 // ---------------------------------------------------------------------------
-template <typename TV, typename TX, int QW, int MODE, bool PREF>
-__global__ __launch_bounds__(PassNW<TV>::value * 64) void k_pass(PassArgs a) {
-  constexpr int NW = PassNW<TV>::value;
-  using VT = typename Vec<TV>::T;
+template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
+__global__ __launch_bounds__(NW * 64) void k_pass(PassArgs a) {
   constexpr int EPL = Vec<TV>::EPL;
   constexpr int LPC = 64 / EPL;  // lanes per 64-row column segment
   constexpr int CPW = EPL;       // columns per wavefront load
   constexpr int JCAP = QW * NW * CPW;
+  constexpr int RPW = PANEL / NW;  // rows updated by each wavefront
   constexpr bool HAS_P1 = (MODE != PM_INIT);
   constexpr bool HAS_P2 = (MODE == PM_A || MODE == PM_B);
+  constexpr bool SRC_X = (MODE == PM_INIT || MODE == PM_A);
+  constexpr int GSTRIDE = NW * CPW;  // columns between a wavefront's groups
 
   __shared__ double s_coef[JCAP];
   __shared__ double s_red[2][NW][PANEL];
   __shared__ double s_w[PANEL];
+  __shared__ double s_nrm[NW];
 
   if (a.st->status != ST_ACTIVE) return;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  // wavefront index made provably uniform so the panel base stays in SGPRs
+  // wavefront index made provably uniform so per-wave offsets stay scalar
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int cs = lane / LPC;
   const int rg = lane % LPC;
@@ -104,55 +149,69 @@ __global__ __launch_bounds__(PassNW<TV>::value * 64) void k_pass(PassArgs a) {
   const double scale = (MODE == PM_A) ? a.st->scaleA : 1.0;
   __syncthreads();
 
-  // Column of this lane in group g: cbase + g * GSTRIDE.
-  constexpr int GSTRIDE = NW * CPW;
-  const int cbase = wave * CPW + cs;
+  const int cbase = wave * CPW + cs;  // column of this lane in group 0
+  // byte offset of this lane's 16-byte fragment of group g: goff0 + g * GBYTES
+  const unsigned goff0 = (unsigned)((wave * CPW * PANEL + lane * EPL) * sizeof(TV));
+  constexpr unsigned GBYTES = (unsigned)(GSTRIDE * PANEL * sizeof(TV));
+  const unsigned tile_bytes = (unsigned)(j * PANEL * sizeof(TV));
+  // update rows: lane < RPW owns panel row urow; the others only carry values
+  const bool uact = lane < RPW;
+  const int urow = wave * RPW + (lane % RPW);
 
   double acc[QW];
 #pragma unroll
   for (int g = 0; g < QW; ++g) acc[g] = 0.0;
   double nrm = 0.0;
 
-  const TV *Wb = static_cast<const TV *>(a.W);
-  const size_t pstride = (size_t)a.n_max * PANEL;
-  const int loff = lane * EPL;
+  const char *Wb = static_cast<const char *>(a.W);
+  const size_t pbytes = (size_t)a.n_max * PANEL * sizeof(TV);
 
   TV t[QW][EPL];
   TV tn[QW][EPL];
 
-  auto load_tile = [&](int64_t p, TV (&dst)[QW][EPL]) {
-    // wave-uniform base of this wavefront's first group in panel p
-    const TV *wb = Wb + (size_t)p * pstride + (size_t)(wave * CPW) * PANEL;
+  // bytes = 0 turns every load into an out-of-range load returning 0 without
+  // memory traffic (used past the last panel, so the loop has no branch
+  // around its loads).
+  auto load_tile = [&](int64_t p, TV (&dst)[QW][EPL], unsigned bytes) {
+    if (!HAS_P1) return;
+    const __amdgpu_buffer_rsrc_t rt = make_rsrc(Wb + (size_t)p * pbytes, bytes);
 #pragma unroll
     for (int g = 0; g < QW; ++g) {
-      if (HAS_P1 && cbase + g * GSTRIDE < j) {
-        const VT v = *reinterpret_cast<const VT *>(wb + (size_t)g * GSTRIDE * PANEL + loff);
-        Vec<TV>::unpack(v, dst[g]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) dst[g][e] = TV(0);
-      }
+      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rt, (int)(goff0 + g * GBYTES), 0, 0);
+      unpack16<TV>(v, dst[g]);
     }
   };
 
   int64_t p = blockIdx.x;
-  if (PREF && p < a.P) load_tile(p, t);
+  if (PREF && p < a.P) {
+    load_tile(p, t, tile_bytes);
+    // Complete the first tile before the loop: otherwise its pending loads
+    // merge with the loop back edge and every iteration waits for the
+    // prefetched tile before phase 1.
+#pragma unroll
+    for (int g = 0; g < QW; ++g) {
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(t[g][e]));
+    }
+  }
   int par = 0;
   for (; p < a.P; p += gridDim.x) {
-    const int64_t row = p * PANEL + lane;
-    double y = 0.0;
-    if (wave == 0) {
-      if (MODE == PM_INIT || MODE == PM_A) {
-        if (row < a.n) y = (double)static_cast<const TX *>(a.x)[row];
-      } else {
-        y = a.w[row];
-      }
+    // y for the update rows of this wavefront (snapshot or work vector)
+    double y;
+    if (SRC_X) {
+      const int64_t rem = a.n - p * PANEL;
+      const unsigned xb = (unsigned)((rem >= PANEL ? PANEL : (rem > 0 ? rem : 0)) * sizeof(TX));
+      const __amdgpu_buffer_rsrc_t rx = make_rsrc(static_cast<const TX *>(a.x) + p * PANEL, xb);
+      y = buf_load_scalar<TX>(rx, uact ? (unsigned)(urow * sizeof(TX)) : kOOR);
+    } else {
+      const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.w + p * PANEL, PANEL * 8);
+      y = buf_load_scalar<double>(rw, uact ? (unsigned)(urow * 8) : kOOR);
     }
     if (PREF) {
-      const int64_t pn = p + gridDim.x;
-      if (pn < a.P) load_tile(pn, tn);
+      const bool more = p + gridDim.x < a.P;
+      load_tile(more ? p + gridDim.x : p, tn, more ? tile_bytes : 0u);
     } else {
-      load_tile(p, t);
+      load_tile(p, t, tile_bytes);
     }
 
     if (HAS_P1) {
@@ -174,21 +233,27 @@ __global__ __launch_bounds__(PassNW<TV>::value * 64) void k_pass(PassArgs a) {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) s_red[par][wave][rg * EPL + e] = u[e];
       }
+      __syncthreads();
     }
-    __syncthreads();
-    if (wave == 0) {
-      double us = 0.0;
-      if (HAS_P1) {
+    double us = 0.0;
+    if (HAS_P1) {
 #pragma unroll
-        for (int w2 = 0; w2 < NW; ++w2) us += s_red[par][w2][lane];
-      }
-      const double wv = (MODE == PM_A) ? (y - us) * scale : (y - us);
-      if (MODE == PM_A || MODE == PM_B) a.w[row] = wv;
-      if (MODE == PM_C || MODE == PM_INIT)
-        const_cast<TV *>(Wb)[(size_t)p * pstride + (size_t)j * PANEL + lane] = (TV)wv;
-      if (MODE == PM_A || MODE == PM_INIT) nrm = fma(y, y, nrm);
+      for (int w2 = 0; w2 < NW; ++w2) us += s_red[par][w2][urow];
+    }
+    const double wv = (MODE == PM_A) ? (y - us) * scale : (y - us);
+    if (MODE == PM_A || MODE == PM_B) {
+      const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.w + p * PANEL, PANEL * 8);
+      buf_store_scalar<double>(wv, rw, uact ? (unsigned)(urow * 8) : kOOR);
+    }
+    if (MODE == PM_C || MODE == PM_INIT) {
+      const __amdgpu_buffer_rsrc_t rv =
+          make_rsrc(Wb + (size_t)p * pbytes + (size_t)j * PANEL * sizeof(TV), PANEL * sizeof(TV));
+      buf_store_scalar<TV>((TV)wv, rv, uact ? (unsigned)(urow * sizeof(TV)) : kOOR);
+    }
+    if (uact) {
+      if (SRC_X) nrm = fma(y, y, nrm);
       if (MODE == PM_C) nrm = fma(wv, wv, nrm);
-      if (HAS_P2) s_w[lane] = wv;
+      if (HAS_P2) s_w[urow] = wv;
     }
     if (HAS_P2) {
       __syncthreads();
@@ -211,6 +276,13 @@ __global__ __launch_bounds__(PassNW<TV>::value * 64) void k_pass(PassArgs a) {
       }
     }
     if (PREF) {
+      // The prefetched tile is first needed here: keep the register moves
+      // (and with them the wait for its loads) at the end of the iteration.
+#pragma unroll
+      for (int g = 0; g < QW; ++g) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(tn[g][e]));
+      }
 #pragma unroll
       for (int g = 0; g < QW; ++g) {
 #pragma unroll
@@ -230,10 +302,16 @@ __global__ __launch_bounds__(PassNW<TV>::value * 64) void k_pass(PassArgs a) {
       if (rg == 0 && c < j) a.part[(size_t)c * a.ldg + blockIdx.x] = v;
     }
   }
-  if (MODE != PM_B && wave == 0) {
+  if (MODE != PM_B) {
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) nrm += xor_shfl(nrm, m);
-    if (lane == 0) a.partn[blockIdx.x] = nrm;
+    if (lane == 0) s_nrm[wave] = nrm;
+    __syncthreads();
+    if (tid == 0) {
+      double t2 = 0.0;
+      for (int w2 = 0; w2 < NW; ++w2) t2 += s_nrm[w2];
+      a.partn[blockIdx.x] = t2;
+    }
   }
 }
 
@@ -456,56 +534,68 @@ __global__ __launch_bounds__(256) void k_copy_basis(const TV *W, const double *s
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-int pick_qw(int j) {
-  if (j <= 32) return 1;
-  if (j <= 64) return 2;
-  if (j <= 128) return 4;
-  if (j <= 256) return 8;
-  return 16;
+// Smallest QW in {1, 2, 4, 8, 16} whose instance covers j columns when one
+// QW step spans cols_per_qw columns.
+int pick_qw(int j, int cols_per_qw) {
+  int qw = 1;
+  while (qw < 16 && qw * cols_per_qw < j) qw *= 2;
+  return qw;
 }
 
-template <typename TV, typename TX, int MODE, bool PREF>
+template <typename TV, typename TX, int NW, int MODE, bool PREF>
 static hipError_t launch_pass_q(int qw, int grid, const PassArgs &a, hipStream_t s) {
-  constexpr int NT = PassNW<TV>::value * 64;
+  constexpr int NT = NW * 64;
   switch (qw) {
-    case 1: hipLaunchKernelGGL((k_pass<TV, TX, 1, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pass<TV, TX, 2, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_pass<TV, TX, 4, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_pass<TV, TX, 8, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pass<TV, TX, 16, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_pass<TV, TX, NW, 1, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pass<TV, TX, NW, 2, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_pass<TV, TX, NW, 4, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_pass<TV, TX, NW, 8, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    default:
+      if constexpr (NW * 16 * Vec<TV>::EPL <= 512)
+        hipLaunchKernelGGL((k_pass<TV, TX, NW, 16, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a);
+      else
+        return hipErrorInvalidValue;
+      break;
   }
   return hipGetLastError();
 }
 
-template <typename TV, typename TX>
+// Register budget: a 16-group FP64 tile (64 VGPRs) cannot be double buffered
+// within the 128 VGPRs a 16-wavefront workgroup allows.
+template <typename TV, int NW>
+static bool prefetch_fits(int qw) {
+  return !(sizeof(TV) == 8 && NW == 16 && qw >= 16);
+}
+
+template <typename TV, typename TX, int NW>
 static hipError_t launch_pass_m(int mode, bool pref, int grid, const PassArgs &a, hipStream_t s) {
-  const int qw = pick_qw(a.j);
+  const int qw = pick_qw(a.j, NW * Vec<TV>::EPL);
+  pref = pref && prefetch_fits<TV, NW>(qw);
   switch (mode) {
-    case PM_INIT: return launch_pass_q<TV, TX, PM_INIT, false>(1, grid, a, s);
+    case PM_INIT: return launch_pass_q<TV, TX, NW, PM_INIT, false>(1, grid, a, s);
     case PM_A:
-      // FP64 tiles of 16 groups leave no room for a second (prefetched) tile.
-      if (sizeof(TV) == 8 && qw >= 16) pref = false;
-      return pref ? launch_pass_q<TV, TX, PM_A, true>(qw, grid, a, s)
-                  : launch_pass_q<TV, TX, PM_A, false>(qw, grid, a, s);
+      return pref ? launch_pass_q<TV, TX, NW, PM_A, true>(qw, grid, a, s)
+                  : launch_pass_q<TV, TX, NW, PM_A, false>(qw, grid, a, s);
     case PM_B:
-      if (sizeof(TV) == 8 && qw >= 16) pref = false;
-      return pref ? launch_pass_q<TV, double, PM_B, true>(qw, grid, a, s)
-                  : launch_pass_q<TV, double, PM_B, false>(qw, grid, a, s);
+      return pref ? launch_pass_q<TV, double, NW, PM_B, true>(qw, grid, a, s)
+                  : launch_pass_q<TV, double, NW, PM_B, false>(qw, grid, a, s);
     default:
-      if (sizeof(TV) == 8 && qw >= 16) pref = false;
-      return pref ? launch_pass_q<TV, double, PM_C, true>(qw, grid, a, s)
-                  : launch_pass_q<TV, double, PM_C, false>(qw, grid, a, s);
+      return pref ? launch_pass_q<TV, double, NW, PM_C, true>(qw, grid, a, s)
+                  : launch_pass_q<TV, double, NW, PM_C, false>(qw, grid, a, s);
   }
 }
 
-hipError_t launch_pass(int mode, bool tv_f64, bool tx_f64, bool prefetch, int grid,
+hipError_t launch_pass(int mode, bool tv_f64, bool tx_f64, bool prefetch, int nw, int grid,
                        const PassArgs &a, hipStream_t s) {
   if (tv_f64) {
-    return tx_f64 ? launch_pass_m<double, double>(mode, prefetch, grid, a, s)
-                  : launch_pass_m<double, float>(mode, prefetch, grid, a, s);
+    return tx_f64 ? launch_pass_m<double, double, 16>(mode, prefetch, grid, a, s)
+                  : launch_pass_m<double, float, 16>(mode, prefetch, grid, a, s);
   }
-  return tx_f64 ? launch_pass_m<float, double>(mode, prefetch, grid, a, s)
-                : launch_pass_m<float, float>(mode, prefetch, grid, a, s);
+  if (nw == 8)
+    return tx_f64 ? launch_pass_m<float, double, 8>(mode, prefetch, grid, a, s)
+                  : launch_pass_m<float, float, 8>(mode, prefetch, grid, a, s);
+  return tx_f64 ? launch_pass_m<float, double, 16>(mode, prefetch, grid, a, s)
+                : launch_pass_m<float, float, 16>(mode, prefetch, grid, a, s);
 }
 
 hipError_t launch_reduce(int mode, const SmallArgs &a, hipStream_t s) {

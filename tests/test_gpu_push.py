@@ -44,13 +44,17 @@ def _compare_f64(g, st, c=100.0):
     return kap
 
 
-@pytest.mark.parametrize("n", [777, 2048, 20000])
+@pytest.mark.parametrize("n", [777, 2048, 20000, 100037])
 def test_f64_tight_well_conditioned(n):
-    """kappa_2(X) ~ 3: GPU and oracle agree to a few ulps scaled by q."""
+    """kappa_2(X) <= ~3: GPU and oracle agree to a few ulps scaled by q.
+    Krylov sequence of a known map for small n, Gaussian snapshots for large n."""
     from pins import _known_A, _krylov
 
-    A, psi1 = _known_A(n=n, seed=31)
-    X = _krylov(A, psi1, 30)
+    if n <= 2048:
+        A, psi1 = _known_A(n=n, seed=31)
+        X = _krylov(A, psi1, 30)
+    else:
+        X = np.random.default_rng(n).standard_normal((n, 30))
     st = oracle.foa_batch(X, tol=0.0)
     g = run_gpu(X, "f64", tol=0.0)
     q, m = g["q"], g["m"]
