@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--N", type=int, default=None, help="override the snapshot count")
     ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-rows", type=int, default=1 << 18)
+    ap.add_argument("--cpu-rows", type=int, default=1 << 20)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--prefetch", type=int, default=-1)
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",

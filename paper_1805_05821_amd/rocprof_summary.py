@@ -6,6 +6,13 @@
   python -m paper_1805_05821_amd.rocprof_summary counter DIR COUNTER
       average value of COUNTER per dispatch for the row-pass kernels and for
       the copy kernel of a calibration run (from *counter_collection.csv).
+  python -m paper_1805_05821_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR \
+         FETCH_COPY_DIR WRITE_COPY_DIR COPY_BYTES BENCH_LOG OUT_JSON
+      HBM bytes per row-pass launch: FETCH_SIZE and WRITE_SIZE (KiB per
+      dispatch), each scaled by bytes-moved / counter-value of the plain copy
+      of COPY_BYTES bytes, next to the algorithmic bytes per launch that the
+      benchmark printed in BENCH_LOG (its JSON line); written to OUT_JSON with
+      the SHA-256 of the kernel source it describes.
 """
 
 import csv
@@ -52,13 +59,15 @@ def summarize_kernels(d):
     for r in rows[:25]:
         lines.append(f"{r['calls']:7d} {r['total_ns'] / 1e6:10.2f} {r['avg_ns'] / 1e3:10.2f} "
                      f"{100 * r['total_ns'] / tot:5.1f}%  {r['name'][:110]}")
-    rp = [r for r in rows if is_row_pass(r["name"])]
-    calls = sum(r["calls"] for r in rp)
-    ns = sum(r["total_ns"] for r in rp)
-    if calls:
-        lines.append("")
-        lines.append(f"row passes (all k_pass instances): {calls} launches, {ns / 1e6:.2f} ms total, "
-                     f"average {ns / calls / 1e6:.4f} ms per launch, {100 * ns / tot:.1f}% of kernel time")
+    lines.append("")
+    for label, key in (("all k_pass instances", "k_pass"), ("FP32 basis, k_pass<float, ...>", "k_pass<float"),
+                       ("FP64 basis, k_pass<double, ...>", "k_pass<double")):
+        rp = [r for r in rows if key in r["name"]]
+        calls = sum(r["calls"] for r in rp)
+        ns = sum(r["total_ns"] for r in rp)
+        if calls:
+            lines.append(f"row passes ({label}): {calls} launches, {ns / 1e6:.2f} ms total, "
+                         f"average {ns / calls / 1e6:.4f} ms per launch, {100 * ns / tot:.1f}% of kernel time")
     return "\n".join(lines)
 
 
@@ -92,11 +101,67 @@ def summarize_counter(d, counter):
     return "\n".join(lines)
 
 
+def _copy_value(d, counter):
+    per = counter_per_dispatch(d, counter)
+    for name, (v, n) in per.items():
+        if "copyBuffer" in name or "copy" in name.lower():
+            return v / max(n, 1)
+    raise RuntimeError(f"no copy kernel under {d}")
+
+
+def _row_pass_avg(d, counter):
+    per = counter_per_dispatch(d, counter)
+    v = sum(x for name, (x, n) in per.items() if is_row_pass(name))
+    n = sum(n for name, (x, n) in per.items() if is_row_pass(name))
+    return v / max(n, 1), n
+
+
+def traffic(fetch_dir, write_dir, fetch_copy, write_copy, copy_bytes, bench_log, out_json):
+    import hashlib
+    import json
+
+    copy_bytes = float(copy_bytes)
+    f_scale = copy_bytes / _copy_value(fetch_copy, "FETCH_SIZE")
+    w_scale = copy_bytes / _copy_value(write_copy, "WRITE_SIZE")
+    f_avg, nf = _row_pass_avg(fetch_dir, "FETCH_SIZE")
+    w_avg, nw = _row_pass_avg(write_dir, "WRITE_SIZE")
+    bench = None
+    for line in open(bench_log):
+        line = line.strip()
+        if line.startswith("{") and '"roofline"' in line:
+            bench = json.loads(line)
+    alg = bench["roofline"]["alg_bytes_per_launch"] if bench else None
+    fetch_b = f_avg * f_scale
+    write_b = w_avg * w_scale
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = os.path.join(root, "paper_1805_05821_amd", "csrc", "foa_kernels.hip")
+    rec = {
+        "kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+        "f32": {
+            "traffic_bytes_per_launch": fetch_b + write_b,
+            "fetch_bytes_per_launch": fetch_b,
+            "write_bytes_per_launch": write_b,
+            "alg_bytes_per_launch": alg,
+            "traffic_over_alg": (fetch_b + write_b) / alg if alg else None,
+            "dispatches": [nf, nw],
+            "fetch_scale": f_scale,
+            "write_scale": w_scale,
+        },
+    }
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "kernels":
         print(summarize_kernels(argv[1]))
     elif len(argv) >= 3 and argv[0] == "counter":
         print(summarize_counter(argv[1], argv[2]))
+    elif len(argv) >= 8 and argv[0] == "traffic":
+        import json
+
+        print(json.dumps(traffic(*argv[1:8]), indent=1))
     else:
         print(__doc__)
         return 2
