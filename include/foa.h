@@ -119,6 +119,12 @@ foa_status foa_get_state(foa_ctx ctx, double *h_Hbar, double *h_beta, int32_t ld
  * ld >= n) in dtype.  Stream-ordered. */
 foa_status foa_copy_basis(foa_ctx ctx, void *d_V, int64_t ld, foa_dtype dtype, int32_t ncols);
 
+/* Rows [r0, r0 + nrows) of v_1..v_ncols into d_V (nrows x ncols, column-major,
+ * leading dimension ld >= nrows), for streaming a basis larger than the
+ * caller's scratch.  FOA_E_ARG when the row range leaves [0, n).  Stream-ordered. */
+foa_status foa_copy_basis_rows(foa_ctx ctx, int64_t r0, int64_t nrows, void *d_V, int64_t ld,
+                               foa_dtype dtype, int32_t ncols);
+
 /* Rank truncation (Algorithm 1 steps 21-23, Algorithm 3 lines 8-9): SVD of
  * beta_m (m as in foa_get_state) on the host in FP64; r = number of singular
  * values above rel_tol * sigma_1, or, for rel_tol < 0, above

@@ -441,9 +441,20 @@ foa_status foa_copy_basis(foa_ctx c, void *d_V, int64_t ld, foa_dtype dtype, int
   if (!c) return FOA_E_ARG;
   if (!d_V || !valid_dtype(dtype) || ld < c->n || ncols < 0 || ncols > c->q_host)
     return set_err(c, FOA_E_ARG, "bad basis copy arguments (ncols %d, q %d)", ncols, c->q_host);
-  hipError_t e = launch_copy_basis(c->prec == FOA_PREC_F64, c->W, c->sa.sigma, c->n, c->n_max, ncols, d_V, ld,
-                                   dtype == FOA_F64, c->stream);
+  hipError_t e = launch_copy_basis(c->prec == FOA_PREC_F64, c->W, c->sa.sigma, 0, c->n, c->n_max, ncols, d_V,
+                                   ld, dtype == FOA_F64, c->stream);
   return hip_err(c, e, "copy basis");
+}
+
+foa_status foa_copy_basis_rows(foa_ctx c, int64_t r0, int64_t nrows, void *d_V, int64_t ld, foa_dtype dtype,
+                               int32_t ncols) {
+  if (!c) return FOA_E_ARG;
+  if (!d_V || !valid_dtype(dtype) || r0 < 0 || nrows < 0 || r0 + nrows > c->n || ld < nrows || ncols < 0 ||
+      ncols > c->q_host)
+    return set_err(c, FOA_E_ARG, "bad basis row-copy arguments");
+  hipError_t e = launch_copy_basis(c->prec == FOA_PREC_F64, c->W, c->sa.sigma, r0, nrows, c->n_max, ncols, d_V,
+                                   ld, dtype == FOA_F64, c->stream);
+  return hip_err(c, e, "copy basis rows");
 }
 
 foa_status foa_profile(foa_ctx c, double out[3]) {

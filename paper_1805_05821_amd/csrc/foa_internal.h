@@ -86,9 +86,9 @@ hipError_t launch_reduce(int mode, const SmallArgs &a, hipStream_t s);
 hipError_t launch_finalize(const SmallArgs &a, hipStream_t s);
 hipError_t launch_finalize_init(const SmallArgs &a, hipStream_t s);
 hipError_t launch_nextb(const SmallArgs &a, hipStream_t s);
-hipError_t launch_copy_basis(bool tv_f64, const void *W, const double *sigma, int64_t n,
-                             int n_max, int ncols, void *out, int64_t ld, bool out_f64,
-                             hipStream_t s);
+hipError_t launch_copy_basis(bool tv_f64, const void *W, const double *sigma, int64_t r0,
+                             int64_t nrows, int n_max, int ncols, void *out, int64_t ld,
+                             bool out_f64, hipStream_t s);
 hipError_t launch_init_state(const SmallArgs &a, double tol, hipStream_t s);
 // Phi = W * B for the panel-layout basis W (n x k used columns) and the
 // k x r FP64 coefficient matrix B (column-major, leading dimension k, sigma

@@ -521,14 +521,16 @@ __global__ __launch_bounds__(256) void k_init_state(SmallArgs a, double tol) {
 }
 
 template <typename TV, typename TO>
-__global__ __launch_bounds__(256) void k_copy_basis(const TV *W, const double *sigma, int64_t n,
-                                                    int n_max, int ncols, TO *out, int64_t ld) {
+__global__ __launch_bounds__(256) void k_copy_basis(const TV *W, const double *sigma, int64_t r0,
+                                                    int64_t nrows, int n_max, int ncols, TO *out,
+                                                    int64_t ld) {
   const int c = blockIdx.y;
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (r >= n || c >= ncols) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nrows || c >= ncols) return;
+  const int64_t r = r0 + i;
   const int64_t p = r / PANEL;
   const double v = (double)W[((size_t)p * n_max + c) * PANEL + (r % PANEL)];
-  out[(size_t)c * ld + r] = (TO)(sigma[c] * v);
+  out[(size_t)c * ld + i] = (TO)(sigma[c] * v);
 }
 
 // ---------------------------------------------------------------------------
@@ -631,24 +633,24 @@ hipError_t launch_init_state(const SmallArgs &a, double tol, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_copy_basis(bool tv_f64, const void *W, const double *sigma, int64_t n, int n_max,
-                             int ncols, void *out, int64_t ld, bool out_f64, hipStream_t s) {
-  if (ncols <= 0) return hipSuccess;
-  dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
+hipError_t launch_copy_basis(bool tv_f64, const void *W, const double *sigma, int64_t r0, int64_t nrows,
+                             int n_max, int ncols, void *out, int64_t ld, bool out_f64, hipStream_t s) {
+  if (ncols <= 0 || nrows <= 0) return hipSuccess;
+  dim3 grid((unsigned)((nrows + 255) / 256), (unsigned)ncols);
   if (tv_f64) {
     if (out_f64)
-      hipLaunchKernelGGL((k_copy_basis<double, double>), grid, dim3(256), 0, s,
-                         (const double *)W, sigma, n, n_max, ncols, (double *)out, ld);
+      hipLaunchKernelGGL((k_copy_basis<double, double>), grid, dim3(256), 0, s, (const double *)W, sigma, r0,
+                         nrows, n_max, ncols, (double *)out, ld);
     else
-      hipLaunchKernelGGL((k_copy_basis<double, float>), grid, dim3(256), 0, s,
-                         (const double *)W, sigma, n, n_max, ncols, (float *)out, ld);
+      hipLaunchKernelGGL((k_copy_basis<double, float>), grid, dim3(256), 0, s, (const double *)W, sigma, r0,
+                         nrows, n_max, ncols, (float *)out, ld);
   } else {
     if (out_f64)
-      hipLaunchKernelGGL((k_copy_basis<float, double>), grid, dim3(256), 0, s,
-                         (const float *)W, sigma, n, n_max, ncols, (double *)out, ld);
+      hipLaunchKernelGGL((k_copy_basis<float, double>), grid, dim3(256), 0, s, (const float *)W, sigma, r0,
+                         nrows, n_max, ncols, (double *)out, ld);
     else
-      hipLaunchKernelGGL((k_copy_basis<float, float>), grid, dim3(256), 0, s,
-                         (const float *)W, sigma, n, n_max, ncols, (float *)out, ld);
+      hipLaunchKernelGGL((k_copy_basis<float, float>), grid, dim3(256), 0, s, (const float *)W, sigma, r0,
+                         nrows, n_max, ncols, (float *)out, ld);
   }
   return hipGetLastError();
 }

@@ -33,7 +33,7 @@ FOA_MAX_CAPACITY = 512
 
 EXPORTED = [
     "foa_workspace_bytes", "foa_init", "foa_push_snapshot", "foa_push_block", "foa_sync",
-    "foa_get_state", "foa_copy_basis", "foa_truncate", "foa_modes", "foa_indicators",
+    "foa_get_state", "foa_copy_basis", "foa_copy_basis_rows", "foa_truncate", "foa_modes", "foa_indicators",
     "foa_reset", "foa_destroy", "foa_status_str", "foa_last_error", "foa_set_option", "foa_profile",
     "foa_batch_workspace_bytes", "foa_batch_init", "foa_batch_push", "foa_batch_sync",
     "foa_batch_view", "foa_batch_destroy",
@@ -70,6 +70,7 @@ def _load():
         "foa_sync": [P, c.POINTER(i32)],
         "foa_get_state": [P, P, P, i32, c.POINTER(i32), c.POINTER(i32)],
         "foa_copy_basis": [P, P, i64, c.c_int, i32],
+        "foa_copy_basis_rows": [P, i64, i64, P, i64, c.c_int, i32],
         "foa_truncate": [P, f64, i32, c.POINTER(i32), P],
         "foa_modes": [P, i32, P, P, P, P, P, i64, i32, c.c_int, c.POINTER(i32)],
         "foa_indicators": [P, i32, P, P, c.POINTER(i32)],
@@ -187,6 +188,10 @@ def foa_get_state(ctx, ld=None):
 
 def foa_copy_basis(ctx, out, ld, dtype, ncols):
     return _check(lib.foa_copy_basis(ctx, _addr(out), int(ld), int(dtype), int(ncols)), ctx)
+
+
+def foa_copy_basis_rows(ctx, r0, nrows, out, ld, dtype, ncols):
+    return _check(lib.foa_copy_basis_rows(ctx, int(r0), int(nrows), _addr(out), int(ld), int(dtype), int(ncols)), ctx)
 
 
 def foa_truncate(ctx, rel_tol=-1.0, r_force=0, m_hint=None):

@@ -52,6 +52,16 @@ class FOAStream:
         F.foa_copy_basis(self.ctx, out, self.n, F.FOA_F64 if dtype == torch.float64 else F.FOA_F32, ncols)
         return out[:ncols]
 
+    def basis_rows(self, r0, nrows, ncols, dtype=None):
+        """Rows [r0, r0+nrows) of v_1..v_ncols as an (ncols, nrows) tensor."""
+        import torch
+
+        dtype = dtype or torch.float64
+        out = torch.empty((max(ncols, 1), max(nrows, 1)), dtype=dtype, device=self.ws.device)
+        F.foa_copy_basis_rows(self.ctx, r0, nrows, out, max(nrows, 1),
+                              F.FOA_F64 if dtype == torch.float64 else F.FOA_F32, ncols)
+        return out[:ncols, :nrows]
+
     def truncate(self, rel_tol=-1.0, r_force=0):
         return F.foa_truncate(self.ctx, rel_tol, r_force)
 
