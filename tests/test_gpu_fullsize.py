@@ -157,8 +157,13 @@ def test_large_1e8_with_modes():
                                 10 * np.sqrt(q) * EPS32)
     del X
     torch.cuda.empty_cache()
-    r, sig = s.truncate()
-    announce(f"truncation rank {r}")
+    r_rule, sig = s.truncate()
+    # the workload's signal has rank 160 (80 pairs, amplitudes down to 1e-5), below
+    # the FP32 numerical-rank threshold N eps32(sigma_1) for its weakest modes, so
+    # the reconstruction uses the signal rank
+    r, _ = s.truncate(r_force=w.modes_r)
+    announce(f"numerical-rank rule r = {r_rule}; reconstruction with r = {r}")
+    assert r == w.modes_r
     phi = torch.empty((w.modes_r, w.n), dtype=torch.float32, device="cuda")
     # at most modes_r packed columns: modes_r / 2 entries (pairs take two columns)
     lam_c, kind, amp, err = F.foa_modes(s.ctx, w.modes_r // 2, phi, w.n, w.modes_r, F.FOA_F32)
