@@ -31,7 +31,7 @@ bool valid_dtype(int d) { return d == FOA_F32 || d == FOA_F64; }
 
 namespace foa {
 
-Layout make_layout(int64_t n, int n_max, foa_prec prec) {
+Layout make_layout(int64_t n, int n_max, foa_prec prec, int ldg) {
   Layout L{};
   const int64_t P = (n + PANEL - 1) / PANEL;
   const size_t sV = prec == FOA_PREC_F64 ? 8 : 4;
@@ -43,7 +43,7 @@ Layout make_layout(int64_t n, int n_max, foa_prec prec) {
   };
   L.P = P;
   L.n_pad = P * PANEL;
-  L.ldg = kMaxGrid;
+  L.ldg = ldg;
   L.ldH = n_max + 1;
   L.ldB = n_max + 1;
   L.W = take((size_t)P * PANEL * (size_t)n_max * sV);

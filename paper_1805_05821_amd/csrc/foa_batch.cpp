@@ -1,0 +1,500 @@
+// Batched form of the C ABI: many independent FOA streams of uneven n and
+// capacity in one caller-owned workspace, all advanced by one snapshot per
+// foa_batch_push as a single graph launch.  Each stream is exactly the single
+// stream of foa_api.cpp (same layout, same kernels' arithmetic); per-stream
+// context views give access to its state, basis, truncation and modes.
+//
+// Work decomposition of the row passes: (stream, panel range) units, ordered
+// by decreasing estimated cost and dealt round-robin to a persistent grid;
+// one pass kernel per column-tile bucket takes the units of the streams whose
+// basis size falls in its bucket.  The unit size and the grid are chosen by
+// timing candidates (autotuner) and cached in a JSON table.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "foa.h"
+#include "foa_ctx.h"
+#include "foa_internal.h"
+
+using namespace foa;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMinUnitPanels = 4;                 // smallest unit: sizes the partial slots
+constexpr int kUnitCandidates[] = {4, 16, 64};
+constexpr int kTuneSteps = 48, kTuneTimed = 16;   // tuning run: last kTuneTimed of kTuneSteps steps
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct BatchLayout {
+  std::vector<size_t> off;       // per-stream Layout base
+  std::vector<Layout> L;
+  size_t states = 0, streams = 0, units = 0, xptrs = 0, rblk_s = 0, rblk_c = 0, tune_x = 0, total = 0;
+  size_t units_cap = 0, rblocks = 0;
+  int64_t max_n = 0;
+  int max_nmax = 0;
+};
+
+BatchLayout batch_layout(int S, const int64_t *n, const int32_t *n_max, foa_prec prec) {
+  BatchLayout B;
+  size_t o = 0;
+  for (int s = 0; s < S; ++s) {
+    const int64_t P = (n[s] + PANEL - 1) / PANEL;
+    const int slots = (int)((P + kMinUnitPanels - 1) / kMinUnitPanels);
+    Layout L = make_layout(n[s], n_max[s], prec, slots);
+    B.off.push_back(o);
+    B.L.push_back(L);
+    o = align_up(o + L.total);
+    B.units_cap += (size_t)slots;
+    B.rblocks += (size_t)(n_max[s] + 1 + 3) / 4;
+    B.max_n = std::max<int64_t>(B.max_n, n[s]);
+    B.max_nmax = std::max<int>(B.max_nmax, n_max[s]);
+  }
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  B.states = take((size_t)S * sizeof(DevState));
+  B.streams = take((size_t)S * sizeof(BatchStream));
+  B.units = take(B.units_cap * sizeof(BatchUnit));
+  B.xptrs = take((size_t)S * sizeof(void *));
+  B.rblk_s = take(B.rblocks * sizeof(int));
+  B.rblk_c = take(B.rblocks * sizeof(int));
+  B.tune_x = take((size_t)B.max_n * sizeof(float));
+  B.total = o;
+  return B;
+}
+
+}  // namespace
+
+struct foa_batch_s {
+  int S = 0;
+  foa_prec prec = FOA_PREC_F32;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // private stream used only for graph capture
+  int device = 0, cus = 0;
+  double tol = 0.0;
+  BatchLayout B;
+  std::vector<int64_t> n;
+  std::vector<int> nmax;
+  std::vector<foa_ctx_s *> views;
+  BatchArgs args{};
+  int unit_panels = 16, grid = 0;
+  double tuned_ms = 0.0;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  std::string tune_path, tune_key;
+  std::vector<DevState> hstates;
+};
+
+namespace {
+
+// Units of a given size, ordered by decreasing estimated cost (panels x n_max).
+int build_units(foa_batch_s *b, int unit_panels, std::vector<BatchUnit> &units, std::vector<int> &nslot) {
+  units.clear();
+  nslot.assign(b->S, 0);
+  for (int s = 0; s < b->S; ++s) {
+    const int64_t P = b->B.L[s].P;
+    int slot = 0;
+    for (int64_t p0 = 0; p0 < P; p0 += unit_panels, ++slot)
+      units.push_back(BatchUnit{s, slot, p0, std::min<int64_t>(P, p0 + unit_panels)});
+    nslot[s] = slot;
+  }
+  std::stable_sort(units.begin(), units.end(), [&](const BatchUnit &a, const BatchUnit &c) {
+    const double ca = (double)(a.p1 - a.p0) * b->nmax[a.s], cc = (double)(c.p1 - c.p0) * b->nmax[c.s];
+    return ca > cc;
+  });
+  return (int)units.size();
+}
+
+foa_status upload_config(foa_batch_s *b, int unit_panels) {
+  std::vector<BatchUnit> units;
+  std::vector<int> nslot;
+  const int nu = build_units(b, unit_panels, units, nslot);
+  std::vector<BatchStream> ds(b->S);
+  for (int s = 0; s < b->S; ++s) {
+    foa_ctx_s *v = b->views[s];
+    BatchStream &d = ds[s];
+    d.W = v->W;
+    d.w = v->w;
+    d.part = v->part;
+    d.partn = v->partn;
+    d.st = v->sa.st;
+    d.H = v->sa.H;
+    d.beta = v->sa.beta;
+    d.sigma = v->sa.sigma;
+    d.bvec = v->sa.bvec;
+    d.h = v->sa.h;
+    d.s = v->sa.s;
+    d.coefA = v->sa.coefA;
+    d.coefB = v->sa.coefB;
+    d.coefC = v->sa.coefC;
+    d.n = v->n;
+    d.P = v->L.P;
+    d.n_max = v->n_max;
+    d.ldg = v->L.ldg;
+    d.ldH = v->L.ldH;
+    d.ldB = v->L.ldB;
+    d.nslot = nslot[s];
+    d.pad = 0;
+  }
+  hipError_t e = hipMemcpy(b->ws + b->B.streams, ds.data(), ds.size() * sizeof(BatchStream), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->ws + b->B.units, units.data(), units.size() * sizeof(BatchUnit), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return FOA_E_DEVICE;
+  b->args.n_units = nu;
+  b->unit_panels = unit_panels;
+  return FOA_OK;
+}
+
+// All kernels of one step, enqueued on stream s (direct launches or capture).
+hipError_t enqueue_step(foa_batch_s *b, bool x_f64, hipStream_t s) {
+  const bool v64 = b->prec == FOA_PREC_F64;
+  const int cols = batch_cols_per_qw(v64);
+  const int qmax = pick_qw(std::max(b->B.max_nmax - 1, 1), cols);
+  const BatchArgs &a = b->args;
+  hipError_t e;
+  if ((e = launch_batch_begin(a, s)) != hipSuccess) return e;
+  if ((e = launch_batch_pass(PM_INIT, v64, x_f64, 1, b->grid, a, s)) != hipSuccess) return e;
+  for (int qw = 1; qw <= qmax; qw *= 2)
+    if ((e = launch_batch_pass(PM_A, v64, x_f64, qw, b->grid, a, s)) != hipSuccess) return e;
+  if ((e = launch_batch_reduce(1, a, s)) != hipSuccess) return e;
+  for (int qw = 1; qw <= qmax; qw *= 2)
+    if ((e = launch_batch_pass(PM_B, v64, true, qw, b->grid, a, s)) != hipSuccess) return e;
+  if ((e = launch_batch_reduce(2, a, s)) != hipSuccess) return e;
+  for (int qw = 1; qw <= qmax; qw *= 2)
+    if ((e = launch_batch_pass(PM_C, v64, true, qw, b->grid, a, s)) != hipSuccess) return e;
+  if ((e = launch_batch_finalize(a, s)) != hipSuccess) return e;
+  return launch_batch_nextb(a, s);
+}
+
+void drop_graphs(foa_batch_s *b) {
+  for (int k = 0; k < 2; ++k) {
+    if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+    if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+    b->exec[k] = nullptr;
+    b->graph[k] = nullptr;
+  }
+}
+
+foa_status ensure_graph(foa_batch_s *b, bool x_f64) {
+  const int k = x_f64 ? 1 : 0;
+  if (b->exec[k]) return FOA_OK;
+  if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return FOA_E_DEVICE;
+  hipError_t e = enqueue_step(b, x_f64, b->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return FOA_E_DEVICE;
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return FOA_E_DEVICE;
+  }
+  b->graph[k] = g;
+  b->exec[k] = x;
+  return FOA_OK;
+}
+
+foa_status reset_states(foa_batch_s *b) {
+  if (launch_batch_init_states(b->args, b->tol, b->stream) != hipSuccess) return FOA_E_DEVICE;
+  for (foa_ctx_s *v : b->views) {
+    v->q_host = 0;
+    v->dev_status = ST_ACTIVE;
+    v->mirror_valid = false;
+    v->dmd.valid = false;
+    v->trunc_r = 0;
+    v->trunc_m = 0;
+    v->Ur.clear();
+  }
+  return FOA_OK;
+}
+
+// ---- autotuner table: {"entries": [{"key": K, "unit_panels": U, "grid": G, "ms_per_step": T}, ...]}
+struct TuneEntry {
+  std::string key;
+  int unit = 0, grid = 0;
+  double ms = 0;
+};
+
+std::vector<TuneEntry> read_table(const std::string &path) {
+  std::vector<TuneEntry> out;
+  std::ifstream f(path);
+  if (!f) return out;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  size_t pos = 0;
+  while ((pos = t.find("\"key\"", pos)) != std::string::npos) {
+    TuneEntry e;
+    const size_t q1 = t.find('"', t.find(':', pos) + 1);
+    const size_t q2 = t.find('"', q1 + 1);
+    if (q1 == std::string::npos || q2 == std::string::npos) break;
+    e.key = t.substr(q1 + 1, q2 - q1 - 1);
+    const size_t end = t.find('}', q2);
+    auto num = [&](const char *name) -> double {
+      const size_t k = t.find(name, q2);
+      if (k == std::string::npos || k > end) return 0.0;
+      return std::atof(t.c_str() + t.find(':', k) + 1);
+    };
+    e.unit = (int)num("\"unit_panels\"");
+    e.grid = (int)num("\"grid\"");
+    e.ms = num("\"ms_per_step\"");
+    if (e.unit > 0 && e.grid > 0) out.push_back(e);
+    pos = q2;
+  }
+  return out;
+}
+
+void write_table(const std::string &path, const std::vector<TuneEntry> &ents) {
+  std::ofstream f(path);
+  f << "{\"entries\": [\n";
+  for (size_t i = 0; i < ents.size(); ++i)
+    f << "  {\"key\": \"" << ents[i].key << "\", \"unit_panels\": " << ents[i].unit << ", \"grid\": " << ents[i].grid
+      << ", \"ms_per_step\": " << ents[i].ms << "}" << (i + 1 < ents.size() ? "," : "") << "\n";
+  f << "]}\n";
+}
+
+// Time kTuneTimed steps (after warm-up steps) of synthetic pushes for one
+// configuration; inputs are a hash sequence regenerated every step.
+foa_status time_config(foa_batch_s *b, int unit, int grid, double *ms_out) {
+  b->grid = grid;
+  foa_status r = upload_config(b, unit);
+  if (r != FOA_OK) return r;
+  if ((r = reset_states(b)) != FOA_OK) return r;
+  float *tx = reinterpret_cast<float *>(b->ws + b->B.tune_x);
+  std::vector<const void *> ptrs(b->S);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FOA_E_DEVICE;
+  hipError_t e = hipSuccess;
+  for (int step = 0; step < kTuneSteps && e == hipSuccess; ++step) {
+    for (int s = 0; s < b->S; ++s) ptrs[s] = step < b->nmax[s] ? (const void *)tx : nullptr;
+    e = hipMemcpyAsync(b->ws + b->B.xptrs, ptrs.data(), ptrs.size() * sizeof(void *), hipMemcpyHostToDevice,
+                       b->stream);
+    if (e == hipSuccess) e = launch_fill_random(tx, b->B.max_n, (uint32_t)step, b->stream);
+    if (e == hipSuccess && step == kTuneSteps - kTuneTimed) e = hipEventRecord(e0, b->stream);
+    if (e == hipSuccess) e = enqueue_step(b, false, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // the host pointer array is reused
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return FOA_E_DEVICE;
+  *ms_out = ms / kTuneTimed;
+  return FOA_OK;
+}
+
+foa_status tune(foa_batch_s *b) {
+  std::vector<TuneEntry> table;
+  if (!b->tune_path.empty()) {
+    table = read_table(b->tune_path);
+    for (const TuneEntry &t : table)
+      if (t.key == b->tune_key) {
+        b->grid = t.grid;
+        b->tuned_ms = t.ms;
+        return upload_config(b, t.unit);
+      }
+  }
+  double best = 1e300;
+  int bu = 16, bg = 2 * b->cus;
+  for (int unit : kUnitCandidates) {
+    for (int gm : {1, 2, 4}) {
+      double ms = 0;
+      foa_status r = time_config(b, unit, gm * b->cus, &ms);
+      if (r != FOA_OK) return r;
+      if (ms < best) {
+        best = ms;
+        bu = unit;
+        bg = gm * b->cus;
+      }
+    }
+  }
+  b->grid = bg;
+  b->tuned_ms = best;
+  foa_status r = upload_config(b, bu);
+  if (r != FOA_OK) return r;
+  if (!b->tune_path.empty()) {
+    table.push_back(TuneEntry{b->tune_key, bu, bg, best});
+    write_table(b->tune_path, table);
+  }
+  return FOA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+foa_status foa_batch_workspace_bytes(int32_t S, const int64_t *n, const int32_t *n_max, foa_prec prec, size_t *bytes) {
+  if (S < 1 || !n || !n_max || !bytes || (prec != FOA_PREC_F32 && prec != FOA_PREC_F64)) return FOA_E_ARG;
+  for (int s = 0; s < S; ++s)
+    if (n[s] < 1 || n_max[s] < 1 || n_max[s] > FOA_MAX_CAPACITY) return FOA_E_ARG;
+  *bytes = batch_layout(S, n, n_max, prec).total;
+  return FOA_OK;
+}
+
+foa_status foa_batch_init(foa_batch *out, int32_t S, const int64_t *n, const int32_t *n_max, foa_prec prec,
+                          void *d_workspace, size_t ws_bytes, void *hip_stream, double breakdown_tol,
+                          const char *tune_table_json) {
+  if (!out) return FOA_E_ARG;
+  *out = nullptr;
+  size_t need = 0;
+  if (foa_batch_workspace_bytes(S, n, n_max, prec, &need) != FOA_OK) return FOA_E_ARG;
+  if (!d_workspace || reinterpret_cast<uintptr_t>(d_workspace) % kAlign || std::isnan(breakdown_tol))
+    return FOA_E_ARG;
+  if (ws_bytes < need) return FOA_E_NOMEM;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return FOA_E_DEVICE;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return FOA_E_DEVICE;
+  foa_batch_s *b = new (std::nothrow) foa_batch_s();
+  if (!b) return FOA_E_NOMEM;
+  b->S = S;
+  b->prec = prec;
+  b->ws = static_cast<char *>(d_workspace);
+  b->ws_bytes = ws_bytes;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->device = dev;
+  b->cus = cus;
+  b->grid = 2 * cus;
+  b->B = batch_layout(S, n, n_max, prec);
+  b->n.assign(n, n + S);
+  b->nmax.assign(n_max, n_max + S);
+  int max_nmax = 0;
+  for (int s = 0; s < S; ++s) max_nmax = std::max<int>(max_nmax, n_max[s]);
+  b->tol = breakdown_tol < 0 ? (double)max_nmax * std::ldexp(1.0, -52) : breakdown_tol;
+  DevState *states = reinterpret_cast<DevState *>(b->ws + b->B.states);
+  for (int s = 0; s < S; ++s) {
+    foa_ctx_s *v = new (std::nothrow) foa_ctx_s();
+    if (!v) {
+      foa_batch_destroy(b);
+      return FOA_E_NOMEM;
+    }
+    v->n = n[s];
+    v->n_max = n_max[s];
+    v->prec = prec;
+    v->ws = b->ws + b->B.off[s];
+    v->ws_bytes = b->B.L[s].total;
+    v->stream = b->stream;
+    v->L = b->B.L[s];
+    v->device = dev;
+    v->cus = cus;
+    v->tol = b->tol;
+    v->is_view = true;
+    bind_pointers(v);
+    v->sa.st = states + s;  // all scalar states are contiguous for one-copy syncs
+    b->views.push_back(v);
+  }
+  b->args.streams = reinterpret_cast<const BatchStream *>(b->ws + b->B.streams);
+  b->args.units = reinterpret_cast<const BatchUnit *>(b->ws + b->B.units);
+  b->args.xptrs = reinterpret_cast<const void *const *>(b->ws + b->B.xptrs);
+  b->args.rblk_stream = reinterpret_cast<const int *>(b->ws + b->B.rblk_s);
+  b->args.rblk_c0 = reinterpret_cast<const int *>(b->ws + b->B.rblk_c);
+  b->args.S = S;
+  b->args.max_nmax = b->B.max_nmax;
+  std::vector<int> rs, rc;
+  for (int s = 0; s < S; ++s)
+    for (int c0 = 0; c0 < n_max[s] + 1; c0 += 4) {
+      rs.push_back(s);
+      rc.push_back(c0);
+    }
+  b->args.n_rblocks = (int)rs.size();
+  if (hipMemcpy(b->ws + b->B.rblk_s, rs.data(), rs.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->ws + b->B.rblk_c, rc.data(), rc.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    foa_batch_destroy(b);
+    return FOA_E_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  std::string arch = "gfx";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  int64_t sum_n = 0;
+  for (int s = 0; s < S; ++s) sum_n += n[s];
+  char key[256];
+  std::snprintf(key, sizeof key, "%s/%s/S%d/n%lld/m%d/cu%d", arch.c_str(), prec == FOA_PREC_F64 ? "f64" : "f32", S,
+                (long long)sum_n, max_nmax, cus);
+  b->tune_key = key;
+  if (tune_table_json) b->tune_path = tune_table_json;
+  foa_status r = tune(b);
+  if (r == FOA_OK) r = reset_states(b);
+  if (r == FOA_OK && hipStreamSynchronize(b->stream) != hipSuccess) r = FOA_E_DEVICE;
+  if (r != FOA_OK) {
+    foa_batch_destroy(b);
+    return r;
+  }
+  *out = b;
+  return FOA_OK;
+}
+
+foa_status foa_batch_push(foa_batch b, const void *const *d_x_ptrs, foa_dtype x_dtype) {
+  if (!b) return FOA_E_ARG;
+  if (!d_x_ptrs || (x_dtype != FOA_F32 && x_dtype != FOA_F64)) return FOA_E_ARG;
+  foa_status r = ensure_graph(b, x_dtype == FOA_F64);
+  if (r != FOA_OK) return r;
+  if (hipMemcpyAsync(b->ws + b->B.xptrs, d_x_ptrs, (size_t)b->S * sizeof(void *), hipMemcpyDeviceToDevice,
+                     b->stream) != hipSuccess)
+    return FOA_E_DEVICE;
+  if (hipGraphLaunch(b->exec[x_dtype == FOA_F64 ? 1 : 0], b->stream) != hipSuccess) return FOA_E_DEVICE;
+  for (foa_ctx_s *v : b->views) {
+    v->mirror_valid = false;
+    v->dmd.valid = false;
+  }
+  return FOA_OK;
+}
+
+foa_status foa_batch_sync(foa_batch b, int32_t *h_q, int32_t *h_status) {
+  if (!b) return FOA_E_ARG;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return FOA_E_DEVICE;
+  b->hstates.resize(b->S);
+  if (hipMemcpy(b->hstates.data(), b->ws + b->B.states, (size_t)b->S * sizeof(DevState), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return FOA_E_DEVICE;
+  for (int s = 0; s < b->S; ++s) {
+    const DevState &d = b->hstates[s];
+    foa_ctx_s *v = b->views[s];
+    v->q_host = d.q;
+    v->dev_status = d.status;
+    v->pushes = d.pushes;
+    if (h_q) h_q[s] = d.q;
+    if (h_status) h_status[s] = (d.status == ST_ACTIVE && d.full) ? FOA_E_CAPACITY : map_status(d.status);
+  }
+  return FOA_OK;
+}
+
+foa_status foa_batch_view(foa_batch b, int32_t s, foa_ctx *view) {
+  if (!b || !view || s < 0 || s >= b->S) return FOA_E_ARG;
+  *view = b->views[s];
+  return FOA_OK;
+}
+
+foa_status foa_batch_destroy(foa_batch b) {
+  if (!b) return FOA_E_ARG;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_graphs(b);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (foa_ctx_s *v : b->views) {
+    release_events(v);
+    delete v;
+  }
+  delete b;
+  return FOA_OK;
+}
+
+}  // extern "C"

@@ -36,7 +36,8 @@ struct DmdCache {
   std::vector<int> entries;                // eigen indices, one per real / pair, in mode order
 };
 
-Layout make_layout(int64_t n, int n_max, foa_prec prec);
+// ldg: leading dimension (slots) of the partial-sum arrays.
+Layout make_layout(int64_t n, int n_max, foa_prec prec, int ldg = 1024);
 
 }  // namespace foa
 

@@ -24,13 +24,15 @@ struct DevState {
   int q;          // basis vectors committed
   int status;     // ST_*
   int pushes;     // snapshots offered (including ignored ones)
-  int pad0;
+  int jstep;      // batched form: q at the start of the current step
+  int act;        // batched form: 1 if the stream takes a snapshot this step
+  int full;       // batched form: a snapshot arrived after the capacity was reached
   double xfro2;   // ||X_1^q||_F^2 of the committed snapshots
   double xn2;     // ||x||^2 of the snapshot being pushed
   double scaleA;  // 1 / beta_{q,q}: scale of step 9 for the next push
   double tol;     // breakdown tolerance (relative to ||X||_F)
   double hlast;   // last h_{j+1,j}
-  double pad1[3];
+  double pad1[2];
 };
 
 // Pass modes of the fused row kernel.
@@ -77,6 +79,32 @@ struct SmallArgs {
   int j;           // basis size before this push (host's expectation)
 };
 
+// ---- batched form ----------------------------------------------------------
+// Per-stream descriptor (device memory).
+struct BatchStream {
+  void *W;
+  double *w, *part, *partn;
+  DevState *st;
+  double *H, *beta, *sigma, *bvec, *h, *s, *coefA, *coefB, *coefC;
+  int64_t n, P;
+  int n_max, ldg, ldH, ldB;
+  int nslot;  // partial-sum slots in use (units of this stream)
+  int pad;
+};
+// Work unit: panels [p0, p1) of stream s; partial sums go to slot `slot`.
+struct BatchUnit {
+  int s, slot;
+  int64_t p0, p1;
+};
+struct BatchArgs {
+  const BatchStream *streams;
+  const BatchUnit *units;
+  const void *const *xptrs;  // device array of S snapshot pointers (NULL: idle)
+  const int *rblk_stream;    // reduce blocks: stream of block b
+  const int *rblk_c0;        // reduce blocks: first column of block b
+  int S, n_units, n_rblocks, max_nmax;
+};
+
 // ---- launchers (defined in foa_kernels.hip) --------------------------------
 // tv_f64: V stored in FP64; tx_f64: snapshot in FP64.
 // nw: wavefronts per workgroup for an FP32 basis (8 or 16; FP64 uses 16).
@@ -98,5 +126,17 @@ hipError_t launch_modes_gemm(bool tv_f64, const void *W, int64_t n, int n_max, i
                              hipStream_t s);
 
 int pick_qw(int j, int cols_per_qw);
+
+// batched form (one call per kernel of a step; all captured in one graph)
+hipError_t launch_batch_begin(const BatchArgs &b, hipStream_t s);
+hipError_t launch_batch_pass(int mode, bool tv_f64, bool tx_f64, int qw, int grid, const BatchArgs &b,
+                             hipStream_t s);
+hipError_t launch_batch_reduce(int mode, const BatchArgs &b, hipStream_t s);
+hipError_t launch_batch_finalize(const BatchArgs &b, hipStream_t s);
+hipError_t launch_batch_nextb(const BatchArgs &b, hipStream_t s);
+hipError_t launch_batch_init_states(const BatchArgs &b, double tol, hipStream_t s);
+// fills out[0..n) with a deterministic pseudo-random sequence of tuning input k
+hipError_t launch_fill_random(float *out, int64_t n, uint32_t k, hipStream_t s);
+int batch_cols_per_qw(bool tv_f64);
 
 }  // namespace foa

@@ -118,8 +118,12 @@ __device__ __forceinline__ void unpack16<double>(const u32x4 &v, double (&o)[2])
 //            across panels; one butterfly per column at the end.
 // With PREF the next panel's tile is loaded while the current one is reduced.
 // ---------------------------------------------------------------------------
+// One workgroup processes panels pstart, pstart + pstep, ... < pend of one
+// stream and writes its partial sums to slot `slot`.  Called uniformly by
+// the whole workgroup (it synchronises).
 template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
-__global__ __launch_bounds__(NW * 64) void k_pass(PassArgs a) {
+__device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart, int64_t pend, int64_t pstep,
+                                              int slot) {
   constexpr int EPL = Vec<TV>::EPL;
   constexpr int LPC = 64 / EPL;  // lanes per 64-row column segment
   constexpr int CPW = EPL;       // columns per wavefront load
@@ -135,8 +139,6 @@ __global__ __launch_bounds__(NW * 64) void k_pass(PassArgs a) {
   __shared__ double s_w[PANEL];
   __shared__ double s_nrm[NW];
 
-  if (a.st->status != ST_ACTIVE) return;
-
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   // wavefront index made provably uniform so per-wave offsets stay scalar
@@ -145,6 +147,7 @@ __global__ __launch_bounds__(NW * 64) void k_pass(PassArgs a) {
   const int rg = lane % LPC;
   const int j = a.j;
 
+  __syncthreads();  // the previous call of this workgroup may still read LDS
   for (int c = tid; c < JCAP; c += NW * 64) s_coef[c] = (c < j) ? a.coef[c] : 0.0;
   const double scale = (MODE == PM_A) ? a.st->scaleA : 1.0;
   __syncthreads();
@@ -182,8 +185,8 @@ __global__ __launch_bounds__(NW * 64) void k_pass(PassArgs a) {
     }
   };
 
-  int64_t p = blockIdx.x;
-  if (PREF && p < a.P) {
+  int64_t p = pstart;
+  if (PREF && p < pend) {
     load_tile(p, t, tile_bytes);
     // Complete the first tile before the loop: otherwise its pending loads
     // merge with the loop back edge and every iteration waits for the
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(NW * 64) void k_pass(PassArgs a) {
     }
   }
   int par = 0;
-  for (; p < a.P; p += gridDim.x) {
+  for (; p < pend; p += pstep) {
     // y for the update rows of this wavefront (snapshot or work vector)
     double y;
     if (SRC_X) {
@@ -208,8 +211,8 @@ __global__ __launch_bounds__(NW * 64) void k_pass(PassArgs a) {
       y = buf_load_scalar<double>(rw, uact ? (unsigned)(urow * 8) : kOOR);
     }
     if (PREF) {
-      const bool more = p + gridDim.x < a.P;
-      load_tile(more ? p + gridDim.x : p, tn, more ? tile_bytes : 0u);
+      const bool more = p + pstep < pend;
+      load_tile(more ? p + pstep : p, tn, more ? tile_bytes : 0u);
     } else {
       load_tile(p, t, tile_bytes);
     }
@@ -299,7 +302,7 @@ __global__ __launch_bounds__(NW * 64) void k_pass(PassArgs a) {
 #pragma unroll
       for (int m = 1; m < LPC; m <<= 1) v += xor_shfl(v, m);
       const int c = cbase + g * GSTRIDE;
-      if (rg == 0 && c < j) a.part[(size_t)c * a.ldg + blockIdx.x] = v;
+      if (rg == 0 && c < j) a.part[(size_t)c * a.ldg + slot] = v;
     }
   }
   if (MODE != PM_B) {
@@ -310,9 +313,15 @@ __global__ __launch_bounds__(NW * 64) void k_pass(PassArgs a) {
     if (tid == 0) {
       double t2 = 0.0;
       for (int w2 = 0; w2 < NW; ++w2) t2 += s_nrm[w2];
-      a.partn[blockIdx.x] = t2;
+      a.partn[slot] = t2;
     }
   }
+}
+
+template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
+__global__ __launch_bounds__(NW * 64) void k_pass(PassArgs a) {
+  if (a.st->status != ST_ACTIVE) return;
+  row_pass_body<TV, TX, NW, QW, MODE, PREF>(a, blockIdx.x, a.P, gridDim.x, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -322,10 +331,9 @@ __global__ __launch_bounds__(NW * 64) void k_pass(PassArgs a) {
 // MODE 2 (after pass B): s = sigma o t, h += s (step 13), coefC = sigma o s.
 // ---------------------------------------------------------------------------
 template <int MODE>
-__global__ __launch_bounds__(256) void k_reduce(SmallArgs a) {
-  if (a.st->status != ST_ACTIVE) return;
+__device__ void reduce_body(const SmallArgs &a, int c0) {
   const int lane = threadIdx.x & 63;
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int c = c0 + (threadIdx.x >> 6);
   if (c < a.j) {
     const double *pc = a.part + (size_t)c * a.ldg;
     double t = 0.0;
@@ -353,6 +361,12 @@ __global__ __launch_bounds__(256) void k_reduce(SmallArgs a) {
   }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(256) void k_reduce(SmallArgs a) {
+  if (a.st->status != ST_ACTIVE) return;
+  reduce_body<MODE>(a, blockIdx.x * 4);
+}
+
 __device__ double block_sum_256(double t, double *sh) {
   const int tid = threadIdx.x;
   sh[tid] = t;
@@ -367,7 +381,7 @@ __device__ double block_sum_256(double t, double *sh) {
 }
 
 // Steps 15-18 plus the breakdown rule; single workgroup.
-__global__ __launch_bounds__(256) void k_finalize(SmallArgs a) {
+__device__ void finalize_body(const SmallArgs &a) {
   __shared__ double sh[256];
   __shared__ int s_status;
   DevState *st = a.st;
@@ -429,7 +443,7 @@ __global__ __launch_bounds__(256) void k_finalize(SmallArgs a) {
 }
 
 // Steps 2-3 for the first snapshot.
-__global__ __launch_bounds__(256) void k_finalize_init(SmallArgs a) {
+__device__ void finalize_init_body(const SmallArgs &a) {
   __shared__ double sh[256];
   DevState *st = a.st;
   const int tid = threadIdx.x;
@@ -460,14 +474,14 @@ __global__ __launch_bounds__(256) void k_finalize_init(SmallArgs a) {
 //   b_i = sum_{l = max(1, i-1)}^{J-1} h_{i,l} beta_{l,J}  (1-based), i = 1..J,
 // computed as 64 rows x 4 contiguous l-slices per block, slices combined in
 // order.  Also coefA = sigma o b and scaleA = 1 / beta_{J,J}.
-__global__ __launch_bounds__(256) void k_nextb(SmallArgs a) {
+__device__ void nextb_body(const SmallArgs &a, int chunk) {
   __shared__ double sh[4][64];
   DevState *st = a.st;
   if (st->status != ST_ACTIVE) return;
   const int J = st->q;
   const int r = threadIdx.x & 63;
   const int sl = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + r;  // 0-based row
+  const int i = chunk * 64 + r;  // 0-based row
   double t = 0.0;
   if (i < J) {
     const int lo = i > 0 ? i - 1 : 0;
@@ -485,13 +499,17 @@ __global__ __launch_bounds__(256) void k_nextb(SmallArgs a) {
     a.bvec[i] = b;
     a.coefA[i] = a.sigma[i] * b;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->scaleA = 1.0 / a.beta[(size_t)(J - 1) * a.ldB + (J - 1)];
+  if (chunk == 0 && threadIdx.x == 0) st->scaleA = 1.0 / a.beta[(size_t)(J - 1) * a.ldB + (J - 1)];
 }
+
+__global__ __launch_bounds__(256) void k_finalize(SmallArgs a) { finalize_body(a); }
+__global__ __launch_bounds__(256) void k_finalize_init(SmallArgs a) { finalize_init_body(a); }
+__global__ __launch_bounds__(256) void k_nextb(SmallArgs a) { nextb_body(a, blockIdx.x); }
 
 // Reset of one stream: scalar state, and zeros in every small array (the
 // entries of H_bar below the subdiagonal and of beta below the diagonal are
 // never written by the push kernels and must read as zero).
-__global__ __launch_bounds__(256) void k_init_state(SmallArgs a, double tol) {
+__device__ void init_state_body(const SmallArgs &a, double tol) {
   const size_t nH = (size_t)a.ldH * (a.n_max + 1), nB = (size_t)a.ldB * (a.n_max + 1);
   const size_t nv = (size_t)a.n_max + 1;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -511,7 +529,9 @@ __global__ __launch_bounds__(256) void k_init_state(SmallArgs a, double tol) {
     st->q = 0;
     st->status = ST_ACTIVE;
     st->pushes = 0;
-    st->pad0 = 0;
+    st->jstep = 0;
+    st->act = 0;
+    st->full = 0;
     st->xfro2 = 0.0;
     st->xn2 = 0.0;
     st->scaleA = 0.0;
@@ -519,6 +539,8 @@ __global__ __launch_bounds__(256) void k_init_state(SmallArgs a, double tol) {
     st->hlast = 0.0;
   }
 }
+
+__global__ __launch_bounds__(256) void k_init_state(SmallArgs a, double tol) { init_state_body(a, tol); }
 
 template <typename TV, typename TO>
 __global__ __launch_bounds__(256) void k_copy_basis(const TV *W, const double *sigma, int64_t r0,
@@ -652,6 +674,215 @@ hipError_t launch_copy_basis(bool tv_f64, const void *W, const double *sigma, in
       hipLaunchKernelGGL((k_copy_basis<float, float>), grid, dim3(256), 0, s, (const float *)W, sigma, r0,
                          nrows, n_max, ncols, (float *)out, ld);
   }
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent streams advanced by one snapshot per step.
+// Every kernel reads the per-stream step state (jstep, act) frozen by
+// k_batch_begin, so a captured graph of the step replays unchanged while the
+// streams grow.  Row passes walk (stream, panel range) work units; one pass
+// kernel per column-tile bucket processes the units of the streams whose
+// basis size falls in its bucket.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ SmallArgs small_of(const BatchStream &d) {
+  SmallArgs a{};
+  a.st = d.st;
+  a.H = d.H;
+  a.beta = d.beta;
+  a.sigma = d.sigma;
+  a.bvec = d.bvec;
+  a.h = d.h;
+  a.s = d.s;
+  a.coefA = d.coefA;
+  a.coefB = d.coefB;
+  a.coefC = d.coefC;
+  a.part = d.part;
+  a.partn = d.partn;
+  a.ldH = d.ldH;
+  a.ldB = d.ldB;
+  a.n_max = d.n_max;
+  a.G = d.nslot;
+  a.ldg = d.ldg;
+  a.j = d.st->jstep;
+  return a;
+}
+
+__global__ __launch_bounds__(256) void k_batch_begin(BatchArgs b) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= b.S) return;
+  const BatchStream &d = b.streams[s];
+  DevState *st = d.st;
+  const bool offered = b.xptrs[s] != nullptr;
+  const bool room = st->q < d.n_max;
+  st->jstep = st->q;
+  st->act = (st->status == ST_ACTIVE && offered && room) ? 1 : 0;
+  if (offered && !room && st->status == ST_ACTIVE) st->full = 1;
+}
+
+template <int NW, int EPL>
+__device__ __forceinline__ int qw_of(int j) {
+  int qw = 1;
+  while (qw < 16 && qw * NW * EPL < j) qw *= 2;
+  return qw;
+}
+
+template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
+__global__ __launch_bounds__(NW * 64) void k_pass_batch(BatchArgs b) {
+  for (int u = blockIdx.x; u < b.n_units; u += gridDim.x) {
+    const BatchUnit un = b.units[u];
+    const BatchStream &d = b.streams[un.s];
+    const DevState *st = d.st;
+    if (!st->act) continue;
+    const int j = st->jstep;
+    if (MODE == PM_INIT) {
+      if (j != 0) continue;
+    } else {
+      if (j == 0 || qw_of<NW, Vec<TV>::EPL>(j) != QW) continue;
+    }
+    PassArgs a{};
+    a.W = d.W;
+    a.x = b.xptrs[un.s];
+    a.w = d.w;
+    a.coef = MODE == PM_A ? d.coefA : (MODE == PM_B ? d.coefB : d.coefC);
+    a.st = st;
+    a.part = d.part;
+    a.partn = d.partn;
+    a.n = d.n;
+    a.P = d.P;
+    a.j = j;
+    a.n_max = d.n_max;
+    a.ldg = d.ldg;
+    row_pass_body<TV, TX, NW, QW, MODE, PREF>(a, un.p0, un.p1, 1, un.slot);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_reduce_batch(BatchArgs b) {
+  const int s = b.rblk_stream[blockIdx.x];
+  const BatchStream &d = b.streams[s];
+  if (!d.st->act || d.st->jstep == 0) return;
+  reduce_body<MODE>(small_of(d), b.rblk_c0[blockIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_finalize_batch(BatchArgs b) {
+  const int s = blockIdx.x;
+  const BatchStream &d = b.streams[s];
+  DevState *st = d.st;
+  if (b.xptrs[s] == nullptr) return;  // idle this step
+  if (!st->act) {                      // offered to a stream that no longer takes snapshots
+    if (threadIdx.x == 0) st->pushes += 1;
+    return;
+  }
+  const SmallArgs a = small_of(d);
+  if (st->jstep == 0)
+    finalize_init_body(a);
+  else
+    finalize_body(a);
+}
+
+__global__ __launch_bounds__(256) void k_nextb_batch(BatchArgs b) {
+  const BatchStream &d = b.streams[blockIdx.y];
+  if (!d.st->act) return;
+  if ((int)blockIdx.x * 64 > d.st->q) return;
+  nextb_body(small_of(d), blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_batch_init_states(BatchArgs b, double tol) {
+  init_state_body(small_of(b.streams[blockIdx.y]), tol);
+}
+
+// Tuning inputs: a fixed integer hash (splitmix64 finaliser) of (k, i) mapped
+// to [-1, 1).  Not part of the method.
+__global__ __launch_bounds__(256) void k_fill_random(float *out, int64_t n, uint32_t k) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    uint64_t z = ((uint64_t)k << 40) ^ (uint64_t)i;
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    out[i] = (float)((double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0);
+  }
+}
+
+int batch_cols_per_qw(bool tv_f64) { return tv_f64 ? 16 * 2 : 8 * 4; }
+
+template <typename TV, typename TX, int NW, int MODE, bool PREF>
+static hipError_t launch_batch_q(int qw, int grid, const BatchArgs &b, hipStream_t s) {
+  constexpr int NT = NW * 64;
+  switch (qw) {
+    case 1: hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 1, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b); break;
+    case 2: hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 2, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b); break;
+    case 4: hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 4, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b); break;
+    case 8: hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 8, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b); break;
+    default:
+      if constexpr (sizeof(TV) == 4 || !PREF)
+        hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 16, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b);
+      else
+        return hipErrorInvalidValue;
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <typename TV, typename TX, int NW>
+static hipError_t launch_batch_m(int mode, int qw, int grid, const BatchArgs &b, hipStream_t s) {
+  // FP64 tiles of 16 groups are not double buffered (register budget)
+  const bool pref = !(sizeof(TV) == 8 && qw >= 16);
+  switch (mode) {
+    case PM_INIT: return launch_batch_q<TV, TX, NW, PM_INIT, false>(1, grid, b, s);
+    case PM_A:
+      return pref ? launch_batch_q<TV, TX, NW, PM_A, true>(qw, grid, b, s)
+                  : launch_batch_q<TV, TX, NW, PM_A, false>(qw, grid, b, s);
+    case PM_B:
+      return pref ? launch_batch_q<TV, double, NW, PM_B, true>(qw, grid, b, s)
+                  : launch_batch_q<TV, double, NW, PM_B, false>(qw, grid, b, s);
+    default:
+      return pref ? launch_batch_q<TV, double, NW, PM_C, true>(qw, grid, b, s)
+                  : launch_batch_q<TV, double, NW, PM_C, false>(qw, grid, b, s);
+  }
+}
+
+hipError_t launch_batch_pass(int mode, bool tv_f64, bool tx_f64, int qw, int grid, const BatchArgs &b,
+                             hipStream_t s) {
+  if (tv_f64)
+    return tx_f64 ? launch_batch_m<double, double, 16>(mode, qw, grid, b, s)
+                  : launch_batch_m<double, float, 16>(mode, qw, grid, b, s);
+  return tx_f64 ? launch_batch_m<float, double, 8>(mode, qw, grid, b, s)
+                : launch_batch_m<float, float, 8>(mode, qw, grid, b, s);
+}
+
+hipError_t launch_batch_begin(const BatchArgs &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_begin, dim3((b.S + 255) / 256), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce(int mode, const BatchArgs &b, hipStream_t s) {
+  if (mode == 1)
+    hipLaunchKernelGGL(k_reduce_batch<1>, dim3(b.n_rblocks), dim3(256), 0, s, b);
+  else
+    hipLaunchKernelGGL(k_reduce_batch<2>, dim3(b.n_rblocks), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const BatchArgs &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_batch, dim3(b.S), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_nextb(const BatchArgs &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_nextb_batch, dim3((b.max_nmax + 64) / 64, b.S), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_init_states(const BatchArgs &b, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_init_states, dim3(4, b.S), dim3(256), 0, s, b, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_random(float *out, int64_t n, uint32_t k, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_random, dim3(256), dim3(256), 0, s, out, n, k);
   return hipGetLastError();
 }
 

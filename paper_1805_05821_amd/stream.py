@@ -94,3 +94,52 @@ class FOAStream:
 def hbar_beta_numpy(stream):
     H, B, q, m = stream.state()
     return np.asarray(H), np.asarray(B), q, m
+
+
+class FOABatch:
+    """Many independent streams in one workspace, advanced together
+    (foa_batch_* of the C ABI)."""
+
+    def __init__(self, n_list, nmax_list, prec="f32", device="cuda", stream=None, breakdown_tol=-1.0,
+                 tune_table=None, ws_fill=None):
+        import torch
+
+        self.n = [int(v) for v in n_list]
+        self.n_max = [int(v) for v in nmax_list]
+        self.S = len(self.n)
+        self.prec = F.FOA_PREC_F64 if prec in ("f64", F.FOA_PREC_F64) else F.FOA_PREC_F32
+        nbytes = F.foa_batch_workspace_bytes(self.n, self.n_max, self.prec)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        if ws_fill is not None:
+            self.ws.fill_(int(ws_fill))
+        self.device = device
+        self.b = F.foa_batch_init(self.n, self.n_max, self.prec, self.ws, stream, breakdown_tol, tune_table)
+        self._ptrs = torch.zeros(self.S, dtype=torch.int64, device=device)
+
+    def push(self, xs, x_dtype=None):
+        """xs: list of S device tensors (or None for an idle stream)."""
+        import torch
+
+        host = [0 if x is None else x.data_ptr() for x in xs]
+        if x_dtype is None:
+            x0 = next((x for x in xs if x is not None), None)
+            x_dtype = F.FOA_F64 if x0 is not None and x0.dtype == torch.float64 else F.FOA_F32
+        self._ptrs.copy_(torch.tensor(host, dtype=torch.int64), non_blocking=False)
+        return F.foa_batch_push(self.b, self._ptrs, x_dtype)
+
+    def sync(self):
+        return F.foa_batch_sync(self.b, self.S)
+
+    def view(self, s):
+        return F.foa_batch_view(self.b, s)
+
+    def close(self):
+        if self.b is not None:
+            F.foa_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
