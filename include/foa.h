@@ -215,6 +215,10 @@ foa_status foa_batch_sync(foa_batch b, int32_t *h_q, int32_t *h_status);
  * through foa_batch_push only (FOA_E_STATE otherwise). */
 foa_status foa_batch_view(foa_batch b, int32_t s, foa_ctx *view);
 
+/* Forget all snapshots of every stream (q = 0), keeping workspace, tuning and
+ * graphs.  Stream-ordered. */
+foa_status foa_batch_reset(foa_batch b);
+
 foa_status foa_batch_destroy(foa_batch b);
 
 #ifdef __cplusplus

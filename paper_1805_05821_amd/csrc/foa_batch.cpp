@@ -484,6 +484,11 @@ foa_status foa_batch_view(foa_batch b, int32_t s, foa_ctx *view) {
   return FOA_OK;
 }
 
+foa_status foa_batch_reset(foa_batch b) {
+  if (!b) return FOA_E_ARG;
+  return reset_states(b);
+}
+
 foa_status foa_batch_destroy(foa_batch b) {
   if (!b) return FOA_E_ARG;
   if (b->stream) (void)hipStreamSynchronize(b->stream);

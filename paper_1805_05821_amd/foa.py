@@ -36,7 +36,7 @@ EXPORTED = [
     "foa_get_state", "foa_copy_basis", "foa_copy_basis_rows", "foa_truncate", "foa_modes", "foa_indicators",
     "foa_reset", "foa_destroy", "foa_status_str", "foa_last_error", "foa_set_option", "foa_profile",
     "foa_batch_workspace_bytes", "foa_batch_init", "foa_batch_push", "foa_batch_sync",
-    "foa_batch_view", "foa_batch_destroy",
+    "foa_batch_view", "foa_batch_reset", "foa_batch_destroy",
 ]
 
 
@@ -83,6 +83,7 @@ def _load():
         "foa_batch_push": [P, P, c.c_int],
         "foa_batch_sync": [P, P, P],
         "foa_batch_view": [P, i32, c.POINTER(P)],
+        "foa_batch_reset": [P],
         "foa_batch_destroy": [P],
     }
     for name, args in sig.items():
@@ -282,6 +283,10 @@ def foa_batch_view(b, s):
     v = ctypes.c_void_p()
     _check(lib.foa_batch_view(b, int(s), ctypes.byref(v)))
     return v
+
+
+def foa_batch_reset(b):
+    return _check(lib.foa_batch_reset(b))
 
 
 def foa_batch_destroy(b):

@@ -127,6 +127,13 @@ class FOABatch:
         self._ptrs.copy_(torch.tensor(host, dtype=torch.int64), non_blocking=False)
         return F.foa_batch_push(self.b, self._ptrs, x_dtype)
 
+    def push_ptrs(self, d_ptrs, x_dtype):
+        """d_ptrs: device int64 tensor of S snapshot addresses (0 = idle)."""
+        return F.foa_batch_push(self.b, d_ptrs, x_dtype)
+
+    def reset(self):
+        return F.foa_batch_reset(self.b)
+
     def sync(self):
         return F.foa_batch_sync(self.b, self.S)
 
