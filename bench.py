@@ -142,6 +142,67 @@ def run_batched(bw, warmup, steps, streams=None):
             "alg_bytes_per_run": alg, "all_streams_complete": ok}
 
 
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def run_large(w, gemm_reps=3):
+    """The n = 1e8 workload: one FOA run over its snapshots (FP32 basis), then
+    the mode reconstruction Phi = V U_r Z at the signal rank (FP32 MFMA).  The
+    snapshots are freed before the mode matrix is allocated."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_1805_05821_amd import foa as F
+    from paper_1805_05821_amd.stream import FOAStream
+
+    t0 = time.perf_counter()
+    X, lam, b = datagen.snapshots_torch(w, "cuda")
+    torch.cuda.synchronize()
+    log(f"[large] generated X ({w.N} x {w.n}) in {time.perf_counter() - t0:.1f} s")
+    s = FOAStream(w.n, w.N, prec="f32")
+    s.set_option("profile", 1)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.push_all(X)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    st, q = s.sync()
+    launches, kms, kbytes = F.foa_profile(s.ctx)
+    del X
+    torch.cuda.empty_cache()
+    gbs = kbytes / (kms / 1e3) / 1e9
+    log(f"[large] FOA run {ms:.1f} ms, q={q}, row passes {gbs:.0f} GB/s")
+    r, _ = s.truncate(r_force=w.modes_r)
+    phi = torch.empty((w.modes_r, w.n), dtype=torch.float32, device="cuda")
+    F.foa_modes(s.ctx, w.modes_r // 2, phi, w.n, w.modes_r, F.FOA_F32)  # warm-up, eigendecomposition cached
+    F.foa_profile_modes(s.ctx)
+    for _ in range(gemm_reps):
+        lam_c, kind, amp, err = F.foa_modes(s.ctx, w.modes_r // 2, phi, w.n, w.modes_r, F.FOA_F32)
+    glaunch, gms, gflops = F.foa_profile_modes(s.ctx)
+    ncols = int(np.sum(np.where(kind == 1, 2, 1)))
+    big = lam[b >= 1e-2]
+    dist = float(np.abs(big[:, None] - lam_c[None, :]).min(axis=1).max())
+    s.close()
+    del s, phi
+    torch.cuda.empty_cache()
+    tflops = gflops / (gms / 1e3) / 1e12
+    log(f"[large] mode GEMM: {ncols} columns, {gms / glaunch:.2f} ms per launch, {tflops:.1f} TFLOP/s")
+    return {"workload": w.name, "n": w.n, "N": w.N, "form": "fp32-basis-cgs2",
+            "status": st, "q": q,
+            "value": round(w.N / (ms / 1e3), 3), "unit": "snapshots/s", "ms_per_run": round(ms, 3),
+            "row_pass_gbs": round(gbs, 1), "row_pass_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "mode_gemm": {"kernel": "k_modes_mfma (FP32 MFMA 32x32x2)", "r": r, "columns": ncols,
+                          "basis_columns": q - 1, "avg_launch_ms": round(gms / glaunch, 3),
+                          "flops_per_launch": gflops / glaunch, "achieved": round(tflops, 2),
+                          "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "bound": "mfma",
+                          "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4)},
+            "dominant_eig_max_distance": dist}
+
+
 def cpu_baseline(w, rows):
     import numpy as np
 
@@ -193,6 +254,8 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the plain FP64 form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the n = 1e8 run and its mode reconstruction")
     ap.add_argument("--cpu-rows", type=int, default=1 << 20)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--prefetch", type=int, default=-1)
@@ -292,11 +355,18 @@ def main():
         out["speedup_f32_vs_f64"] = round(snaps / snaps64, 3)
         out["error_f32_vs_f64"] = {"rel_H_2norm": eH, "kappa2": kap, "bound_10_eps32_kappa": 10 * EPS32 * kap,
                                    "within_bound": bool(eH <= 10 * EPS32 * kap)}
+    del X
+    torch.cuda.empty_cache()
     if not args.no_batched:
         try:
             out["batched_form"] = run_batched(datagen.get_workload("batched_256"), 1, 1)
         except Exception as e:  # reported, never silently dropped
             out["batched_form"] = {"error": f"{type(e).__name__}: {e}"}
+    if not args.no_large:
+        try:
+            out["large_form"] = run_large(datagen.get_workload("large_1e8x300"))
+        except Exception as e:  # reported, never silently dropped
+            out["large_form"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu:
         log(f"cpu baseline: oracle on {args.cpu_rows} rows ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)

@@ -188,6 +188,13 @@ foa_status foa_set_option(foa_ctx ctx, const char *key, int64_t value);
  * them.  Synchronises. */
 foa_status foa_profile(foa_ctx ctx, double out[3]);
 
+/* Timing of the mode reconstruction (foa_modes with a mode matrix), enabled
+ * by the same "profile" option: out[0] = launches of the reconstruction
+ * kernel, out[1] = their summed duration in milliseconds, out[2] = their
+ * summed algorithmic flops (2 n m r for m basis columns and r packed mode
+ * columns), all since the previous call, which resets them.  Synchronises. */
+foa_status foa_profile_modes(foa_ctx ctx, double out[3]);
+
 /* ---- many independent streams (batched form) ----------------------------- */
 
 /* Workspace for S streams with row counts n[s] and capacities n_max[s]. */

@@ -126,7 +126,7 @@ int pass_grid(const foa_ctx_s *c) {
   return g < 1 ? 1 : g;
 }
 
-static hipEvent_t take_event(foa_ctx_s *c) {
+hipEvent_t take_event(foa_ctx_s *c) {
   if (!c->ev_free.empty()) {
     hipEvent_t e = c->ev_free.back();
     c->ev_free.pop_back();
@@ -149,7 +149,7 @@ static hipError_t timed_pass(foa_ctx_s *c, int mode, bool v64, bool x64, bool pr
   hipError_t e = launch_pass(mode, v64, x64, pref, c->nw, G, pa, c->stream);
   if (c->profile && e0 && e1) {
     (void)hipEventRecord(e1, c->stream);
-    c->ev_pending.push_back({e0, e1, alg_bytes});
+    c->ev_pending.push_back({e0, e1, alg_bytes, 0});
   }
   return e;
 }
@@ -158,9 +158,15 @@ foa_status collect_profile(foa_ctx_s *c) {
   for (auto &p : c->ev_pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-      c->prof_launches += 1;
-      c->prof_ms += ms;
-      c->prof_bytes += p.bytes;
+      if (p.kind == 0) {
+        c->prof_launches += 1;
+        c->prof_ms += ms;
+        c->prof_bytes += p.work;
+      } else {
+        c->prof_gemm_launches += 1;
+        c->prof_gemm_ms += ms;
+        c->prof_gemm_flops += p.work;
+      }
     }
     c->ev_free.push_back(p.a);
     c->ev_free.push_back(p.b);
@@ -466,6 +472,18 @@ foa_status foa_profile(foa_ctx c, double out[3]) {
   out[1] = c->prof_ms;
   out[2] = c->prof_bytes;
   c->prof_launches = c->prof_ms = c->prof_bytes = 0;
+  return FOA_OK;
+}
+
+foa_status foa_profile_modes(foa_ctx c, double out[3]) {
+  if (!c || !out) return FOA_E_ARG;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_err(c, e, "hipStreamSynchronize");
+  collect_profile(c);
+  out[0] = c->prof_gemm_launches;
+  out[1] = c->prof_gemm_ms;
+  out[2] = c->prof_gemm_flops;
+  c->prof_gemm_launches = c->prof_gemm_ms = c->prof_gemm_flops = 0;
   return FOA_OK;
 }
 

@@ -75,10 +75,12 @@ struct foa_ctx_s {
   std::string err;
   // row-pass timing (foa_profile)
   bool profile = false;
-  struct EvPair { hipEvent_t a, b; double bytes; };
+  // kind 0: row pass (work = algorithmic bytes); kind 1: mode GEMM (work = flops)
+  struct EvPair { hipEvent_t a, b; double work; int kind; };
   std::vector<EvPair> ev_pending;
   std::vector<hipEvent_t> ev_free;
   double prof_launches = 0, prof_ms = 0, prof_bytes = 0;
+  double prof_gemm_launches = 0, prof_gemm_ms = 0, prof_gemm_flops = 0;
 };
 
 namespace foa {
@@ -95,5 +97,6 @@ int projected_order(const foa_ctx_s *c);
 int pass_grid(const foa_ctx_s *c);
 foa_status collect_profile(foa_ctx_s *c);
 void release_events(foa_ctx_s *c);
+hipEvent_t take_event(foa_ctx_s *c);
 
 }  // namespace foa

@@ -1,6 +1,10 @@
 // Mode reconstruction Phi = V B (Algorithm 1 steps 25 and 28): the panel-layout
 // basis W (n x k columns in use, FP32 or FP64) times the k x r coefficient
-// matrix B (FP64, sigma folded in, packed real columns).
+// matrix B (FP64, sigma folded in, packed real columns).  An FP32 basis with
+// FP32 output runs on FP32 MFMA; every other combination uses the FP64-
+// accumulating row kernel.
+#include <algorithm>
+
 #include "foa_internal.h"
 
 namespace foa {
@@ -32,6 +36,126 @@ __global__ __launch_bounds__(256) void k_modes_rowwise(const TV *W, int64_t n, i
   for (int cc = 0; cc < nc; ++cc) out[(size_t)(c0 + cc) * ld + row] = (TO)acc[cc];
 }
 
+// MFMA kernel (FP32 basis, FP32 output): Phi^T = B^T W^T on 32x32x2 FP32 MFMA
+// with FP32 accumulation.  Tile: 128 data rows (two panels) x 32*NB mode
+// columns per workgroup; wavefront w owns data rows 32w..32w+31 and all NB
+// 32-mode blocks, so for r <= 256 the basis is read exactly once.  k advances
+// in chunks of 32 staged through LDS, the next chunk's global loads in flight
+// in registers while the current one is multiplied: W as As[k][row] (rows
+// contiguous, as in the panel layout; stride 160 so the two half-wavefronts of
+// a fragment read are 32 banks apart), B as Bs[k][mode] (odd stride, so the
+// transposing writes are conflict-free).  Operands: A = B^T (lane l holds
+// mode l%32, k-offset l/32), B = W^T (lane l holds data row l%32, k-offset
+// l/32); the result D[i][j] has j = lane % 32, so each store instruction
+// writes 32 consecutive rows of one mode column.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+constexpr int MT_ROWS = 128, MT_K = 32, MT_LDA = 160;
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_modes_mfma(const float *W, int64_t n, int64_t P, int n_max, int kdim,
+                                                    const double *B, int r, float *out, int64_t ld) {
+  constexpr int LDB = 32 * NB + 1;
+  constexpr int BPT = NB * 4;  // B elements staged per thread per chunk (32 k x 32 NB modes / 256)
+  __shared__ float As[MT_K * MT_LDA];
+  __shared__ float Bs[MT_K * LDB];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.x * MT_ROWS;
+  const int n0 = blockIdx.y * 32 * NB;
+  f32x16 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc[b][t] = 0.f;
+
+  f32x4v ra[4];
+  double rb[BPT];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = (tid + u * 256) * 4;  // first of 4 consecutive rows
+      const int c = e / MT_ROWS, row = e % MT_ROWS;
+      const int64_t p = (m0 + row) / PANEL;
+      ra[u] = f32x4v{0.f, 0.f, 0.f, 0.f};
+      if (k0 + c < kdim && p < P)
+        ra[u] = *reinterpret_cast<const f32x4v *>(W + ((size_t)p * n_max + (k0 + c)) * PANEL + (row % PANEL));
+    }
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+      const int e = tid + u * 256;
+      const int c = e / MT_K, kk = e % MT_K;
+      rb[u] = 0.0;
+      if (n0 + c < r && k0 + kk < kdim) rb[u] = B[(size_t)(n0 + c) * kdim + (k0 + kk)];
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = (tid + u * 256) * 4;
+      *reinterpret_cast<f32x4v *>(&As[(e / MT_ROWS) * MT_LDA + e % MT_ROWS]) = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+      const int e = tid + u * 256;
+      Bs[(e % MT_K) * LDB + e / MT_K] = (float)rb[u];
+    }
+  };
+
+  load_chunk(0);
+  for (int k0 = 0; k0 < kdim; k0 += MT_K) {
+    store_chunk();
+    __syncthreads();
+    if (k0 + MT_K < kdim) load_chunk(k0 + MT_K);
+#pragma unroll 4
+    for (int kk = 0; kk < MT_K; kk += 2) {
+      const int kr = kk + (lane >> 5);
+      const float wop = As[kr * MT_LDA + wave * 32 + (lane & 31)];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const float bop = Bs[kr * LDB + b * 32 + (lane & 31)];
+        acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(bop, wop, acc[b], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // D[i][j]: j = lane % 32 (data row), i = 8 (t / 4) + 4 (lane / 32) + t % 4 (mode)
+  const int64_t row = m0 + wave * 32 + (lane & 31);
+  if (row >= n) return;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int mode = n0 + b * 32 + 8 * (t >> 2) + 4 * (lane >> 5) + (t & 3);
+      if (mode < r) out[(size_t)mode * ld + row] = acc[b][t];
+    }
+  }
+}
+
+template <int NB>
+static void launch_mfma_nb(const float *W, int64_t n, int n_max, int k, const double *B, int r, float *out,
+                           int64_t ld, hipStream_t s) {
+  const int64_t P = (n + PANEL - 1) / PANEL;
+  dim3 g((unsigned)((n + MT_ROWS - 1) / MT_ROWS), (unsigned)((r + 32 * NB - 1) / (32 * NB)));
+  hipLaunchKernelGGL((k_modes_mfma<NB>), g, dim3(256), 0, s, W, n, P, n_max, k, B, r, out, ld);
+}
+
+static void launch_mfma(const float *W, int64_t n, int n_max, int k, const double *B, int r, float *out,
+                        int64_t ld, hipStream_t s) {
+  switch (std::min(8, (r + 31) / 32)) {
+    case 1: launch_mfma_nb<1>(W, n, n_max, k, B, r, out, ld, s); break;
+    case 2: launch_mfma_nb<2>(W, n, n_max, k, B, r, out, ld, s); break;
+    case 3: launch_mfma_nb<3>(W, n, n_max, k, B, r, out, ld, s); break;
+    case 4: launch_mfma_nb<4>(W, n, n_max, k, B, r, out, ld, s); break;
+    case 5: launch_mfma_nb<5>(W, n, n_max, k, B, r, out, ld, s); break;
+    case 6: launch_mfma_nb<6>(W, n, n_max, k, B, r, out, ld, s); break;
+    case 7: launch_mfma_nb<7>(W, n, n_max, k, B, r, out, ld, s); break;
+    default: launch_mfma_nb<8>(W, n, n_max, k, B, r, out, ld, s); break;
+  }
+}
+
 hipError_t launch_modes_gemm(bool tv_f64, const void *W, int64_t n, int n_max, int k, const double *B, int r,
                              void *out, int64_t ld, bool out_f64, hipStream_t s) {
   if (r <= 0 || k <= 0) return hipSuccess;
@@ -45,12 +169,12 @@ hipError_t launch_modes_gemm(bool tv_f64, const void *W, int64_t n, int n_max, i
       hipLaunchKernelGGL((k_modes_rowwise<double, float>), grid, dim3(256), 0, s, (const double *)W, n, n_max, k,
                          B, r, (float *)out, ld);
   } else {
-    if (out_f64)
+    if (out_f64) {
       hipLaunchKernelGGL((k_modes_rowwise<float, double>), grid, dim3(256), 0, s, (const float *)W, n, n_max, k,
                          B, r, (double *)out, ld);
-    else
-      hipLaunchKernelGGL((k_modes_rowwise<float, float>), grid, dim3(256), 0, s, (const float *)W, n, n_max, k, B,
-                         r, (float *)out, ld);
+    } else {
+      launch_mfma((const float *)W, n, n_max, k, B, r, (float *)out, ld, s);
+    }
   }
   return hipGetLastError();
 }

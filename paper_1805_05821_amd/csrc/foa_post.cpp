@@ -262,8 +262,18 @@ foa_status foa_modes(foa_ctx c, int32_t m_max, double *h_lambda, int8_t *h_kind,
   double *dB = reinterpret_cast<double *>(static_cast<char *>(c->ws) + c->L.mcoef);
   hipError_t e = hipMemcpy(dB, Bp.data(), Bp.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_err(c, e, "hipMemcpy mode coefficients");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->profile) {
+    e0 = take_event(c);
+    e1 = take_event(c);
+    if (e0 && e1) (void)hipEventRecord(e0, c->stream);
+  }
   e = launch_modes_gemm(c->prec == FOA_PREC_F64, c->W, c->n, c->n_max, m, dB, ncols, d_phi, ld_phi,
                         phi_dtype == FOA_F64, c->stream);
+  if (c->profile && e0 && e1) {
+    (void)hipEventRecord(e1, c->stream);
+    c->ev_pending.push_back({e0, e1, 2.0 * (double)c->n * m * ncols, 1});
+  }
   return hip_err(c, e, "mode GEMM");
 }
 

@@ -35,6 +35,7 @@ EXPORTED = [
     "foa_workspace_bytes", "foa_init", "foa_push_snapshot", "foa_push_block", "foa_sync",
     "foa_get_state", "foa_copy_basis", "foa_copy_basis_rows", "foa_truncate", "foa_modes", "foa_indicators",
     "foa_reset", "foa_destroy", "foa_status_str", "foa_last_error", "foa_set_option", "foa_profile",
+    "foa_profile_modes",
     "foa_batch_workspace_bytes", "foa_batch_init", "foa_batch_push", "foa_batch_sync",
     "foa_batch_view", "foa_batch_reset", "foa_batch_destroy",
 ]
@@ -78,6 +79,7 @@ def _load():
         "foa_destroy": [P],
         "foa_set_option": [P, c.c_char_p, i64],
         "foa_profile": [P, P],
+        "foa_profile_modes": [P, P],
         "foa_batch_workspace_bytes": [i32, P, P, c.c_int, c.POINTER(sz)],
         "foa_batch_init": [c.POINTER(P), i32, P, P, c.c_int, P, sz, P, f64, c.c_char_p],
         "foa_batch_push": [P, P, c.c_int],
@@ -240,6 +242,13 @@ def foa_profile(ctx):
     """(launches, total_ms, algorithmic_bytes) of the row passes since the last call."""
     out = np.zeros(3, dtype=np.float64)
     _check(lib.foa_profile(ctx, _host(out)), ctx)
+    return int(out[0]), float(out[1]), float(out[2])
+
+
+def foa_profile_modes(ctx):
+    """(launches, total_ms, algorithmic_flops) of the mode reconstruction since the last call."""
+    out = np.zeros(3, dtype=np.float64)
+    _check(lib.foa_profile_modes(ctx, _host(out)), ctx)
     return int(out[0]), float(out[1]), float(out[2])
 
 

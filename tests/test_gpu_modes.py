@@ -158,3 +158,46 @@ def test_f32_modes_close_to_f64():
     assert np.array_equal(ka, kb)
     assert match_eigs(la, lb) <= 1e-4
     assert _match_columns(Pb, Pa, ka) <= 1e-3
+
+
+@pytest.mark.parametrize("n,N,r_force", [(100037, 101, -1), (100037, 101, 37), (5000, 300, -1)])
+def test_mfma_modes_match_fp64_accumulation(n, N, r_force):
+    """FP32 basis: the FP32-output reconstruction (FP32 MFMA, FP32 accumulation)
+    against the FP64-output one (FP64 accumulation) from the same stored basis
+    and coefficients.  Shapes span several 128-row tiles with a ragged tail,
+    several 32-deep k chunks with a ragged last one, ragged mode blocks and,
+    for N = 300, a second 256-mode tile.  With an orthonormal basis a column's
+    2-norm error is at most gamma_{k+1} sqrt(k) times its norm (FP32 rounding
+    of the coefficients and k FP32 multiply-adds); a wrong fragment layout
+    gives O(1) errors."""
+    import torch
+
+    from paper_1805_05821_amd import foa as F
+
+    rng = np.random.default_rng(n + N)
+    X = rng.standard_normal((n, N))
+    g = run_gpu(X, "f32", tol=0.0)
+    s = g["stream"]
+    assert g["q"] == N
+    if r_force > 0:
+        r, _ = s.truncate(r_force=r_force)
+        assert r == r_force
+    outs = {}
+    for dt, code, tdt in (("f64", F.FOA_F64, torch.float64), ("f32", F.FOA_F32, torch.float32)):
+        phi = torch.full((N, n), float("nan"), dtype=tdt, device="cuda")
+        lam, kind, amp, err = F.foa_modes(s.ctx, N, phi, n, N, code)
+        ncols = int(np.sum(np.where(kind == 1, 2, 1)))
+        outs[dt] = (lam, kind, ncols, phi[:ncols].double().cpu().numpy())
+        # columns past the packed ones are left untouched
+        assert torch.isnan(phi[ncols:]).all()
+    l64, k64, c64, P64 = outs["f64"]
+    l32, k32, c32, P32 = outs["f32"]
+    assert np.array_equal(k64, k32) and c64 == c32 and np.array_equal(l64, l32)
+    k = g["m"]
+    tol = (k + 2) * np.sqrt(k) * 2.0 ** -24
+    err = np.linalg.norm(P32 - P64, axis=1) / np.linalg.norm(P64, axis=1)
+    announce(f"n={n} N={N} r_force={r_force}: {c64} columns, k={k}, max column rel err {err.max():.2e} "
+             f"(bound {tol:.1e})")
+    assert np.isfinite(P32).all()
+    assert err.max() <= tol
+    s.close()
