@@ -61,7 +61,8 @@ Layout make_layout(int64_t n, int n_max, foa_prec prec, int ldg) {
   L.coefB = take(vec);
   L.coefC = take(vec);
   L.st = take(sizeof(DevState));
-  L.mcoef = take((size_t)n_max * n_max * 8);
+  // mode coefficients: FP64 k x r, or the padded FP32 layout of the MFMA path
+  L.mcoef = take(std::max((size_t)n_max * n_max * 8, (size_t)modes_kpad(n_max) * modes_rpad(n_max) * 4));
   L.total = off;
   return L;
 }

@@ -118,11 +118,17 @@ hipError_t launch_copy_basis(bool tv_f64, const void *W, const double *sigma, in
                              int64_t nrows, int n_max, int ncols, void *out, int64_t ld,
                              bool out_f64, hipStream_t s);
 hipError_t launch_init_state(const SmallArgs &a, double tol, hipStream_t s);
-// Phi = W * B for the panel-layout basis W (n x k used columns) and the
-// k x r FP64 coefficient matrix B (column-major, leading dimension k, sigma
-// already folded in); Phi is column-major with leading dimension ld.
+// Phi = W * B for the panel-layout basis W (n x k used columns) and a k x r
+// coefficient matrix (sigma already folded in); Phi is column-major with
+// leading dimension ld.  Two coefficient layouts, chosen by modes_use_mfma:
+//  * FP32 MFMA path (FP32 basis and FP32 output): B is FP32, row-major
+//    modes_kpad(k) x modes_rpad(r) (mode index contiguous), zero-padded;
+//  * otherwise: B is FP64, column-major k x r (leading dimension k).
+bool modes_use_mfma(bool tv_f64, bool out_f64);
+int modes_kpad(int k);
+int modes_rpad(int r);
 hipError_t launch_modes_gemm(bool tv_f64, const void *W, int64_t n, int n_max, int k,
-                             const double *B, int r, void *out, int64_t ld, bool out_f64,
+                             const void *B, int r, void *out, int64_t ld, bool out_f64,
                              hipStream_t s);
 
 int pick_qw(int j, int cols_per_qw);

@@ -29,6 +29,7 @@
 
 #include <math.h>
 
+#include "foa_buffer.h"
 #include "foa_internal.h"
 
 namespace foa {
@@ -40,23 +41,6 @@ struct Vec {
 
 
 __device__ __forceinline__ double xor_shfl(double v, int m) { return __shfl_xor(v, m, 64); }
-
-// ---------------------------------------------------------------------------
-// Buffer-resource helpers.  Every global access of the row pass is an
-// unconditional buffer load/store on a per-panel resource: the hardware range
-// check (offset >= num_records) returns 0 for loads and drops stores, which
-// masks dead columns, padded rows and idle lanes without branches, so the
-// compiler can count outstanding memory operations exactly and keep the
-// prefetched panel in flight across the compute of the current one.
-// ---------------------------------------------------------------------------
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-constexpr int kRsrcWord3 = 0x00020000;   // raw buffer, 32-bit data format (CDNA)
-constexpr unsigned kOOR = 0x80000000u;   // offset beyond every range used below
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, unsigned bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kRsrcWord3);
-}
 
 template <typename T>
 __device__ __forceinline__ double buf_load_scalar(__amdgpu_buffer_rsrc_t r, unsigned off);

@@ -247,20 +247,30 @@ foa_status foa_modes(foa_ctx c, int32_t m_max, double *h_lambda, int8_t *h_kind,
   if (!d_phi || ncols == 0) return FOA_OK;
   // packed real coefficients, sigma folded in: V = W diag(sigma)
   const int m = d.m;
-  std::vector<double> Bp((size_t)m * ncols);
+  const bool v64 = c->prec == FOA_PREC_F64, o64 = phi_dtype == FOA_F64;
+  const bool mfma = modes_use_mfma(v64, o64);
+  const size_t ldp = mfma ? (size_t)modes_rpad(ncols) : 1;   // stride between rows l
+  const size_t cst = mfma ? 1 : (size_t)m;                    // stride between columns
+  std::vector<double> Bp(mfma ? (size_t)modes_kpad(m) * ldp : (size_t)m * ncols, 0.0);
   int col = 0;
   for (int e = 0; e < cnt; ++e) {
     const int i = d.entries[e];
     const cd *b = d.B.data() + (size_t)i * m;
-    for (int l = 0; l < m; ++l) Bp[(size_t)col * m + l] = c->hsigma[l] * b[l].real();
+    for (int l = 0; l < m; ++l) Bp[col * cst + l * ldp] = c->hsigma[l] * b[l].real();
     ++col;
     if (!d.is_real[i]) {
-      for (int l = 0; l < m; ++l) Bp[(size_t)col * m + l] = c->hsigma[l] * b[l].imag();
+      for (int l = 0; l < m; ++l) Bp[col * cst + l * ldp] = c->hsigma[l] * b[l].imag();
       ++col;
     }
   }
-  double *dB = reinterpret_cast<double *>(static_cast<char *>(c->ws) + c->L.mcoef);
-  hipError_t e = hipMemcpy(dB, Bp.data(), Bp.size() * sizeof(double), hipMemcpyHostToDevice);
+  void *dB = static_cast<char *>(c->ws) + c->L.mcoef;
+  hipError_t e;
+  if (mfma) {
+    std::vector<float> Bf(Bp.begin(), Bp.end());
+    e = hipMemcpy(dB, Bf.data(), Bf.size() * sizeof(float), hipMemcpyHostToDevice);
+  } else {
+    e = hipMemcpy(dB, Bp.data(), Bp.size() * sizeof(double), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) return hip_err(c, e, "hipMemcpy mode coefficients");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->profile) {
@@ -268,8 +278,7 @@ foa_status foa_modes(foa_ctx c, int32_t m_max, double *h_lambda, int8_t *h_kind,
     e1 = take_event(c);
     if (e0 && e1) (void)hipEventRecord(e0, c->stream);
   }
-  e = launch_modes_gemm(c->prec == FOA_PREC_F64, c->W, c->n, c->n_max, m, dB, ncols, d_phi, ld_phi,
-                        phi_dtype == FOA_F64, c->stream);
+  e = launch_modes_gemm(v64, c->W, c->n, c->n_max, m, dB, ncols, d_phi, ld_phi, o64, c->stream);
   if (c->profile && e0 && e1) {
     (void)hipEventRecord(e1, c->stream);
     c->ev_pending.push_back({e0, e1, 2.0 * (double)c->n * m * ncols, 1});
