@@ -203,8 +203,13 @@ foa_status foa_batch_workspace_bytes(int32_t S, const int64_t *n, const int32_t 
 
 /* Create S independent streams sharing one workspace and one hipStream_t.
  * Every push advances all streams by one snapshot in a single graph launch.
- * tune_table_json: path of an autotuner table (read and updated), or NULL
- * for the built-in choice. */
+ * The launch configuration (row-pass grid and smallest panel range per
+ * workgroup) is chosen by timing candidates at init, or read from
+ * tune_table_json: path of an autotuner table (read, and appended to when the
+ * shape is new), or NULL to time the candidates at every init.  The
+ * configuration fixes the summation order of the row passes: the same
+ * configuration and the same pushes give bitwise-identical results; another
+ * configuration changes them by rounding only. */
 foa_status foa_batch_init(foa_batch *b, int32_t S, const int64_t *n, const int32_t *n_max,
                           foa_prec prec, void *d_workspace, size_t ws_bytes, void *hip_stream,
                           double breakdown_tol, const char *tune_table_json);

@@ -4,11 +4,11 @@
 // stream of foa_api.cpp (same layout, same kernels' arithmetic); per-stream
 // context views give access to its state, basis, truncation and modes.
 //
-// Work decomposition of the row passes: (stream, panel range) units, ordered
-// by decreasing estimated cost and dealt round-robin to a persistent grid;
-// one pass kernel per column-tile bucket takes the units of the streams whose
-// basis size falls in its bucket.  The unit size and the grid are chosen by
-// timing candidates (autotuner) and cached in a JSON table.
+// Work decomposition of the row passes, rebuilt on the device every step: the
+// active streams are bucketed by basis size (one pass kernel per column-tile
+// width) and each bucket's panels are cut into equal contiguous ranges, one
+// per workgroup.  The grid and the smallest range ("unit_panels") are chosen
+// by timing candidates (autotuner) and cached in a JSON table.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,7 +29,7 @@ using namespace foa;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMinUnitPanels = 4;                 // smallest unit: sizes the partial slots
+constexpr int kMinUnitPanels = 4;                 // smallest range: sizes the partial slots
 constexpr int kUnitCandidates[] = {4, 16, 64};
 constexpr int kTuneSteps = 48, kTuneTimed = 16;   // tuning run: last kTuneTimed of kTuneSteps steps
 
@@ -38,8 +38,9 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct BatchLayout {
   std::vector<size_t> off;       // per-stream Layout base
   std::vector<Layout> L;
-  size_t states = 0, streams = 0, units = 0, xptrs = 0, rblk_s = 0, rblk_c = 0, tune_x = 0, total = 0;
-  size_t units_cap = 0, rblocks = 0;
+  size_t states = 0, streams = 0, xptrs = 0, rblk_s = 0, rblk_c = 0, tune_x = 0, total = 0;
+  size_t plist = 0, ppre = 0, pfirst = 0, pmeta = 0, pspos = 0;
+  size_t rblocks = 0;
   int64_t max_n = 0;
   int max_nmax = 0;
 };
@@ -49,12 +50,12 @@ BatchLayout batch_layout(int S, const int64_t *n, const int32_t *n_max, foa_prec
   size_t o = 0;
   for (int s = 0; s < S; ++s) {
     const int64_t P = (n[s] + PANEL - 1) / PANEL;
-    const int slots = (int)((P + kMinUnitPanels - 1) / kMinUnitPanels);
+    // ranges are >= kMinUnitPanels panels, so at most P / kMinUnitPanels + 2 touch a stream
+    const int slots = (int)((P + kMinUnitPanels - 1) / kMinUnitPanels) + 2;
     Layout L = make_layout(n[s], n_max[s], prec, slots);
     B.off.push_back(o);
     B.L.push_back(L);
     o = align_up(o + L.total);
-    B.units_cap += (size_t)slots;
     B.rblocks += (size_t)(n_max[s] + 1 + 3) / 4;
     B.max_n = std::max<int64_t>(B.max_n, n[s]);
     B.max_nmax = std::max<int>(B.max_nmax, n_max[s]);
@@ -66,7 +67,11 @@ BatchLayout batch_layout(int S, const int64_t *n, const int32_t *n_max, foa_prec
   };
   B.states = take((size_t)S * sizeof(DevState));
   B.streams = take((size_t)S * sizeof(BatchStream));
-  B.units = take(B.units_cap * sizeof(BatchUnit));
+  B.plist = take((size_t)NBUCKET * S * sizeof(int));
+  B.ppre = take((size_t)NBUCKET * (S + 1) * sizeof(int64_t));
+  B.pfirst = take((size_t)NBUCKET * kMaxBatchGrid * sizeof(int));
+  B.pmeta = take((size_t)NBUCKET * 2 * sizeof(int));
+  B.pspos = take((size_t)S * sizeof(int));
   B.xptrs = take((size_t)S * sizeof(void *));
   B.rblk_s = take(B.rblocks * sizeof(int));
   B.rblk_c = take(B.rblocks * sizeof(int));
@@ -101,28 +106,7 @@ struct foa_batch_s {
 
 namespace {
 
-// Units of a given size, ordered by decreasing estimated cost (panels x n_max).
-int build_units(foa_batch_s *b, int unit_panels, std::vector<BatchUnit> &units, std::vector<int> &nslot) {
-  units.clear();
-  nslot.assign(b->S, 0);
-  for (int s = 0; s < b->S; ++s) {
-    const int64_t P = b->B.L[s].P;
-    int slot = 0;
-    for (int64_t p0 = 0; p0 < P; p0 += unit_panels, ++slot)
-      units.push_back(BatchUnit{s, slot, p0, std::min<int64_t>(P, p0 + unit_panels)});
-    nslot[s] = slot;
-  }
-  std::stable_sort(units.begin(), units.end(), [&](const BatchUnit &a, const BatchUnit &c) {
-    const double ca = (double)(a.p1 - a.p0) * b->nmax[a.s], cc = (double)(c.p1 - c.p0) * b->nmax[c.s];
-    return ca > cc;
-  });
-  return (int)units.size();
-}
-
 foa_status upload_config(foa_batch_s *b, int unit_panels) {
-  std::vector<BatchUnit> units;
-  std::vector<int> nslot;
-  const int nu = build_units(b, unit_panels, units, nslot);
   std::vector<BatchStream> ds(b->S);
   for (int s = 0; s < b->S; ++s) {
     foa_ctx_s *v = b->views[s];
@@ -147,15 +131,12 @@ foa_status upload_config(foa_batch_s *b, int unit_panels) {
     d.ldg = v->L.ldg;
     d.ldH = v->L.ldH;
     d.ldB = v->L.ldB;
-    d.nslot = nslot[s];
-    d.pad = 0;
   }
   hipError_t e = hipMemcpy(b->ws + b->B.streams, ds.data(), ds.size() * sizeof(BatchStream), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(b->ws + b->B.units, units.data(), units.size() * sizeof(BatchUnit), hipMemcpyHostToDevice);
   if (e != hipSuccess) return FOA_E_DEVICE;
-  b->args.n_units = nu;
   b->unit_panels = unit_panels;
+  b->args.min_seg = unit_panels;
+  b->args.grid = b->grid;
   return FOA_OK;
 }
 
@@ -166,7 +147,7 @@ hipError_t enqueue_step(foa_batch_s *b, bool x_f64, hipStream_t s) {
   const int qmax = pick_qw(std::max(b->B.max_nmax - 1, 1), cols);
   const BatchArgs &a = b->args;
   hipError_t e;
-  if ((e = launch_batch_begin(a, s)) != hipSuccess) return e;
+  if ((e = launch_batch_plan(a, s)) != hipSuccess) return e;
   if ((e = launch_batch_pass(PM_INIT, v64, x_f64, 1, b->grid, a, s)) != hipSuccess) return e;
   for (int qw = 1; qw <= qmax; qw *= 2)
     if ((e = launch_batch_pass(PM_A, v64, x_f64, qw, b->grid, a, s)) != hipSuccess) return e;
@@ -272,7 +253,7 @@ void write_table(const std::string &path, const std::vector<TuneEntry> &ents) {
 // Time kTuneTimed steps (after warm-up steps) of synthetic pushes for one
 // configuration; inputs are a hash sequence regenerated every step.
 foa_status time_config(foa_batch_s *b, int unit, int grid, double *ms_out) {
-  b->grid = grid;
+  b->grid = std::min(grid, kMaxBatchGrid);
   foa_status r = upload_config(b, unit);
   if (r != FOA_OK) return r;
   if ((r = reset_states(b)) != FOA_OK) return r;
@@ -307,7 +288,7 @@ foa_status tune(foa_batch_s *b) {
     table = read_table(b->tune_path);
     for (const TuneEntry &t : table)
       if (t.key == b->tune_key) {
-        b->grid = t.grid;
+        b->grid = std::min(t.grid, kMaxBatchGrid);
         b->tuned_ms = t.ms;
         return upload_config(b, t.unit);
       }
@@ -326,7 +307,7 @@ foa_status tune(foa_batch_s *b) {
       }
     }
   }
-  b->grid = bg;
+  b->grid = std::min(bg, kMaxBatchGrid);
   b->tuned_ms = best;
   foa_status r = upload_config(b, bu);
   if (r != FOA_OK) return r;
@@ -372,7 +353,7 @@ foa_status foa_batch_init(foa_batch *out, int32_t S, const int64_t *n, const int
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->device = dev;
   b->cus = cus;
-  b->grid = 2 * cus;
+  b->grid = std::min(2 * cus, kMaxBatchGrid);
   b->B = batch_layout(S, n, n_max, prec);
   b->n.assign(n, n + S);
   b->nmax.assign(n_max, n_max + S);
@@ -402,7 +383,12 @@ foa_status foa_batch_init(foa_batch *out, int32_t S, const int64_t *n, const int
     b->views.push_back(v);
   }
   b->args.streams = reinterpret_cast<const BatchStream *>(b->ws + b->B.streams);
-  b->args.units = reinterpret_cast<const BatchUnit *>(b->ws + b->B.units);
+  b->args.list = reinterpret_cast<int *>(b->ws + b->B.plist);
+  b->args.pre = reinterpret_cast<int64_t *>(b->ws + b->B.ppre);
+  b->args.first = reinterpret_cast<int *>(b->ws + b->B.pfirst);
+  b->args.meta = reinterpret_cast<int *>(b->ws + b->B.pmeta);
+  b->args.spos = reinterpret_cast<int *>(b->ws + b->B.pspos);
+  b->args.cols_per_qw = batch_cols_per_qw(prec == FOA_PREC_F64);
   b->args.xptrs = reinterpret_cast<const void *const *>(b->ws + b->B.xptrs);
   b->args.rblk_stream = reinterpret_cast<const int *>(b->ws + b->B.rblk_s);
   b->args.rblk_c0 = reinterpret_cast<const int *>(b->ws + b->B.rblk_c);

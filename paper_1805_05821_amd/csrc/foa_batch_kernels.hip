@@ -1,0 +1,369 @@
+// Batched form of the FOA push (Algorithm 1 steps 5-18 for many independent
+// streams per step): the per-step plan, the row passes over the planned
+// segments, and the per-stream reductions and small kernels.
+#include "foa_device.h"
+
+namespace foa {
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent streams advanced by one snapshot per step.
+// Every kernel reads the per-stream step state (jstep, act, seg0, nseg)
+// frozen by the plan kernels, so a captured graph of the step replays
+// unchanged while the streams grow.
+//
+// Plan: the active streams are grouped into buckets by basis size (one row-pass
+// instantiation per column-tile width), and within a bucket the concatenation
+// of the streams' panels is cut into G equal contiguous ranges, one per
+// workgroup (G = min(grid, panels / min_seg)).  A workgroup walks the (one or
+// few) streams its range overlaps; its partial sums for a stream go to slot
+// (workgroup - first workgroup on that stream), so each stream's slots are
+// dense and the reductions sum them in a fixed order.  An empty bucket's
+// launch exits at once.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ SmallArgs small_of(const BatchStream &d) {
+  SmallArgs a{};
+  a.st = d.st;
+  a.H = d.H;
+  a.beta = d.beta;
+  a.sigma = d.sigma;
+  a.bvec = d.bvec;
+  a.h = d.h;
+  a.s = d.s;
+  a.coefA = d.coefA;
+  a.coefB = d.coefB;
+  a.coefC = d.coefC;
+  a.part = d.part;
+  a.partn = d.partn;
+  a.ldH = d.ldH;
+  a.ldB = d.ldB;
+  a.n_max = d.n_max;
+  a.G = d.st->nseg;
+  a.ldg = d.ldg;
+  a.j = d.st->jstep;
+  return a;
+}
+
+// bucket of an active stream with basis size j: 0 for the first push, else
+// 1 + log2 of the tile width (in units of cols_per_qw columns, at most 16)
+__device__ __forceinline__ int bucket_of(int j, int cols_per_qw) {
+  if (j == 0) return 0;
+  int k = 1, qw = 1;
+  while (qw < 16 && qw * cols_per_qw < j) {
+    qw *= 2;
+    ++k;
+  }
+  return k;
+}
+
+template <int QW>
+constexpr int bucket_of_qw() {
+  return QW == 1 ? 1 : QW == 2 ? 2 : QW == 4 ? 3 : QW == 8 ? 4 : 5;
+}
+
+// Step state and bucket lists, one workgroup of 1024 threads.  Streams are
+// taken 1024 at a time; per bucket a wavefront prefix sum (count and panels)
+// plus the per-wavefront totals give each active stream its list position
+// and panel offset.
+__global__ __launch_bounds__(1024) void k_batch_plan(BatchArgs b) {
+  __shared__ int s_wcnt[16][NBUCKET];
+  __shared__ int64_t s_wpan[16][NBUCKET];
+  __shared__ int s_cnt[NBUCKET];
+  __shared__ int64_t s_tot[NBUCKET];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid < NBUCKET) {
+    s_cnt[tid] = 0;
+    s_tot[tid] = 0;
+  }
+  __syncthreads();
+  for (int c0 = 0; c0 < b.S; c0 += 1024) {
+    const int s = c0 + tid;
+    int bk = -1;
+    int64_t P = 0;
+    if (s < b.S) {
+      const BatchStream &d = b.streams[s];
+      DevState *st = d.st;
+      const bool offered = b.xptrs[s] != nullptr;
+      const int j = st->q;
+      const bool room = j < d.n_max;
+      const int act = (st->status == ST_ACTIVE && offered && room) ? 1 : 0;
+      st->jstep = j;
+      st->act = act;
+      st->nseg = 0;
+      if (offered && !room && st->status == ST_ACTIVE) st->full = 1;
+      if (act) {
+        bk = bucket_of(j, b.cols_per_qw);
+        P = d.P;
+      }
+    }
+    int myf = 0;
+    int64_t myp = 0;
+#pragma unroll
+    for (int k = 0; k < NBUCKET; ++k) {
+      int f = bk == k ? 1 : 0;
+      int64_t pp = bk == k ? P : 0;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int tf = __shfl_up(f, o, 64);
+        const int64_t tp = __shfl_up(pp, o, 64);
+        if (lane >= o) {
+          f += tf;
+          pp += tp;
+        }
+      }
+      if (bk == k) {
+        myf = f;
+        myp = pp;
+      }
+      if (lane == 63) {
+        s_wcnt[wave][k] = f;
+        s_wpan[wave][k] = pp;
+      }
+    }
+    __syncthreads();
+    if (bk >= 0) {
+      int wb = 0;
+      int64_t wp = 0;
+      for (int w = 0; w < wave; ++w) {
+        wb += s_wcnt[w][bk];
+        wp += s_wpan[w][bk];
+      }
+      const int pos = s_cnt[bk] + wb + myf - 1;
+      b.list[(size_t)bk * b.S + pos] = s;
+      b.pre[(size_t)bk * (b.S + 1) + pos] = s_tot[bk] + wp + myp - P;
+      b.spos[s] = (bk << 24) | pos;
+    }
+    __syncthreads();
+    if (tid < NBUCKET) {
+      int c = 0;
+      int64_t t = 0;
+      for (int w = 0; w < 16; ++w) {
+        c += s_wcnt[w][tid];
+        t += s_wpan[w][tid];
+      }
+      s_cnt[tid] += c;
+      s_tot[tid] += t;
+    }
+    __syncthreads();
+  }
+  if (tid < NBUCKET) {
+    const int c = s_cnt[tid];
+    const int64_t T = s_tot[tid];
+    b.pre[(size_t)tid * (b.S + 1) + c] = T;
+    int G = 0;
+    if (T > 0) {
+      const int64_t g = T / b.min_seg;
+      G = (int)(g < 1 ? 1 : (g > b.grid ? b.grid : g));
+    }
+    b.meta[2 * tid] = c;
+    b.meta[2 * tid + 1] = G;
+  }
+}
+
+// Workgroup g of bucket k covers panels [g T / G, (g + 1) T / G) of the
+// bucket's concatenation; the workgroup holding panel p is
+// ((p + 1) G - 1) / T.  Blocks 0..NBUCKET-1: first stream of every
+// workgroup (binary search in the prefix); the rest: per stream, its first
+// workgroup and the number of workgroups (partial slots) on it.
+__global__ __launch_bounds__(256) void k_batch_plan_ranges(BatchArgs b) {
+  if (blockIdx.x < NBUCKET) {
+    const int k = blockIdx.x;
+    const int cnt = b.meta[2 * k], G = b.meta[2 * k + 1];
+    const int64_t *pre = b.pre + (size_t)k * (b.S + 1);
+    const int64_t T = pre[cnt];
+    for (int g = threadIdx.x; g < G; g += 256) {
+      const int64_t lo = (int64_t)g * T / G;
+      int a = 0, c = cnt - 1;  // largest i with pre[i] <= lo
+      while (a < c) {
+        const int m = (a + c + 1) / 2;
+        if (pre[m] <= lo)
+          a = m;
+        else
+          c = m - 1;
+      }
+      b.first[k * kMaxBatchGrid + g] = a;
+    }
+    return;
+  }
+  const int s = (blockIdx.x - NBUCKET) * 256 + threadIdx.x;
+  if (s >= b.S) return;
+  DevState *st = b.streams[s].st;
+  if (!st->act) return;
+  const int code = b.spos[s];
+  const int k = code >> 24, pos = code & 0xFFFFFF;
+  const int cnt = b.meta[2 * k], G = b.meta[2 * k + 1];
+  const int64_t *pre = b.pre + (size_t)k * (b.S + 1);
+  const int64_t T = pre[cnt];
+  const int64_t p0 = pre[pos], p1 = pre[pos + 1];
+  const int g0 = (int)(((p0 + 1) * G - 1) / T);
+  const int g1 = (int)((p1 * G - 1) / T);
+  st->seg0 = g0;
+  st->nseg = g1 - g0 + 1;
+}
+
+template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
+__global__ __launch_bounds__(NW * 64) void k_pass_batch(BatchArgs b) {
+  constexpr int k = MODE == PM_INIT ? 0 : bucket_of_qw<QW>();
+  const int G = b.meta[2 * k + 1];
+  if ((int)blockIdx.x >= G) return;
+  const int cnt = b.meta[2 * k];
+  const int64_t *pre = b.pre + (size_t)k * (b.S + 1);
+  const int *list = b.list + (size_t)k * b.S;
+  const int64_t T = pre[cnt];
+  int64_t lo = (int64_t)blockIdx.x * T / G;
+  const int64_t hi = (int64_t)(blockIdx.x + 1) * T / G;
+  int i = b.first[k * kMaxBatchGrid + blockIdx.x];
+  while (lo < hi) {
+    const int s = list[i];
+    const int64_t ps = pre[i], pe = pre[i + 1];
+    const int64_t e = pe < hi ? pe : hi;
+    const BatchStream &d = b.streams[s];
+    const DevState *st = d.st;
+    PassArgs a{};
+    a.W = d.W;
+    a.x = b.xptrs[s];
+    a.w = d.w;
+    a.coef = MODE == PM_A ? d.coefA : (MODE == PM_B ? d.coefB : d.coefC);
+    a.st = st;
+    a.part = d.part;
+    a.partn = d.partn;
+    a.n = d.n;
+    a.P = d.P;
+    a.j = st->jstep;
+    a.n_max = d.n_max;
+    a.ldg = d.ldg;
+    row_pass_body<TV, TX, NW, QW, MODE, PREF>(a, lo - ps, e - ps, 1, (int)blockIdx.x - st->seg0);
+    lo = e;
+    ++i;
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_reduce_batch(BatchArgs b) {
+  const int s = b.rblk_stream[blockIdx.x];
+  const BatchStream &d = b.streams[s];
+  if (!d.st->act || d.st->jstep == 0) return;
+  reduce_body<MODE>(small_of(d), b.rblk_c0[blockIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_finalize_batch(BatchArgs b) {
+  const int s = blockIdx.x;
+  const BatchStream &d = b.streams[s];
+  DevState *st = d.st;
+  if (b.xptrs[s] == nullptr) return;  // idle this step
+  if (!st->act) {                      // offered to a stream that no longer takes snapshots
+    if (threadIdx.x == 0) st->pushes += 1;
+    return;
+  }
+  const SmallArgs a = small_of(d);
+  if (st->jstep == 0)
+    finalize_init_body(a);
+  else
+    finalize_body(a);
+}
+
+__global__ __launch_bounds__(256) void k_nextb_batch(BatchArgs b) {
+  const BatchStream &d = b.streams[blockIdx.y];
+  if (!d.st->act) return;
+  if ((int)blockIdx.x * 64 > d.st->q) return;
+  nextb_body(small_of(d), blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_batch_init_states(BatchArgs b, double tol) {
+  init_state_body(small_of(b.streams[blockIdx.y]), tol);
+}
+
+// Tuning inputs: a fixed integer hash (splitmix64 finaliser) of (k, i) mapped
+// to [-1, 1).  Not part of the method.
+__global__ __launch_bounds__(256) void k_fill_random(float *out, int64_t n, uint32_t k) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    uint64_t z = ((uint64_t)k << 40) ^ (uint64_t)i;
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    out[i] = (float)((double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0);
+  }
+}
+
+int batch_cols_per_qw(bool tv_f64) { return tv_f64 ? 16 * 2 : 8 * 4; }
+
+template <typename TV, typename TX, int NW, int MODE, bool PREF>
+static hipError_t launch_batch_q(int qw, int grid, const BatchArgs &b, hipStream_t s) {
+  constexpr int NT = NW * 64;
+  switch (qw) {
+    case 1: hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 1, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b); break;
+    case 2: hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 2, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b); break;
+    case 4: hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 4, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b); break;
+    case 8: hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 8, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b); break;
+    default:
+      if constexpr (sizeof(TV) == 4 || !PREF)
+        hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 16, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b);
+      else
+        return hipErrorInvalidValue;
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <typename TV, typename TX, int NW>
+static hipError_t launch_batch_m(int mode, int qw, int grid, const BatchArgs &b, hipStream_t s) {
+  // FP64 tiles of 16 groups are not double buffered (register budget)
+  const bool pref = !(sizeof(TV) == 8 && qw >= 16);
+  switch (mode) {
+    case PM_INIT: return launch_batch_q<TV, TX, NW, PM_INIT, false>(1, grid, b, s);
+    case PM_A:
+      return pref ? launch_batch_q<TV, TX, NW, PM_A, true>(qw, grid, b, s)
+                  : launch_batch_q<TV, TX, NW, PM_A, false>(qw, grid, b, s);
+    case PM_B:
+      return pref ? launch_batch_q<TV, double, NW, PM_B, true>(qw, grid, b, s)
+                  : launch_batch_q<TV, double, NW, PM_B, false>(qw, grid, b, s);
+    default:
+      return pref ? launch_batch_q<TV, double, NW, PM_C, true>(qw, grid, b, s)
+                  : launch_batch_q<TV, double, NW, PM_C, false>(qw, grid, b, s);
+  }
+}
+
+hipError_t launch_batch_pass(int mode, bool tv_f64, bool tx_f64, int qw, int grid, const BatchArgs &b,
+                             hipStream_t s) {
+  if (tv_f64)
+    return tx_f64 ? launch_batch_m<double, double, 16>(mode, qw, grid, b, s)
+                  : launch_batch_m<double, float, 16>(mode, qw, grid, b, s);
+  return tx_f64 ? launch_batch_m<float, double, 8>(mode, qw, grid, b, s)
+                : launch_batch_m<float, float, 8>(mode, qw, grid, b, s);
+}
+
+hipError_t launch_batch_plan(const BatchArgs &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, s, b);
+  hipLaunchKernelGGL(k_batch_plan_ranges, dim3(NBUCKET + (b.S + 255) / 256), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce(int mode, const BatchArgs &b, hipStream_t s) {
+  if (mode == 1)
+    hipLaunchKernelGGL(k_reduce_batch<1>, dim3(b.n_rblocks), dim3(256), 0, s, b);
+  else
+    hipLaunchKernelGGL(k_reduce_batch<2>, dim3(b.n_rblocks), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const BatchArgs &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize_batch, dim3(b.S), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_nextb(const BatchArgs &b, hipStream_t s) {
+  hipLaunchKernelGGL(k_nextb_batch, dim3((b.max_nmax + 64) / 64, b.S), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_init_states(const BatchArgs &b, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_init_states, dim3(4, b.S), dim3(256), 0, s, b, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_random(float *out, int64_t n, uint32_t k, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_random, dim3(256), dim3(256), 0, s, out, n, k);
+  return hipGetLastError();
+}
+
+}  // namespace foa

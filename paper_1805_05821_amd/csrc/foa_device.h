@@ -1,0 +1,487 @@
+// Device bodies of the FOA push kernels (Algorithm 1 steps 5-18), shared
+// by the single-stream kernels and the batched kernels.
+#pragma once
+
+#include <math.h>
+
+#include "foa_buffer.h"
+#include "foa_internal.h"
+
+namespace foa {
+
+
+template <typename TV>
+struct Vec {
+  static constexpr int EPL = 16 / sizeof(TV);  // rows per lane per 16-byte load
+};
+
+
+__device__ __forceinline__ double xor_shfl(double v, int m) { return __shfl_xor(v, m, 64); }
+
+template <typename T>
+__device__ __forceinline__ double buf_load_scalar(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ double buf_load_scalar<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load_scalar<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store_scalar(T v, __amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ void buf_store_scalar<float>(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void buf_store_scalar<double>(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+
+// Whole-vector bit casts only: casting a single element lvalue of an
+// ext_vector (e.g. __builtin_bit_cast(float, v.y)) reads element 0.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename TV>
+__device__ __forceinline__ void unpack16(const u32x4 &v, TV (&o)[16 / sizeof(TV)]);
+template <>
+__device__ __forceinline__ void unpack16<float>(const u32x4 &v, float (&o)[4]) {
+  const f32x4 f = __builtin_bit_cast(f32x4, v);
+  o[0] = f.x;
+  o[1] = f.y;
+  o[2] = f.z;
+  o[3] = f.w;
+}
+template <>
+__device__ __forceinline__ void unpack16<double>(const u32x4 &v, double (&o)[2]) {
+  const f64x2 d = __builtin_bit_cast(f64x2, v);
+  o[0] = d.x;
+  o[1] = d.y;
+}
+
+// ---------------------------------------------------------------------------
+// Fused row pass.
+//
+// Work decomposition: one workgroup walks panels blockIdx.x, +gridDim.x, ...
+// Within a panel (64 rows x j columns), wavefront `wave` owns column groups
+// g*NW + wave (g < QW); a group is the 1 KiB contiguous block of CPW columns
+// read by one 16-byte load per lane.  Lane l holds rows EPL*(l % LPC) .. +EPL-1
+// of column (group start) + l / LPC.
+//   phase 1 (row sums  u_r = sum_c V_rc coef_c): per-lane FMA over its groups,
+//            butterfly over the lanes sharing rows, then across wavefronts
+//            through LDS in wavefront order;
+//   update  (every wavefront, 64/NW rows each): w_r = (y_r - u_r) * scale;
+//   phase 2 (column sums V^T w): per-lane FP64 accumulators that persist
+//            across panels; one butterfly per column at the end.
+// With PREF the next panel's tile is loaded while the current one is reduced.
+// ---------------------------------------------------------------------------
+// One workgroup processes panels pstart, pstart + pstep, ... < pend of one
+// stream and writes its partial sums to slot `slot`.  Called uniformly by
+// the whole workgroup (it synchronises).
+template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
+__device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart, int64_t pend, int64_t pstep,
+                                              int slot) {
+  constexpr int EPL = Vec<TV>::EPL;
+  constexpr int LPC = 64 / EPL;  // lanes per 64-row column segment
+  constexpr int CPW = EPL;       // columns per wavefront load
+  constexpr int JCAP = QW * NW * CPW;
+  constexpr int RPW = PANEL / NW;  // rows updated by each wavefront
+  constexpr bool HAS_P1 = (MODE != PM_INIT);
+  constexpr bool HAS_P2 = (MODE == PM_A || MODE == PM_B);
+  constexpr bool SRC_X = (MODE == PM_INIT || MODE == PM_A);
+  constexpr int GSTRIDE = NW * CPW;  // columns between a wavefront's groups
+
+  __shared__ double s_coef[JCAP];
+  __shared__ double s_red[2][NW][PANEL];
+  __shared__ double s_w[PANEL];
+  __shared__ double s_nrm[NW];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  // wavefront index made provably uniform so per-wave offsets stay scalar
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int cs = lane / LPC;
+  const int rg = lane % LPC;
+  const int j = a.j;
+
+  __syncthreads();  // the previous call of this workgroup may still read LDS
+  for (int c = tid; c < JCAP; c += NW * 64) s_coef[c] = (c < j) ? a.coef[c] : 0.0;
+  const double scale = (MODE == PM_A) ? a.st->scaleA : 1.0;
+  __syncthreads();
+
+  const int cbase = wave * CPW + cs;  // column of this lane in group 0
+  // byte offset of this lane's 16-byte fragment of group g: goff0 + g * GBYTES
+  const unsigned goff0 = (unsigned)((wave * CPW * PANEL + lane * EPL) * sizeof(TV));
+  constexpr unsigned GBYTES = (unsigned)(GSTRIDE * PANEL * sizeof(TV));
+  const unsigned tile_bytes = (unsigned)(j * PANEL * sizeof(TV));
+  // update rows: lane < RPW owns panel row urow; the others only carry values
+  const bool uact = lane < RPW;
+  const int urow = wave * RPW + (lane % RPW);
+
+  double acc[QW];
+#pragma unroll
+  for (int g = 0; g < QW; ++g) acc[g] = 0.0;
+  double nrm = 0.0;
+
+  const char *Wb = static_cast<const char *>(a.W);
+  const size_t pbytes = (size_t)a.n_max * PANEL * sizeof(TV);
+
+  TV t[QW][EPL];
+  TV tn[QW][EPL];
+
+  // bytes = 0 turns every load into an out-of-range load returning 0 without
+  // memory traffic (used past the last panel, so the loop has no branch
+  // around its loads).
+  auto load_tile = [&](int64_t p, TV (&dst)[QW][EPL], unsigned bytes) {
+    if (!HAS_P1) return;
+    const __amdgpu_buffer_rsrc_t rt = make_rsrc(Wb + (size_t)p * pbytes, bytes);
+#pragma unroll
+    for (int g = 0; g < QW; ++g) {
+      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rt, (int)(goff0 + g * GBYTES), 0, 0);
+      unpack16<TV>(v, dst[g]);
+    }
+  };
+
+  int64_t p = pstart;
+  if (PREF && p < pend) {
+    load_tile(p, t, tile_bytes);
+    // Complete the first tile before the loop: otherwise its pending loads
+    // merge with the loop back edge and every iteration waits for the
+    // prefetched tile before phase 1.
+#pragma unroll
+    for (int g = 0; g < QW; ++g) {
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(t[g][e]));
+    }
+  }
+  int par = 0;
+  for (; p < pend; p += pstep) {
+    // y for the update rows of this wavefront (snapshot or work vector)
+    double y;
+    if (SRC_X) {
+      const int64_t rem = a.n - p * PANEL;
+      const unsigned xb = (unsigned)((rem >= PANEL ? PANEL : (rem > 0 ? rem : 0)) * sizeof(TX));
+      const __amdgpu_buffer_rsrc_t rx = make_rsrc(static_cast<const TX *>(a.x) + p * PANEL, xb);
+      y = buf_load_scalar<TX>(rx, uact ? (unsigned)(urow * sizeof(TX)) : kOOR);
+    } else {
+      const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.w + p * PANEL, PANEL * 8);
+      y = buf_load_scalar<double>(rw, uact ? (unsigned)(urow * 8) : kOOR);
+    }
+    if (PREF) {
+      const bool more = p + pstep < pend;
+      load_tile(more ? p + pstep : p, tn, more ? tile_bytes : 0u);
+    } else {
+      load_tile(p, t, tile_bytes);
+    }
+
+    if (HAS_P1) {
+      double u[EPL];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) u[e] = 0.0;
+#pragma unroll
+      for (int g = 0; g < QW; ++g) {
+        const double cf = s_coef[cbase + g * GSTRIDE];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) u[e] = fma((double)t[g][e], cf, u[e]);
+      }
+#pragma unroll
+      for (int m = LPC; m < 64; m <<= 1) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) u[e] += xor_shfl(u[e], m);
+      }
+      if (cs == 0) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) s_red[par][wave][rg * EPL + e] = u[e];
+      }
+      __syncthreads();
+    }
+    double us = 0.0;
+    if (HAS_P1) {
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) us += s_red[par][w2][urow];
+    }
+    const double wv = (MODE == PM_A) ? (y - us) * scale : (y - us);
+    if (MODE == PM_A || MODE == PM_B) {
+      const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.w + p * PANEL, PANEL * 8);
+      buf_store_scalar<double>(wv, rw, uact ? (unsigned)(urow * 8) : kOOR);
+    }
+    if (MODE == PM_C || MODE == PM_INIT) {
+      const __amdgpu_buffer_rsrc_t rv =
+          make_rsrc(Wb + (size_t)p * pbytes + (size_t)j * PANEL * sizeof(TV), PANEL * sizeof(TV));
+      buf_store_scalar<TV>((TV)wv, rv, uact ? (unsigned)(urow * sizeof(TV)) : kOOR);
+    }
+    if (uact) {
+      if (SRC_X) nrm = fma(y, y, nrm);
+      if (MODE == PM_C) nrm = fma(wv, wv, nrm);
+      if (HAS_P2) s_w[urow] = wv;
+    }
+    if (HAS_P2) {
+      __syncthreads();
+      double wr[EPL];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) wr[e] = s_w[rg * EPL + e];
+      if constexpr (sizeof(TV) == 4) {
+        // Keep only the FP32 tile live across the two phases: convert again
+        // here instead of holding the FP64 copies made in phase 1.
+#pragma unroll
+        for (int g = 0; g < QW; ++g) {
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(t[g][e]));
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < QW; ++g) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) acc[g] = fma((double)t[g][e], wr[e], acc[g]);
+      }
+    }
+    if (PREF) {
+      // The prefetched tile is first needed here: keep the register moves
+      // (and with them the wait for its loads) at the end of the iteration.
+#pragma unroll
+      for (int g = 0; g < QW; ++g) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(tn[g][e]));
+      }
+#pragma unroll
+      for (int g = 0; g < QW; ++g) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) t[g][e] = tn[g][e];
+      }
+    }
+    par ^= 1;
+  }
+
+  if (HAS_P2) {
+#pragma unroll
+    for (int g = 0; g < QW; ++g) {
+      double v = acc[g];
+#pragma unroll
+      for (int m = 1; m < LPC; m <<= 1) v += xor_shfl(v, m);
+      const int c = cbase + g * GSTRIDE;
+      if (rg == 0 && c < j) a.part[(size_t)c * a.ldg + slot] = v;
+    }
+  }
+  if (MODE != PM_B) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) nrm += xor_shfl(nrm, m);
+    if (lane == 0) s_nrm[wave] = nrm;
+    __syncthreads();
+    if (tid == 0) {
+      double t2 = 0.0;
+      for (int w2 = 0; w2 < NW; ++w2) t2 += s_nrm[w2];
+      a.partn[slot] = t2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column reduction of the pass partials, one wavefront per column (fixed order:
+// lane-strided sums, then a butterfly).  MODE 1 (after pass A): h = sigma o t,
+// coefB = sigma o h, and the extra wavefront c == j reduces ||psi||^2.
+// MODE 2 (after pass B): s = sigma o t, h += s (step 13), coefC = sigma o s.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__device__ inline void reduce_body(const SmallArgs &a, int c0) {
+  const int lane = threadIdx.x & 63;
+  const int c = c0 + (threadIdx.x >> 6);
+  if (c < a.j) {
+    const double *pc = a.part + (size_t)c * a.ldg;
+    double t = 0.0;
+    for (int g = lane; g < a.G; g += 64) t += pc[g];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) t += xor_shfl(t, m);
+    if (lane == 0) {
+      const double sg = a.sigma[c];
+      const double v = sg * t;
+      if (MODE == 1) {
+        a.h[c] = v;
+        a.coefB[c] = sg * v;
+      } else {
+        a.s[c] = v;
+        a.h[c] = a.h[c] + v;
+        a.coefC[c] = sg * v;
+      }
+    }
+  } else if (MODE == 1 && c == a.j) {
+    double t = 0.0;
+    for (int g = lane; g < a.G; g += 64) t += a.partn[g];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) t += xor_shfl(t, m);
+    if (lane == 0) a.st->xn2 = t;
+  }
+}
+
+__device__ inline double block_sum_256(double t, double *sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = t;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] = sh[tid] + sh[tid + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Steps 15-18 plus the breakdown rule; single workgroup.
+__device__ inline void finalize_body(const SmallArgs &a) {
+  __shared__ double sh[256];
+  __shared__ int s_status;
+  DevState *st = a.st;
+  const int tid = threadIdx.x;
+  if (st->status != ST_ACTIVE) {
+    if (tid == 0) st->pushes += 1;
+    return;
+  }
+  const int j = a.j;
+  double t = 0.0;
+  for (int g = tid; g < a.G; g += 256) t += a.partn[g];
+  const double wn2 = block_sum_256(t, sh);
+  int bad = 0;
+  for (int i = tid; i < j; i += 256) bad |= !isfinite(a.h[i]);
+  bad = __syncthreads_or(bad);
+  const double bjj = a.beta[(size_t)(j - 1) * a.ldB + (j - 1)];
+  if (tid == 0) {
+    const double hn = sqrt(wn2);
+    const double xn2 = st->xn2;
+    int status = ST_ACTIVE;
+    if (bad || !isfinite(hn) || !isfinite(xn2)) {
+      status = ST_NONFINITE;
+    } else {
+      const double xf = st->xfro2 + xn2;
+      st->xfro2 = xf;
+      st->hlast = hn;
+      if (hn * bjj <= st->tol * sqrt(xf)) status = ST_INVARIANT;
+    }
+    s_status = status;
+  }
+  __syncthreads();
+  const int status = s_status;
+  if (status == ST_NONFINITE) {
+    if (tid == 0) {
+      st->status = ST_NONFINITE;
+      st->pushes += 1;
+    }
+    return;
+  }
+  for (int i = tid; i < j; i += 256) {
+    const double hi = a.h[i];
+    a.H[(size_t)(j - 1) * a.ldH + i] = hi;
+    a.beta[(size_t)j * a.ldB + i] = a.bvec[i] + hi * bjj;  // steps 16-18
+  }
+  if (tid == 0) {
+    if (status == ST_INVARIANT) {
+      a.H[(size_t)(j - 1) * a.ldH + j] = 0.0;
+      a.beta[(size_t)j * a.ldB + j] = 0.0;
+      st->status = ST_INVARIANT;
+    } else {
+      const double hn = st->hlast;
+      a.H[(size_t)(j - 1) * a.ldH + j] = hn;
+      a.beta[(size_t)j * a.ldB + j] = hn * bjj;
+      a.sigma[j] = 1.0 / hn;
+      st->q = j + 1;
+    }
+    st->pushes += 1;
+  }
+}
+
+// Steps 2-3 for the first snapshot.
+__device__ inline void finalize_init_body(const SmallArgs &a) {
+  __shared__ double sh[256];
+  DevState *st = a.st;
+  const int tid = threadIdx.x;
+  if (st->status != ST_ACTIVE) {
+    if (tid == 0) st->pushes += 1;
+    return;
+  }
+  double t = 0.0;
+  for (int g = tid; g < a.G; g += 256) t += a.partn[g];
+  const double xn2 = block_sum_256(t, sh);
+  if (tid == 0) {
+    const double b11 = sqrt(xn2);
+    if (!isfinite(b11)) {
+      st->status = ST_NONFINITE;
+    } else if (b11 == 0.0) {
+      st->status = ST_ZERO;
+    } else {
+      a.beta[0] = b11;
+      a.sigma[0] = 1.0 / b11;
+      st->xfro2 = xn2;
+      st->q = 1;
+    }
+    st->pushes += 1;
+  }
+}
+
+// Steps 5-8 for the next push (J = q basis vectors):
+//   b_i = sum_{l = max(1, i-1)}^{J-1} h_{i,l} beta_{l,J}  (1-based), i = 1..J,
+// computed as 64 rows x 4 contiguous l-slices per block, slices combined in
+// order.  Also coefA = sigma o b and scaleA = 1 / beta_{J,J}.
+__device__ inline void nextb_body(const SmallArgs &a, int chunk) {
+  __shared__ double sh[4][64];
+  DevState *st = a.st;
+  if (st->status != ST_ACTIVE) return;
+  const int J = st->q;
+  const int r = threadIdx.x & 63;
+  const int sl = threadIdx.x >> 6;
+  const int i = chunk * 64 + r;  // 0-based row
+  double t = 0.0;
+  if (i < J) {
+    const int lo = i > 0 ? i - 1 : 0;
+    const int hi = J - 1;  // exclusive upper bound (columns 0..J-2)
+    const int len = hi > lo ? hi - lo : 0;
+    const int a0 = lo + (len * sl) / 4;
+    const int a1 = lo + (len * (sl + 1)) / 4;
+    const double *bc = a.beta + (size_t)(J - 1) * a.ldB;
+    for (int l = a0; l < a1; ++l) t = fma(a.H[(size_t)l * a.ldH + i], bc[l], t);
+  }
+  sh[sl][r] = t;
+  __syncthreads();
+  if (sl == 0 && i < J) {
+    const double b = ((sh[0][r] + sh[1][r]) + sh[2][r]) + sh[3][r];
+    a.bvec[i] = b;
+    a.coefA[i] = a.sigma[i] * b;
+  }
+  if (chunk == 0 && threadIdx.x == 0) st->scaleA = 1.0 / a.beta[(size_t)(J - 1) * a.ldB + (J - 1)];
+}
+
+// Reset of one stream: scalar state, and zeros in every small array (the
+// entries of H_bar below the subdiagonal and of beta below the diagonal are
+// never written by the push kernels and must read as zero).
+__device__ inline void init_state_body(const SmallArgs &a, double tol) {
+  const size_t nH = (size_t)a.ldH * (a.n_max + 1), nB = (size_t)a.ldB * (a.n_max + 1);
+  const size_t nv = (size_t)a.n_max + 1;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nH; i += stride) a.H[i] = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nB; i += stride) a.beta[i] = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+    a.sigma[i] = 0.0;
+    a.bvec[i] = 0.0;
+    a.h[i] = 0.0;
+    a.s[i] = 0.0;
+    a.coefA[i] = 0.0;
+    a.coefB[i] = 0.0;
+    a.coefC[i] = 0.0;
+  }
+  DevState *st = a.st;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->q = 0;
+    st->status = ST_ACTIVE;
+    st->pushes = 0;
+    st->jstep = 0;
+    st->act = 0;
+    st->full = 0;
+    st->xfro2 = 0.0;
+    st->xn2 = 0.0;
+    st->scaleA = 0.0;
+    st->tol = tol;
+    st->hlast = 0.0;
+  }
+}
+
+}  // namespace foa

@@ -32,7 +32,9 @@ struct DevState {
   double scaleA;  // 1 / beta_{q,q}: scale of step 9 for the next push
   double tol;     // breakdown tolerance (relative to ||X||_F)
   double hlast;   // last h_{j+1,j}
-  double pad1[2];
+  int nseg;       // batched form: partial-sum slots written by this step's passes
+  int seg0;       // batched form: first workgroup of this step's passes on the stream
+  double pad1;
 };
 
 // Pass modes of the fused row kernel.
@@ -88,21 +90,29 @@ struct BatchStream {
   double *H, *beta, *sigma, *bvec, *h, *s, *coefA, *coefB, *coefC;
   int64_t n, P;
   int n_max, ldg, ldH, ldB;
-  int nslot;  // partial-sum slots in use (units of this stream)
-  int pad;
 };
-// Work unit: panels [p0, p1) of stream s; partial sums go to slot `slot`.
-struct BatchUnit {
-  int s, slot;
-  int64_t p0, p1;
-};
+// Buckets of the per-step plan: 0 = first push of a stream (basis empty);
+// 1 + log2(QW) = basis size in the column-tile range of tile width QW.
+constexpr int NBUCKET = 6;
+constexpr int kMaxBatchGrid = 4096;
+// Per-step plan (device memory, rebuilt by the plan kernels every step): for
+// bucket k, the active streams in stream order with their panel prefix sums,
+// the number of workgroups that share the bucket's panels, and for each of
+// them the list position of its first stream.
 struct BatchArgs {
   const BatchStream *streams;
-  const BatchUnit *units;
   const void *const *xptrs;  // device array of S snapshot pointers (NULL: idle)
   const int *rblk_stream;    // reduce blocks: stream of block b
   const int *rblk_c0;        // reduce blocks: first column of block b
-  int S, n_units, n_rblocks, max_nmax;
+  int *list;                 // NBUCKET x S
+  int64_t *pre;              // NBUCKET x (S + 1)
+  int *first;                // NBUCKET x kMaxBatchGrid
+  int *meta;                 // NBUCKET x 2: streams in the bucket, workgroups in use
+  int *spos;                 // S: bucket (high 8 bits) and list position of each active stream
+  int S, n_rblocks, max_nmax;
+  int cols_per_qw;           // basis columns per unit of tile width
+  int grid;                  // workgroups of every batched row-pass launch
+  int min_seg;               // fewest panels per workgroup
 };
 
 // ---- launchers (defined in foa_kernels.hip) --------------------------------
@@ -134,7 +144,7 @@ hipError_t launch_modes_gemm(bool tv_f64, const void *W, int64_t n, int n_max, i
 int pick_qw(int j, int cols_per_qw);
 
 // batched form (one call per kernel of a step; all captured in one graph)
-hipError_t launch_batch_begin(const BatchArgs &b, hipStream_t s);
+hipError_t launch_batch_plan(const BatchArgs &b, hipStream_t s);
 hipError_t launch_batch_pass(int mode, bool tv_f64, bool tx_f64, int qw, int grid, const BatchArgs &b,
                              hipStream_t s);
 hipError_t launch_batch_reduce(int mode, const BatchArgs &b, hipStream_t s);
