@@ -120,8 +120,21 @@ foa_status map_status(int s) {
   }
 }
 
-int pass_grid(const foa_ctx_s *c) {
-  int g = c->grid_opt > 0 ? c->grid_opt : c->grid_auto;
+// Row-pass grid of a push at basis size j: the "grid" option if set, else
+// one full complement of resident workgroups for the pass kernel at this tile
+// width (at least grid_auto); bounded by the partial-sum slots and the panels.
+int pass_grid(foa_ctx_s *c, int j, bool x_f64) {
+  int g = c->grid_opt;
+  if (g <= 0) {
+    const bool v64 = c->prec == FOA_PREC_F64;
+    const int cols = v64 ? 32 : c->nw * 4;
+    const int qw = pick_qw(j > 0 ? j : 1, cols);
+    int qi = 0;
+    while ((1 << qi) < qw) ++qi;
+    int &occ = c->occ_cache[x_f64 ? 1 : 0][qi];
+    if (occ <= 0) occ = pass_occupancy(v64, x_f64, c->prefetch, c->nw, qw);
+    g = std::max(c->grid_auto, occ * c->cus);
+  }
   if (g > kMaxGrid) g = kMaxGrid;
   if ((int64_t)g > c->L.P) g = (int)c->L.P;
   return g < 1 ? 1 : g;
@@ -191,7 +204,7 @@ void release_events(foa_ctx_s *c) {
 foa_status enqueue_push(foa_ctx_s *c, const void *x, bool x_f64) {
   const bool v64 = c->prec == FOA_PREC_F64;
   const int j = c->q_host;
-  const int G = pass_grid(c);
+  const int G = pass_grid(c, j, x_f64);
   PassArgs pa{};
   pa.W = c->W;
   pa.x = x;
@@ -368,11 +381,13 @@ foa_status foa_set_option(foa_ctx c, const char *key, int64_t value) {
   }
   if (!std::strcmp(key, "prefetch")) {
     c->prefetch = value != 0;
+    std::memset(c->occ_cache, 0, sizeof c->occ_cache);
     return FOA_OK;
   }
   if (!std::strcmp(key, "nw")) {
     if (value != 8 && value != 16) return set_err(c, FOA_E_ARG, "nw must be 8 or 16");
     c->nw = (int)value;
+    std::memset(c->occ_cache, 0, sizeof c->occ_cache);
     return FOA_OK;
   }
   if (!std::strcmp(key, "profile")) {

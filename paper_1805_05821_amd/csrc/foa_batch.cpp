@@ -97,6 +97,7 @@ struct foa_batch_s {
   std::vector<foa_ctx_s *> views;
   BatchArgs args{};
   int unit_panels = 16, grid = 0;
+  int occ[NBUCKET] = {};  // resident row-pass workgroups per CU, per bucket
   double tuned_ms = 0.0;
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -136,7 +137,12 @@ foa_status upload_config(foa_batch_s *b, int unit_panels) {
   if (e != hipSuccess) return FOA_E_DEVICE;
   b->unit_panels = unit_panels;
   b->args.min_seg = unit_panels;
-  b->args.grid = b->grid;
+  // every bucket gets at least the tuned grid, and at least one workgroup
+  // per resident slot of its kernel
+  for (int k = 0; k < NBUCKET; ++k) {
+    if (b->occ[k] <= 0) b->occ[k] = batch_pass_occupancy(b->prec == FOA_PREC_F64, k);
+    b->args.gridb[k] = std::min(kMaxBatchGrid, std::max(b->grid, b->occ[k] * b->cus));
+  }
   return FOA_OK;
 }
 
@@ -148,15 +154,15 @@ hipError_t enqueue_step(foa_batch_s *b, bool x_f64, hipStream_t s) {
   const BatchArgs &a = b->args;
   hipError_t e;
   if ((e = launch_batch_plan(a, s)) != hipSuccess) return e;
-  if ((e = launch_batch_pass(PM_INIT, v64, x_f64, 1, b->grid, a, s)) != hipSuccess) return e;
-  for (int qw = 1; qw <= qmax; qw *= 2)
-    if ((e = launch_batch_pass(PM_A, v64, x_f64, qw, b->grid, a, s)) != hipSuccess) return e;
+  if ((e = launch_batch_pass(PM_INIT, v64, x_f64, 1, a.gridb[0], a, s)) != hipSuccess) return e;
+  for (int qw = 1, k = 1; qw <= qmax; qw *= 2, ++k)
+    if ((e = launch_batch_pass(PM_A, v64, x_f64, qw, a.gridb[k], a, s)) != hipSuccess) return e;
   if ((e = launch_batch_reduce(1, a, s)) != hipSuccess) return e;
-  for (int qw = 1; qw <= qmax; qw *= 2)
-    if ((e = launch_batch_pass(PM_B, v64, true, qw, b->grid, a, s)) != hipSuccess) return e;
+  for (int qw = 1, k = 1; qw <= qmax; qw *= 2, ++k)
+    if ((e = launch_batch_pass(PM_B, v64, true, qw, a.gridb[k], a, s)) != hipSuccess) return e;
   if ((e = launch_batch_reduce(2, a, s)) != hipSuccess) return e;
-  for (int qw = 1; qw <= qmax; qw *= 2)
-    if ((e = launch_batch_pass(PM_C, v64, true, qw, b->grid, a, s)) != hipSuccess) return e;
+  for (int qw = 1, k = 1; qw <= qmax; qw *= 2, ++k)
+    if ((e = launch_batch_pass(PM_C, v64, true, qw, a.gridb[k], a, s)) != hipSuccess) return e;
   if ((e = launch_batch_finalize(a, s)) != hipSuccess) return e;
   return launch_batch_nextb(a, s);
 }

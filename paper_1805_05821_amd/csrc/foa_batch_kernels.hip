@@ -152,7 +152,7 @@ __global__ __launch_bounds__(1024) void k_batch_plan(BatchArgs b) {
     int G = 0;
     if (T > 0) {
       const int64_t g = T / b.min_seg;
-      G = (int)(g < 1 ? 1 : (g > b.grid ? b.grid : g));
+      G = (int)(g < 1 ? 1 : (g > b.gridb[tid] ? b.gridb[tid] : g));
     }
     b.meta[2 * tid] = c;
     b.meta[2 * tid + 1] = G;
@@ -321,6 +321,31 @@ static hipError_t launch_batch_m(int mode, int qw, int grid, const BatchArgs &b,
       return pref ? launch_batch_q<TV, double, NW, PM_C, true>(qw, grid, b, s)
                   : launch_batch_q<TV, double, NW, PM_C, false>(qw, grid, b, s);
   }
+}
+
+template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
+static int occ_batch() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void *>(&k_pass_batch<TV, TX, NW, QW, MODE, PREF>), NW * 64, 0) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+template <typename TV, int NW>
+static int occ_batch_k(int k) {
+  switch (k) {
+    case 0: return occ_batch<TV, float, NW, 1, PM_INIT, false>();
+    case 1: return occ_batch<TV, float, NW, 1, PM_A, true>();
+    case 2: return occ_batch<TV, float, NW, 2, PM_A, true>();
+    case 3: return occ_batch<TV, float, NW, 4, PM_A, true>();
+    case 4: return occ_batch<TV, float, NW, 8, PM_A, true>();
+    default: return occ_batch<TV, float, NW, 16, PM_A, sizeof(TV) == 4>();
+  }
+}
+
+int batch_pass_occupancy(bool tv_f64, int k) {
+  return tv_f64 ? occ_batch_k<double, 16>(k) : occ_batch_k<float, 8>(k);
 }
 
 hipError_t launch_batch_pass(int mode, bool tv_f64, bool tx_f64, int qw, int grid, const BatchArgs &b,

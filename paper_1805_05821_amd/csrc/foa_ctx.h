@@ -56,6 +56,7 @@ struct foa_ctx_s {
   foa::SmallArgs sa{};
   // launch configuration
   int grid_auto = 0, grid_opt = 0;
+  int occ_cache[2][5] = {};  // resident pass-A workgroups per CU [x_f64][log2 qw]
   bool prefetch = false;
   int nw = 16;  // wavefronts per row-pass workgroup (FP32 basis: 8 or 16)
   double tol = 0.0;
@@ -94,7 +95,7 @@ foa_status refresh_mirror(foa_ctx_s *c);
 foa_status reset_device_state(foa_ctx_s *c);
 foa_status enqueue_push(foa_ctx_s *c, const void *x, bool x_f64);
 int projected_order(const foa_ctx_s *c);
-int pass_grid(const foa_ctx_s *c);
+int pass_grid(foa_ctx_s *c, int j, bool x_f64);
 foa_status collect_profile(foa_ctx_s *c);
 void release_events(foa_ctx_s *c);
 hipEvent_t take_event(foa_ctx_s *c);

@@ -18,6 +18,30 @@ struct Vec {
 
 __device__ __forceinline__ double xor_shfl(double v, int m) { return __shfl_xor(v, m, 64); }
 
+// v(lane) + v(lane ^ M) for M = 16 or 32 with the lane-swap VALU instructions
+// (no LDS traffic).  With both operands equal, the 32-swap returns the lower
+// half of the wave in both halves of one result and the upper half in both
+// halves of the other (16-swap: rows 0,0,2,2 and 1,1,3,3), so the sum of the
+// two results is the butterfly sum in every lane, identical in both partners.
+template <int M>
+__device__ __forceinline__ double xor_sum(double v) {
+  static_assert(M == 16 || M == 32, "lane-swap butterfly distance");
+  const u32x2 b = __builtin_bit_cast(u32x2, v);
+  u32x2 p, q;
+  if constexpr (M == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(b.x, b.x, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(b.y, b.y, false, false);
+    p = u32x2{lo[0], hi[0]};
+    q = u32x2{lo[1], hi[1]};
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap(b.x, b.x, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(b.y, b.y, false, false);
+    p = u32x2{lo[0], hi[0]};
+    q = u32x2{lo[1], hi[1]};
+  }
+  return __builtin_bit_cast(double, p) + __builtin_bit_cast(double, q);
+}
+
 template <typename T>
 __device__ __forceinline__ double buf_load_scalar(__amdgpu_buffer_rsrc_t r, unsigned off);
 template <>
@@ -86,6 +110,7 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
                                               int slot) {
   constexpr int EPL = Vec<TV>::EPL;
   constexpr int LPC = 64 / EPL;  // lanes per 64-row column segment
+  static_assert(LPC == 16 || LPC == 32, "16-byte fragments of FP32 or FP64");
   constexpr int CPW = EPL;       // columns per wavefront load
   constexpr int JCAP = QW * NW * CPW;
   constexpr int RPW = PANEL / NW;  // rows updated by each wavefront
@@ -187,11 +212,13 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
 #pragma unroll
         for (int e = 0; e < EPL; ++e) u[e] = fma((double)t[g][e], cf, u[e]);
       }
+      // butterfly over the lanes sharing rows (distances LPC .. 32)
+      if constexpr (LPC <= 16) {
 #pragma unroll
-      for (int m = LPC; m < 64; m <<= 1) {
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) u[e] += xor_shfl(u[e], m);
+        for (int e = 0; e < EPL; ++e) u[e] = xor_sum<16>(u[e]);
       }
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) u[e] = xor_sum<32>(u[e]);
       if (cs == 0) {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) s_red[par][wave][rg * EPL + e] = u[e];

@@ -111,7 +111,7 @@ struct BatchArgs {
   int *spos;                 // S: bucket (high 8 bits) and list position of each active stream
   int S, n_rblocks, max_nmax;
   int cols_per_qw;           // basis columns per unit of tile width
-  int grid;                  // workgroups of every batched row-pass launch
+  int gridb[NBUCKET];        // workgroups of the row-pass launches of bucket k
   int min_seg;               // fewest panels per workgroup
 };
 
@@ -120,6 +120,8 @@ struct BatchArgs {
 // nw: wavefronts per workgroup for an FP32 basis (8 or 16; FP64 uses 16).
 hipError_t launch_pass(int mode, bool tv_f64, bool tx_f64, bool prefetch, int nw, int grid,
                        const PassArgs &a, hipStream_t s);
+// resident workgroups per CU of the row-pass kernel used at tile width qw
+int pass_occupancy(bool tv_f64, bool tx_f64, bool prefetch, int nw, int qw);
 hipError_t launch_reduce(int mode, const SmallArgs &a, hipStream_t s);
 hipError_t launch_finalize(const SmallArgs &a, hipStream_t s);
 hipError_t launch_finalize_init(const SmallArgs &a, hipStream_t s);
@@ -154,5 +156,7 @@ hipError_t launch_batch_init_states(const BatchArgs &b, double tol, hipStream_t 
 // fills out[0..n) with a deterministic pseudo-random sequence of tuning input k
 hipError_t launch_fill_random(float *out, int64_t n, uint32_t k, hipStream_t s);
 int batch_cols_per_qw(bool tv_f64);
+// resident workgroups per CU of the batched row-pass kernel of bucket k
+int batch_pass_occupancy(bool tv_f64, int k);
 
 }  // namespace foa

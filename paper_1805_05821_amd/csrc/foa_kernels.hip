@@ -130,6 +130,37 @@ hipError_t launch_pass(int mode, bool tv_f64, bool tx_f64, bool prefetch, int nw
                 : launch_pass_m<float, float, 16>(mode, prefetch, grid, a, s);
 }
 
+// Resident workgroups per CU of the pass-A kernel for tile width qw (the
+// widest register footprint of the three passes at that width).
+template <typename TV, typename TX, int NW, int QW>
+static int occ_q(bool pref) {
+  int nb = 0;
+  const void *f = pref ? reinterpret_cast<const void *>(&k_pass<TV, TX, NW, QW, PM_A, true>)
+                       : reinterpret_cast<const void *>(&k_pass<TV, TX, NW, QW, PM_A, false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, NW * 64, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+template <typename TV, typename TX, int NW>
+static int occ_m(int qw, bool pref) {
+  pref = pref && prefetch_fits<TV, NW>(qw);
+  switch (qw) {
+    case 1: return occ_q<TV, TX, NW, 1>(pref);
+    case 2: return occ_q<TV, TX, NW, 2>(pref);
+    case 4: return occ_q<TV, TX, NW, 4>(pref);
+    case 8: return occ_q<TV, TX, NW, 8>(pref);
+    default:
+      if constexpr (NW * 16 * Vec<TV>::EPL <= 512) return occ_q<TV, TX, NW, 16>(pref);
+      return 1;
+  }
+}
+
+int pass_occupancy(bool tv_f64, bool tx_f64, bool prefetch, int nw, int qw) {
+  if (tv_f64) return tx_f64 ? occ_m<double, double, 16>(qw, prefetch) : occ_m<double, float, 16>(qw, prefetch);
+  if (nw == 8) return tx_f64 ? occ_m<float, double, 8>(qw, prefetch) : occ_m<float, float, 8>(qw, prefetch);
+  return tx_f64 ? occ_m<float, double, 16>(qw, prefetch) : occ_m<float, float, 16>(qw, prefetch);
+}
+
 hipError_t launch_reduce(int mode, const SmallArgs &a, hipStream_t s) {
   const int waves = a.j + (mode == 1 ? 1 : 0);
   const int blocks = (waves + 3) / 4;
