@@ -233,12 +233,10 @@ def traffic_from_profiles(kind):
     path = os.path.join(ROOT, "profiles", "row_pass_traffic.json")
     if not os.path.exists(path):
         return None
-    import hashlib
+    from paper_1805_05821_amd.rocprof_summary import row_pass_source_digest
 
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_1805_05821_amd", "csrc", "foa_kernels.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("kernel_source_sha256") != digest:
+    if rec.get("kernel_source_sha256") != row_pass_source_digest():
         return None
     return rec.get(kind)
 

@@ -96,6 +96,14 @@ foa_status foa_init(foa_ctx *ctx, int64_t n, int32_t n_max, foa_prec prec, void 
  * breakdown are ignored on the device). */
 foa_status foa_push_snapshot(foa_ctx ctx, const void *d_x, foa_dtype x_dtype);
 
+/* In-place fill target for the next snapshot (the memory note of Appendix
+ * A.1: a new snapshot may occupy storage the method already holds): *d_col receives a device buffer of n FP64 entries inside the
+ * workspace (the push's work vector).  Fill it on the context's stream after
+ * the previous push, then call foa_push_snapshot(ctx, *d_col, FOA_F64); the
+ * first pass reads each row before it overwrites that row, so the snapshot
+ * needs no storage of its own.  The contents are overwritten by every push. */
+foa_status foa_next_column(foa_ctx ctx, void **d_col);
+
 /* Push p snapshots stored as columns of a device matrix (column j at
  * d_X + j*ld elements), processed in order exactly as p single pushes
  * (Algorithm 4 with p > 1, Section 3.1). */

@@ -491,6 +491,12 @@ foa_status foa_profile(foa_ctx c, double out[3]) {
   return FOA_OK;
 }
 
+foa_status foa_next_column(foa_ctx c, void **d_col) {
+  if (!c || !d_col) return FOA_E_ARG;
+  *d_col = c->w;
+  return FOA_OK;
+}
+
 foa_status foa_profile_modes(foa_ctx c, double out[3]) {
   if (!c || !out) return FOA_E_ARG;
   hipError_t e = hipStreamSynchronize(c->stream);

@@ -35,7 +35,7 @@ EXPORTED = [
     "foa_workspace_bytes", "foa_init", "foa_push_snapshot", "foa_push_block", "foa_sync",
     "foa_get_state", "foa_copy_basis", "foa_copy_basis_rows", "foa_truncate", "foa_modes", "foa_indicators",
     "foa_reset", "foa_destroy", "foa_status_str", "foa_last_error", "foa_set_option", "foa_profile",
-    "foa_profile_modes",
+    "foa_profile_modes", "foa_next_column",
     "foa_batch_workspace_bytes", "foa_batch_init", "foa_batch_push", "foa_batch_sync",
     "foa_batch_view", "foa_batch_reset", "foa_batch_destroy",
 ]
@@ -80,6 +80,7 @@ def _load():
         "foa_set_option": [P, c.c_char_p, i64],
         "foa_profile": [P, P],
         "foa_profile_modes": [P, P],
+        "foa_next_column": [P, P],
         "foa_batch_workspace_bytes": [i32, P, P, c.c_int, c.POINTER(sz)],
         "foa_batch_init": [c.POINTER(P), i32, P, P, c.c_int, P, sz, P, f64, c.c_char_p],
         "foa_batch_push": [P, P, c.c_int],
@@ -250,6 +251,13 @@ def foa_profile_modes(ctx):
     out = np.zeros(3, dtype=np.float64)
     _check(lib.foa_profile_modes(ctx, _host(out)), ctx)
     return int(out[0]), float(out[1]), float(out[2])
+
+
+def foa_next_column(ctx):
+    """Device address of the in-place snapshot buffer (n FP64 entries)."""
+    out = ctypes.c_void_p()
+    _check(lib.foa_next_column(ctx, ctypes.byref(out)), ctx)
+    return int(out.value)
 
 
 def foa_last_error(ctx):

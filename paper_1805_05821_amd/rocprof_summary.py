@@ -3,6 +3,10 @@
   python -m paper_1805_05821_amd.rocprof_summary kernels DIR
       per-kernel statistics (from *kernel_stats.csv) plus the aggregate of the
       fused row-pass kernels (all k_pass instances).
+  python -m paper_1805_05821_amd.rocprof_summary window DIR PREFIX START COUNT
+      average duration of the dispatches START .. START+COUNT-1 (time order)
+      of the kernels whose name starts with PREFIX (from *kernel_trace.csv):
+      picks one run out of a trace that holds several.
   python -m paper_1805_05821_amd.rocprof_summary counter DIR COUNTER
       average value of COUNTER per dispatch for the row-pass kernels and for
       the copy kernel of a calibration run (from *counter_collection.csv).
@@ -116,8 +120,23 @@ def _row_pass_avg(d, counter):
     return v / max(n, 1), n
 
 
-def traffic(fetch_dir, write_dir, fetch_copy, write_copy, copy_bytes, bench_log, out_json):
+ROW_PASS_SOURCES = ("foa_buffer.h", "foa_device.h", "foa_kernels.hip")
+
+
+def row_pass_source_digest():
+    """SHA-256 over the sources that define the single-stream row-pass
+    kernels; a stored traffic measurement applies only while it matches."""
     import hashlib
+
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for name in ROW_PASS_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic(fetch_dir, write_dir, fetch_copy, write_copy, copy_bytes, bench_log, out_json):
     import json
 
     copy_bytes = float(copy_bytes)
@@ -133,10 +152,9 @@ def traffic(fetch_dir, write_dir, fetch_copy, write_copy, copy_bytes, bench_log,
     alg = bench["roofline"]["alg_bytes_per_launch"] if bench else None
     fetch_b = f_avg * f_scale
     write_b = w_avg * w_scale
-    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    src = os.path.join(root, "paper_1805_05821_amd", "csrc", "foa_kernels.hip")
     rec = {
-        "kernel_source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+        "kernel_source_sha256": row_pass_source_digest(),
+        "kernel_sources": list(ROW_PASS_SOURCES),
         "f32": {
             "traffic_bytes_per_launch": fetch_b + write_b,
             "fetch_bytes_per_launch": fetch_b,
@@ -153,9 +171,27 @@ def traffic(fetch_dir, write_dir, fetch_copy, write_copy, copy_bytes, bench_log,
     return rec
 
 
+def window(d, prefix, start, count):
+    """Average duration of dispatches [start, start + count) in time order
+    among the kernels whose name starts with prefix."""
+    rows = []
+    for path in _find(d, "kernel_trace.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if _col(r, "Kernel_Name", "Kernel-Name").startswith(prefix):
+                    rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    rows.sort()
+    sel = rows[int(start):int(start) + int(count)]
+    ms = [(b - a) / 1e6 for a, b in sel]
+    return (f"{prefix}*: dispatches {start}..{int(start) + len(sel) - 1} of {len(rows)} in time order: "
+            f"{len(sel)} dispatches, total {sum(ms):.2f} ms, average {sum(ms) / max(len(ms), 1):.4f} ms")
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "kernels":
         print(summarize_kernels(argv[1]))
+    elif len(argv) >= 5 and argv[0] == "window":
+        print(window(argv[1], argv[2], argv[3], argv[4]))
     elif len(argv) >= 3 and argv[0] == "counter":
         print(summarize_counter(argv[1], argv[2]))
     elif len(argv) >= 8 and argv[0] == "traffic":

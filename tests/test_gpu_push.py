@@ -163,6 +163,35 @@ def test_block_push_equals_single_pushes():
     assert np.array_equal(a["H"], b["H"]) and np.array_equal(a["beta"], b["beta"])
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_next_column_in_place(prec):
+    """Snapshots written into the in-place buffer give bitwise the same state
+    as pushes from a separate FP64 array (ragged n, several panels)."""
+    import torch
+
+    from paper_1805_05821_amd import foa as F
+    from paper_1805_05821_amd.stream import FOAStream
+
+    X = _noisy(5000 + 37, 24)
+    ref = run_gpu(X, prec)
+    s = FOAStream(X.shape[0], X.shape[1], prec=prec, ws_fill=0xFF)
+    addr = F.foa_next_column(s.ctx)
+    assert addr % 8 == 0
+    # a tensor view of the buffer, through the workspace tensor that holds it
+    off = addr - s.ws.data_ptr()
+    assert 0 <= off and off + 8 * X.shape[0] <= s.ws.numel()
+    col = s.ws[off:off + 8 * X.shape[0]].view(torch.float64)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+    for k in range(X.shape[1]):
+        col.copy_(Xd[k])
+        F.foa_push_snapshot(s.ctx, addr, F.FOA_F64)
+    st, q = s.sync()
+    H, B, q2, m = s.state()
+    assert q == ref["q"]
+    assert np.array_equal(H, ref["H"]) and np.array_equal(B, ref["beta"])
+    s.close()
+
+
 def test_zero_first_snapshot():
     X = _noisy(500, 5)
     X[:, 0] = 0.0
