@@ -1,0 +1,205 @@
+"""Pins of the blocked oracle (oracle/blocked.py) against facts it does not
+define: the sequential oracle (itself pinned), Householder QR, orthogonality,
+the factorisation residual, exact-rank recovery with the breakdown rule, and
+the O(eps kappa) growth of the projection error (Section 3.2.2).  Planted
+mistakes must fail at least one of them."""
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle.blocked as ob
+import oracle.foa as ofoa
+from pins import _krylov, match_eigs
+
+EPS64 = 2.0 ** -52
+
+
+def _noisy(n=3000, N=61, name="noisy_2p20x200"):
+    w = datagen.get_workload(name).with_n(n).with_N(N)
+    X, lam, b = datagen.snapshots_numpy(w, dtype="float64")
+    return X
+
+
+def pin_matches_sequential(B):
+    """Same factors as the sequential oracle within O(q eps kappa)."""
+    out = []
+    for name, n in (("noisy_2p20x200", 3000), ("noisy_2p24x500", 20000)):
+        X = _noisy(n, 61, name)
+        a = ofoa.foa_batch(X)
+        b = B.foa_blocked(X)
+        q, m = a.q, a.q - 1
+        kap = np.linalg.cond(a.beta[:m, :m])
+        eH = np.linalg.norm(b.H[:m, :m] - a.H[:m, :m], 2) / np.linalg.norm(a.H[:m, :m], 2)
+        eB = np.linalg.norm(b.beta[:q, :q] - a.beta[:q, :q]) / np.linalg.norm(a.beta[:q, :q])
+        out.append(b.q == q and eH <= 10 * q * EPS64 * kap and eB <= 10 * q * EPS64 * kap)
+    return all(out)
+
+
+def pin_orthogonal_factorisation(B):
+    """||I - V^T V|| <= 10 sqrt(q) eps and X = V beta to 10 sqrt(q) eps (eqs. qrfactorth, errorinfact)."""
+    X = _noisy(20000, 61, "noisy_2p24x500")
+    b = B.foa_blocked(X)
+    q = b.q
+    V = b.V[:, :q]
+    orth = np.linalg.norm(np.eye(q) - V.T @ V, 2)
+    fact = np.linalg.norm(X[:, :q] - V @ b.beta[:q, :q]) / np.linalg.norm(X[:, :q])
+    hess = np.abs(np.tril(b.H[:q, :q - 1], -2)).max() == 0.0
+    tri = np.abs(np.tril(b.beta[:q, :q], -1)).max() == 0.0
+    return orth <= 10 * np.sqrt(q) * EPS64 and fact <= 10 * np.sqrt(q) * EPS64 and hess and tri
+
+
+def pin_householder(B):
+    """beta equals Householder R with a positive diagonal; H_bar = R_{:,2:} R_{1:q-1}^{-1}."""
+    X = _noisy(500, 25)
+    b = B.foa_blocked(X)
+    Q, R = np.linalg.qr(X)
+    d = np.sign(np.diag(R))
+    R = d[:, None] * R
+    q = b.q
+    Hc = R[:, 1:q] @ np.linalg.inv(R[:q - 1, :q - 1])
+    kap = np.linalg.cond(R)
+    return (np.abs(b.beta[:q, :q] - R).max() <= 100 * q * EPS64 * kap * np.abs(R).max()
+            and np.abs(b.H[:q, :q - 1] - Hc).max() <= 100 * q * EPS64 * kap * np.abs(Hc).max())
+
+
+def pin_exact_rank(B):
+    """Exact-rank data: the block that crosses the rank falls back to the
+    sequential rule, breakdown at the same snapshot, generating eigenvalues exact."""
+    w = datagen.get_workload("exact_rank_4096x64")
+    X, lam, b = datagen.snapshots_numpy(w)
+    bb = B.foa_blocked(X)
+    ev = np.linalg.eigvals(bb.H[:bb.q, :bb.q])
+    lam_all = np.concatenate([lam, np.conj(lam)])
+    return bb.status == ofoa.INVARIANT and bb.q == 20 and match_eigs(ev, lam_all) <= 1e-9
+
+
+def pin_kappa_slope(B):
+    """Projection error grows like kappa, not kappa^2 (Section 3.2.2 figure)."""
+    A = np.vander(np.linspace(0, 1, 50))
+    psi1 = np.random.default_rng(5).standard_normal(50)
+    ks, es = [], []
+    for N in range(5, 12):
+        X = _krylov(A, psi1, N)
+        st = B.foa_blocked(X, tol=0.0)
+        m = N - 1
+        V = st.V[:, :m]
+        es.append(np.linalg.norm(V.T @ A @ V - st.H[:m, :m]))
+        ks.append(np.linalg.cond(X[:, :m]))
+    slope = np.polyfit(np.log(ks), np.log(es), 1)[0]
+    return 0.6 <= slope <= 1.4
+
+
+def pin_block_qr(B):
+    """The block QR of an ill-conditioned block (kappa 1e10) is orthogonal to
+    eps and reproduces the block (Householder-quality)."""
+    rng = np.random.default_rng(3)
+    U, _ = np.linalg.qr(rng.standard_normal((4000, 4)))
+    W, _ = np.linalg.qr(rng.standard_normal((4, 4)))
+    Z = U @ np.diag([1.0, 1e-3, 1e-7, 1e-10]) @ W.T
+    res = B.block_qr(Z)
+    if res is None:
+        return False
+    Q, S = res
+    return (np.linalg.norm(np.eye(4) - Q.T @ Q, 2) <= 100 * EPS64
+            and np.linalg.norm(Z - Q @ S) <= 100 * EPS64 * np.linalg.norm(Z)
+            and np.abs(np.tril(S, -1)).max() == 0.0 and np.all(np.diag(S) > 0))
+
+
+PINS = [pin_matches_sequential, pin_orthogonal_factorisation, pin_householder, pin_exact_rank,
+        pin_kappa_slope, pin_block_qr]
+
+
+@pytest.mark.parametrize("pin", PINS, ids=lambda f: f.__name__)
+def test_blocked_oracle_pin(pin):
+    assert pin(ob)
+
+
+# ---- planted mistakes --------------------------------------------------------
+
+class _Mutant:
+    """oracle.blocked with one function replaced."""
+
+    def __init__(self, **repl):
+        self.__dict__.update({k: getattr(ob, k) for k in ("PB", "UNIT", "block_qr", "_chol_upper",
+                                                          "_right_solve_upper")})
+        self.__dict__.update(repl)
+        self.block_step = lambda st, Y: self.step_impl(self, st, Y)
+        self.foa_blocked = lambda X, p=ob.PB, tol=None, capacity=None: _foa_blocked(self, X, p, tol, capacity)
+
+
+def _foa_blocked(M, X, p, tol, capacity):
+    X = np.asarray(X, dtype=np.float64)
+    n, N = X.shape
+    cap = N if capacity is None else int(capacity)
+    st = ofoa.foa_stream_init(n, cap, tol)
+    ofoa.foa_stream_update(st, X[:, :1])
+    k = 1
+    while k < N:
+        if (st.status == ofoa.ACTIVE and k + p <= N and st.q + p <= cap
+                and M.block_step(st, np.ascontiguousarray(X[:, k:k + p]))):
+            k += p
+            continue
+        m = min(p, N - k)
+        ofoa.foa_stream_update(st, X[:, k:k + m])
+        k += m
+    return st
+
+
+def _step(M, st, Y, passes=2, h_col_shift=0, drop_S=False, transpose_R=False):
+    n, p = Y.shape
+    j = st.q
+    V = st.V[:, :j]
+    yn2 = np.einsum("ij,ij->j", Y, Y)
+    R1 = V.T @ Y
+    Z = Y - V @ R1
+    R = R1
+    if passes == 2:
+        R2 = V.T @ Z
+        Z = Z - V @ R2
+        R = R1 + R2
+    res = M.block_qr(Z)
+    if res is None:
+        return False
+    Q, S = res
+    if drop_S:
+        S = np.diag(np.diag(S))
+    if transpose_R:
+        R = R[:, ::-1]
+    xf = st.xfro2 + np.cumsum(yn2)
+    if np.any(np.diag(S) <= st.tol * np.sqrt(xf)):
+        return False
+    st.beta[:j, j:j + p] = R
+    st.beta[j:j + p, j:j + p] = S
+    st.V[:, j:j + p] = Q
+    for c in range(j - 1, j + p - 1):
+        cc = c + h_col_shift
+        st.H[:c + 2, c] = (st.beta[:c + 2, c + 1] - st.H[:c + 2, :c] @ st.beta[:c, cc]) / st.beta[c, c]
+    st.xfro2 = float(xf[-1])
+    st.q = j + p
+    st.pushes += p
+    return True
+
+
+MUTANTS = {
+    "single_projection": dict(passes=1),
+    "h_recurrence_index": dict(h_col_shift=-1),
+    "block_R_offdiagonal_dropped": dict(drop_S=True),
+    "R_columns_reversed": dict(transpose_R=True),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_blocked_mutant_is_caught(name):
+    kw = MUTANTS[name]
+    M = _Mutant()
+    M.step_impl = lambda M_, st, Y: _step(M_, st, Y, **kw)
+    failed = []
+    for pin in PINS:
+        try:
+            ok = pin(M)
+        except Exception:
+            ok = False
+        if not ok:
+            failed.append(pin.__name__)
+    assert failed, f"mutant {name} passed every pin"
