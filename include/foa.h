@@ -96,6 +96,33 @@ foa_status foa_init(foa_ctx *ctx, int64_t n, int32_t n_max, foa_prec prec, void 
  * breakdown are ignored on the device). */
 foa_status foa_push_snapshot(foa_ctx ctx, const void *d_x, foa_dtype x_dtype);
 
+/* ---- blocked form (p snapshots per basis sweep) ---------------------------- */
+
+/* Caller workspace of foa_push_blocked for a stream of n rows and capacity
+ * n_max (about n * 32 bytes plus n_max * 32 KB). */
+foa_status foa_block_workspace_bytes(int64_t n, int32_t n_max, foa_prec prec, size_t *bytes);
+
+/* Push p snapshots (rows of d_X, row stride ld >= n elements, x_dtype) in
+ * blocks of 4: the factorisation X = V beta and H_bar of the modified FOA
+ * (Section 2, eq. betacolumnupdate; the QR view of Section 3.1) reached with
+ * three sweeps over the basis per block instead of per snapshot.  Per block:
+ * classical Gram-Schmidt of the whole block against V, twice, then the
+ * block's own QR by shifted CholeskyQR3 (Fukaya et al., SIAM J. Sci. Comput.
+ * 2020), beta's new columns [R1 + R2; S] and H_bar's new columns from eq.
+ * betacolumnupdate solved column by column.  The results equal the
+ * sequential form's in exact arithmetic and differ by rounding of the same
+ * O(eps kappa_2) order.  A block whose new diagonal entry of beta falls at or
+ * under the breakdown threshold, or whose Cholesky steps fail, is taken one
+ * snapshot at a time by the sequential kernels (which apply the breakdown
+ * and non-finite rules), as are the first snapshot, a trailing part of fewer
+ * than 4 snapshots and, for an FP64 basis, basis sizes above 256.
+ * d_bws: device buffer of foa_block_workspace_bytes bytes, 256-byte aligned,
+ * caller-owned, contents not preserved.  Synchronising (the host checks each
+ * run of blocks).  FOA_E_CAPACITY if q + p > n_max; FOA_E_STATE on a batch
+ * view or a stream that is not active; FOA_E_NOMEM for a small workspace. */
+foa_status foa_push_blocked(foa_ctx ctx, const void *d_X, int64_t ld, int32_t p, foa_dtype x_dtype,
+                            void *d_bws, size_t bws_bytes);
+
 /* In-place fill target for the next snapshot (the memory note of Appendix
  * A.1: a new snapshot may occupy storage the method already holds): *d_col receives a device buffer of n FP64 entries inside the
  * workspace (the push's work vector).  Fill it on the context's stream after

@@ -1,0 +1,180 @@
+// Blocked push (host side): foa_block_workspace_bytes, foa_push_blocked.
+// The kernels and the method are described in foa_block.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "foa.h"
+#include "foa_ctx.h"
+#include "foa_internal.h"
+
+using namespace foa;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kGramGrid = 1024;  // workgroups of the block Gram passes (partial slots)
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct BlockLayout {
+  size_t Z = 0, coef = 0, partb = 0, partg = 0, sm = 0, flag = 0, total = 0;
+};
+
+BlockLayout block_layout(int64_t n, int n_max, int ldg) {
+  BlockLayout B;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  const int64_t P = (n + PANEL - 1) / PANEL;
+  B.Z = take((size_t)P * PANEL * BPK * 8);
+  B.coef = take((size_t)n_max * BPK * 8);
+  B.partb = take((size_t)n_max * BPK * ldg * 8);
+  B.partg = take((size_t)kGramGrid * BPK * BPK * 8);
+  B.sm = take((size_t)SM_TOTAL * 8);
+  B.flag = take(sizeof(int));
+  B.total = o;
+  return B;
+}
+
+// All kernels of one block of BPK snapshots starting at basis size j.
+hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const void *x, int64_t ldx, bool x64,
+                         int j) {
+  const bool v64 = c->prec == FOA_PREC_F64;
+  BlockArgs a{};
+  a.W = c->W;
+  a.x = x;
+  a.ldx = ldx;
+  a.Z = reinterpret_cast<double *>(bws + L.Z);
+  a.coef = reinterpret_cast<double *>(bws + L.coef);
+  a.partb = reinterpret_cast<double *>(bws + L.partb);
+  a.partg = reinterpret_cast<double *>(bws + L.partg);
+  a.sm = reinterpret_cast<double *>(bws + L.sm);
+  a.flag = reinterpret_cast<int *>(bws + L.flag);
+  a.st = c->sa.st;
+  a.H = c->sa.H;
+  a.beta = c->sa.beta;
+  a.sigma = c->sa.sigma;
+  a.n = c->n;
+  a.P = c->L.P;
+  a.j = j;
+  a.n_max = c->n_max;
+  a.ldg = c->L.ldg;
+  a.ldH = c->L.ldH;
+  a.ldB = c->L.ldB;
+  a.G = (int)std::min<int64_t>({(int64_t)c->L.ldg, c->L.P, (int64_t)2 * c->cus});
+  a.Gz = (int)std::min<int64_t>(kGramGrid, std::max<int64_t>(1, (c->L.P * PANEL + 255) / 256));
+  const int qw = pick_qw(j, 32);
+  hipStream_t s = c->stream;
+  hipError_t e;
+  if ((e = launch_zgram(0, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // ||y_k||^2
+  if ((e = launch_bpass(0, v64, x64, qw, a.G, a, s)) != hipSuccess) return e;       // D = W^T Y
+  if ((e = launch_breduce(1, a, s)) != hipSuccess) return e;                         // R1, coef
+  if ((e = launch_bpass(1, v64, x64, qw, a.G, a, s)) != hipSuccess) return e;       // Z = Y - W C, D
+  if ((e = launch_breduce(2, a, s)) != hipSuccess) return e;                         // R2, R += R2, coef
+  if ((e = launch_bpass(2, v64, true, qw, a.G, a, s)) != hipSuccess) return e;      // Z = Z - W C
+  if ((e = launch_zgram(1, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // Z^T Z
+  if ((e = launch_bchol(0, a, s)) != hipSuccess) return e;                           // shifted
+  if ((e = launch_zgram(2, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // Z T0, Gram
+  if ((e = launch_bchol(1, a, s)) != hipSuccess) return e;
+  if ((e = launch_zgram(2, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // Z T1, Gram
+  if ((e = launch_bchol(1, a, s)) != hipSuccess) return e;
+  if ((e = launch_zgram(3, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // V <- Z T2
+  if ((e = launch_bcommit(a, s)) != hipSuccess) return e;
+  SmallArgs sa = c->sa;
+  sa.j = j + BPK;  // nextb sizes its grid from j + 1 and reads the committed q itself
+  return launch_nextb(sa, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+foa_status foa_block_workspace_bytes(int64_t n, int32_t n_max, foa_prec prec, size_t *bytes) {
+  if (!bytes || n < 1 || n_max < 1 || n_max > FOA_MAX_CAPACITY ||
+      (prec != FOA_PREC_F32 && prec != FOA_PREC_F64))
+    return FOA_E_ARG;
+  *bytes = block_layout(n, n_max, 1024).total;
+  return FOA_OK;
+}
+
+foa_status foa_push_blocked(foa_ctx c, const void *d_X, int64_t ld, int32_t p, foa_dtype x_dtype, void *d_bws,
+                            size_t bws_bytes) {
+  if (!c) return FOA_E_ARG;
+  if (!d_X || (x_dtype != FOA_F32 && x_dtype != FOA_F64) || p < 0 || (p > 0 && ld < c->n) || !d_bws)
+    return set_err(c, FOA_E_ARG, "bad blocked-push arguments");
+  if (c->is_view) return set_err(c, FOA_E_STATE, "blocked pushes go to a single stream, not a batch view");
+  const BlockLayout L = block_layout(c->n, c->n_max, c->L.ldg);
+  if (bws_bytes < L.total || reinterpret_cast<uintptr_t>(d_bws) % kAlign)
+    return set_err(c, FOA_E_NOMEM, "block workspace of %zu bytes needed", L.total);
+  foa_status r = sync_state(c);
+  if (r != FOA_OK) return r;
+  if (c->dev_status != ST_ACTIVE) return set_err(c, FOA_E_STATE, "stream is not active");
+  if (c->q_host + p > c->n_max) return set_err(c, FOA_E_CAPACITY, "block exceeds capacity");
+  const bool x64 = x_dtype == FOA_F64;
+  const size_t es = x64 ? 8 : 4;
+  const char *X = static_cast<const char *>(d_X);
+  char *bws = static_cast<char *>(d_bws);
+  int *flag = reinterpret_cast<int *>(bws + L.flag);
+  // the block passes address a block through one 32-bit buffer range
+  const bool range_ok = (double)(BPK * ld + PANEL) * es < 4294967295.0;
+  auto push_one = [&](int k) -> foa_status {
+    foa_status rr = enqueue_push(c, X + (size_t)k * ld * es, x64);
+    return rr;
+  };
+  int k = 0;
+  if (p > 0 && c->q_host == 0) {
+    if ((r = push_one(0)) != FOA_OK) return r;
+    ++k;
+    if ((r = sync_state(c)) != FOA_OK) return r;
+  }
+  const bool v64 = c->prec == FOA_PREC_F64;
+  while (k < p) {
+    if (c->dev_status != ST_ACTIVE) break;
+    // blocks that can go now: whole blocks, basis sizes the block passes take
+    int nblk = 0;
+    while (k + (nblk + 1) * BPK <= p && range_ok &&
+           block_supported(v64, pick_qw(c->q_host + nblk * BPK, 32)))
+      ++nblk;
+    if (nblk == 0) {
+      while (k < p) {
+        if ((r = push_one(k)) != FOA_OK) return r;
+        ++k;
+      }
+      break;
+    }
+    const int q0 = c->q_host;
+    hipError_t e = launch_bflag_clear(flag, c->stream);
+    for (int b = 0; b < nblk && e == hipSuccess; ++b)
+      e = enqueue_block(c, L, bws, X + (size_t)(k + b * BPK) * ld * es, ld, x64, q0 + b * BPK);
+    if (e != hipSuccess) return hip_err(c, e, "blocked push");
+    c->mirror_valid = false;
+    c->dmd.valid = false;
+    if ((r = sync_state(c)) != FOA_OK) return r;
+    int rejected = 0;
+    if (hipMemcpy(&rejected, flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+      return hip_err(c, hipErrorUnknown, "hipMemcpy block flag");
+    const int done = (c->q_host - q0) / BPK;
+    k += done * BPK;
+    if (rejected && c->dev_status == ST_ACTIVE && k < p) {
+      // the first block that did not go: its snapshots one at a time
+      const int m = std::min(BPK, p - k);
+      for (int i = 0; i < m; ++i) {
+        if ((r = push_one(k)) != FOA_OK) return r;
+        ++k;
+      }
+      if ((r = sync_state(c)) != FOA_OK) return r;
+    }
+  }
+  // snapshots offered after the stream stopped are ignored by the device (and
+  // counted as offered), as in foa_push_block
+  for (; k < p; ++k)
+    if ((r = push_one(k)) != FOA_OK) return r;
+  return sync_state(c);
+}
+
+}  // extern "C"

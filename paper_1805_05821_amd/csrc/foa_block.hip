@@ -1,0 +1,581 @@
+// Blocked form of the FOA push: BPK snapshots per step.
+//
+// The modified FOA builds the thin QR factorisation X = V beta together with
+// H_bar, where beta_{:,c+1} = H_bar_{:,1:c} beta_{1:c,c} (eq. betacolumnupdate;
+// the QR view of Section 3.1).  The blocked form reaches the same factors in
+// exact arithmetic with a block Y of snapshots at a time:
+//   R1 = V^T Y;  Z = Y - V R1;  R2 = V^T Z;  Z = Z - V R2     (block CGS2)
+//   Z = Q S by shifted CholeskyQR3 (Fukaya et al., SIAM J. Sci. Comput. 2020)
+//   beta's new columns [R1 + R2; S], V's new columns Q, and H_bar's new
+//   columns from the recurrence above solved column by column.
+// So the basis is swept three times per block instead of three times per
+// snapshot.  A block is committed only if its Cholesky steps succeed and every
+// new diagonal entry of beta is above the breakdown threshold; otherwise the
+// device state is left as it was and the host takes those snapshots one at a
+// time (the sequential kernels then apply the paper's breakdown rule).
+//
+// Kernels (all on the context stream, all no-ops once the block is rejected):
+//   k_bpass   : the block row passes over V (FP64 accumulation, BPK right-hand
+//               sides; same panel walk and tile layout as the single push);
+//   k_zgram   : passes over the n x BPK block (||y||^2, Z^T Z, Z <- Z T with
+//               its Gram matrix, the final Q written into V);
+//   k_breduce : fixed-order reduction of the pass partials into R1 / R2 and
+//               the next pass's coefficients;
+//   k_bchol   : Gram reduction, (shifted) Cholesky and triangular inverse;
+//   k_bcommit : breakdown test, beta, H_bar, sigma and the scalar state.
+#include "foa_device.h"
+
+namespace foa {
+
+enum { BP_R1 = 0, BP_Z1 = 1, BP_Z2 = 2 };
+bool block_supported(bool tv_f64, int qw);
+enum { ZG_YNORM = 0, ZG_GRAM = 1, ZG_APPLY = 2, ZG_WRITEV = 3 };
+
+// ---------------------------------------------------------------------------
+// Block row pass.  MODE BP_R1: D = W^T Y (column sums only).  BP_Z1:
+// Z = Y - W C, D = W^T Z.  BP_Z2: Z = Z - W C.  W is the stored basis (the
+// sigma scaling of its columns is folded into C and into the reduction of D).
+// Per panel, the BPK right-hand sides of a row are spread over the update
+// lanes (row, k); phase 1 and phase 2 are those of the single push with BPK
+// values per row.
+// ---------------------------------------------------------------------------
+template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
+__global__ __launch_bounds__(NW * 64) void k_bpass(BlockArgs a) {
+  constexpr int EPL = Vec<TV>::EPL;
+  constexpr int LPC = 64 / EPL;
+  constexpr int CPW = EPL;
+  constexpr int JCAP = QW * NW * CPW;
+  constexpr int RPW = PANEL / NW;
+  constexpr int GSTRIDE = NW * CPW;
+  constexpr bool HAS_P1 = MODE != BP_R1;
+  constexpr bool HAS_P2 = MODE != BP_Z2;
+  constexpr bool SRC_X = MODE != BP_Z2;
+  static_assert(RPW * BPK <= 64, "update lanes");
+
+  if (a.st->status != ST_ACTIVE || *a.flag) return;
+
+  __shared__ double s_coef[HAS_P1 ? JCAP * BPK : 1];
+  __shared__ double s_red[2][NW][PANEL * BPK];
+  __shared__ double s_w[2][PANEL * BPK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int cs = lane / LPC;
+  const int rg = lane % LPC;
+  const int j = a.j;
+  const int slot = blockIdx.x;
+
+  if (HAS_P1)
+    for (int c = tid; c < JCAP * BPK; c += NW * 64) s_coef[c] = (c < j * BPK) ? a.coef[c] : 0.0;
+  __syncthreads();
+
+  const int cbase = wave * CPW + cs;
+  const unsigned goff0 = (unsigned)((wave * CPW * PANEL + lane * EPL) * sizeof(TV));
+  constexpr unsigned GBYTES = (unsigned)(GSTRIDE * PANEL * sizeof(TV));
+  const unsigned tile_bytes = (unsigned)(j * PANEL * sizeof(TV));
+  // update lanes: (row, right-hand side) pairs of this wavefront's rows
+  const bool uact = lane < RPW * BPK;
+  const int urow = wave * RPW + (lane % (RPW * BPK)) / BPK;
+  const int uk = lane % BPK;
+
+  double acc[QW][BPK];
+#pragma unroll
+  for (int g = 0; g < QW; ++g)
+#pragma unroll
+    for (int k = 0; k < BPK; ++k) acc[g][k] = 0.0;
+
+  const char *Wb = static_cast<const char *>(a.W);
+  const size_t pbytes = (size_t)a.n_max * PANEL * sizeof(TV);
+  TV t[QW][EPL];
+  TV tn[QW][EPL];
+  auto load_tile = [&](int64_t p, TV (&dst)[QW][EPL], unsigned bytes) {
+    const __amdgpu_buffer_rsrc_t rt = make_rsrc(Wb + (size_t)p * pbytes, bytes);
+#pragma unroll
+    for (int g = 0; g < QW; ++g) {
+      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rt, (int)(goff0 + g * GBYTES), 0, 0);
+      unpack16<TV>(v, dst[g]);
+    }
+  };
+
+  const int64_t pend = a.P, pstep = gridDim.x;
+  int64_t p = blockIdx.x;
+  if (PREF && p < pend) {
+    load_tile(p, t, tile_bytes);
+#pragma unroll
+    for (int g = 0; g < QW; ++g)
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(t[g][e]));
+  }
+  int par = 0;
+  for (; p < pend; p += pstep) {
+    double y;
+    if (SRC_X) {
+      const int64_t rem = a.n - p * PANEL;
+      const int valid = (int)(rem >= PANEL ? PANEL : (rem > 0 ? rem : 0));
+      const __amdgpu_buffer_rsrc_t rx = make_rsrc(static_cast<const TX *>(a.x) + p * PANEL,
+                                                  (unsigned)(((BPK - 1) * a.ldx + valid) * sizeof(TX)));
+      const unsigned off = (uact && urow < valid) ? (unsigned)((uk * a.ldx + urow) * sizeof(TX)) : kOOR;
+      y = buf_load_scalar<TX>(rx, off);
+    } else {
+      const __amdgpu_buffer_rsrc_t rz = make_rsrc(a.Z + p * PANEL * BPK, PANEL * BPK * 8);
+      y = buf_load_scalar<double>(rz, uact ? (unsigned)((uk * PANEL + urow) * 8) : kOOR);
+    }
+    if (PREF) {
+      const bool more = p + pstep < pend;
+      load_tile(more ? p + pstep : p, tn, more ? tile_bytes : 0u);
+    } else {
+      load_tile(p, t, tile_bytes);
+    }
+
+    double us = 0.0;
+    if (HAS_P1) {
+      double u[EPL][BPK];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e)
+#pragma unroll
+        for (int k = 0; k < BPK; ++k) u[e][k] = 0.0;
+#pragma unroll
+      for (int g = 0; g < QW; ++g) {
+#pragma unroll
+        for (int k = 0; k < BPK; ++k) {
+          const double cf = s_coef[(cbase + g * GSTRIDE) * BPK + k];
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) u[e][k] = fma((double)t[g][e], cf, u[e][k]);
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < EPL; ++e)
+#pragma unroll
+        for (int k = 0; k < BPK; ++k) {
+          if constexpr (LPC <= 16) u[e][k] = xor_sum<16>(u[e][k]);
+          u[e][k] = xor_sum<32>(u[e][k]);
+        }
+      if (cs == 0) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e)
+#pragma unroll
+          for (int k = 0; k < BPK; ++k) s_red[par][wave][(rg * EPL + e) * BPK + k] = u[e][k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) us += s_red[par][w2][urow * BPK + uk];
+    }
+    const double wv = y - us;
+    if (MODE != BP_R1) {
+      const __amdgpu_buffer_rsrc_t rz = make_rsrc(a.Z + p * PANEL * BPK, PANEL * BPK * 8);
+      buf_store_scalar<double>(wv, rz, uact ? (unsigned)((uk * PANEL + urow) * 8) : kOOR);
+    }
+    if (HAS_P2) {
+      if (uact) s_w[par][urow * BPK + uk] = wv;
+      __syncthreads();
+      double wr[EPL][BPK];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e)
+#pragma unroll
+        for (int k = 0; k < BPK; ++k) wr[e][k] = s_w[par][(rg * EPL + e) * BPK + k];
+      if constexpr (sizeof(TV) == 4) {
+#pragma unroll
+        for (int g = 0; g < QW; ++g)
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(t[g][e]));
+      }
+#pragma unroll
+      for (int g = 0; g < QW; ++g)
+#pragma unroll
+        for (int k = 0; k < BPK; ++k)
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) acc[g][k] = fma((double)t[g][e], wr[e][k], acc[g][k]);
+    }
+    if (PREF) {
+#pragma unroll
+      for (int g = 0; g < QW; ++g)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(tn[g][e]));
+#pragma unroll
+      for (int g = 0; g < QW; ++g)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) t[g][e] = tn[g][e];
+    }
+    par ^= 1;
+  }
+
+  if (HAS_P2) {
+#pragma unroll
+    for (int g = 0; g < QW; ++g) {
+      const int c = cbase + g * GSTRIDE;
+#pragma unroll
+      for (int k = 0; k < BPK; ++k) {
+        double v = acc[g][k];
+#pragma unroll
+        for (int m = 1; m < LPC; m <<= 1) v += xor_shfl(v, m);
+        if (rg == 0 && c < j) a.partb[((size_t)c * BPK + k) * a.ldg + slot] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Passes over the n x BPK block, one thread per row (rows grid-strided).
+// ZG_YNORM: partial ||y_k||^2 of the snapshots.  ZG_GRAM: partial Z^T Z.
+// ZG_APPLY: Z <- Z T (T upper triangular) and the partial Gram of the result.
+// ZG_WRITEV: V's columns j .. j+BPK-1 <- Z T, rounded to the storage type.
+// Partials: partg[slot * GSLOT + (k * BPK + l)], slot = workgroup.
+// ---------------------------------------------------------------------------
+constexpr int GSLOT = BPK * BPK;
+
+template <typename TV, typename TX, int MODE>
+__global__ __launch_bounds__(256) void k_zgram(BlockArgs a) {
+  if (a.st->status != ST_ACTIVE || *a.flag) return;
+  __shared__ double sh[256];
+  __shared__ double sT[BPK * BPK];
+  const int tid = threadIdx.x;
+  if (MODE == ZG_APPLY || MODE == ZG_WRITEV) {
+    if (tid < BPK * BPK) sT[tid] = a.sm[SM_T + tid];
+    __syncthreads();
+  }
+  double g[BPK][BPK];
+#pragma unroll
+  for (int k = 0; k < BPK; ++k)
+#pragma unroll
+    for (int l = 0; l < BPK; ++l) g[k][l] = 0.0;
+  const int64_t npad = a.P * PANEL;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + tid; r < npad; r += (int64_t)gridDim.x * 256) {
+    const int64_t p = r / PANEL;
+    const int rr = (int)(r % PANEL);
+    double z[BPK];
+    if (MODE == ZG_YNORM) {
+#pragma unroll
+      for (int k = 0; k < BPK; ++k)
+        z[k] = r < a.n ? (double)static_cast<const TX *>(a.x)[(int64_t)k * a.ldx + r] : 0.0;
+#pragma unroll
+      for (int k = 0; k < BPK; ++k) g[k][k] = fma(z[k], z[k], g[k][k]);
+      continue;
+    }
+    double *zr = a.Z + p * PANEL * BPK + rr;
+#pragma unroll
+    for (int k = 0; k < BPK; ++k) z[k] = zr[k * PANEL];
+    if (MODE == ZG_APPLY || MODE == ZG_WRITEV) {
+      double o[BPK];
+#pragma unroll
+      for (int l = 0; l < BPK; ++l) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k <= l; ++k) s = fma(z[k], sT[k * BPK + l], s);  // T[k][l], k <= l
+        o[l] = s;
+      }
+#pragma unroll
+      for (int l = 0; l < BPK; ++l) z[l] = o[l];
+    }
+    if (MODE == ZG_WRITEV) {
+      TV *vc = static_cast<TV *>(a.W) + (size_t)p * a.n_max * PANEL + (size_t)a.j * PANEL + rr;
+#pragma unroll
+      for (int k = 0; k < BPK; ++k) vc[k * PANEL] = (TV)z[k];
+      continue;
+    }
+    if (MODE == ZG_APPLY) {
+#pragma unroll
+      for (int k = 0; k < BPK; ++k) zr[k * PANEL] = z[k];
+    }
+#pragma unroll
+    for (int k = 0; k < BPK; ++k)
+#pragma unroll
+      for (int l = 0; l < BPK; ++l) g[k][l] = fma(z[k], z[l], g[k][l]);
+  }
+  if (MODE == ZG_WRITEV) return;
+#pragma unroll
+  for (int k = 0; k < BPK; ++k)
+#pragma unroll
+    for (int l = 0; l < BPK; ++l) {
+      if (MODE == ZG_YNORM && k != l) continue;
+      const double s = block_sum_256(g[k][l], sh);
+      if (tid == 0) a.partg[(size_t)blockIdx.x * GSLOT + k * BPK + l] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reduction of the block-pass partials: one wavefront per (column, rhs) pair
+// in a fixed order.  MODE 1 (after BP_R1): R = sigma o D, coef = sigma o R,
+// and (extra wavefronts) ||y_k||^2 from the ZG_YNORM partials.  MODE 2 (after
+// BP_Z1): R += sigma o D, coef = sigma o (sigma o D).
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_breduce(BlockArgs a) {
+  if (a.st->status != ST_ACTIVE || *a.flag) return;
+  const int lane = threadIdx.x & 63;
+  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int npairs = a.j * BPK;
+  if (wv < npairs) {
+    const int c = wv / BPK, k = wv % BPK;
+    const double *pc = a.partb + (size_t)wv * a.ldg;
+    double t = 0.0;
+    for (int g = lane; g < a.G; g += 64) t += pc[g];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) t += xor_shfl(t, m);
+    if (lane == 0) {
+      const double r = a.sigma[c] * t;
+      const size_t idx = (size_t)c * BPK + k;
+      if (MODE == 1) {
+        a.sm[SM_R + idx] = r;
+      } else {
+        a.sm[SM_R + idx] += r;
+      }
+      a.coef[idx] = a.sigma[c] * r;
+    }
+  } else if (MODE == 1 && wv < npairs + BPK) {
+    const int k = wv - npairs;
+    double t = 0.0;
+    for (int g = lane; g < a.Gz; g += 64) t += a.partg[(size_t)g * GSLOT + k * BPK + k];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) t += xor_shfl(t, m);
+    if (lane == 0) a.sm[SM_YN2 + k] = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky step ROUND (0: shifted) of the block QR: reduce the Gram partials
+// (fixed order), factor G (+ s I) = S^T S, store T = S^{-1} and accumulate
+// S_total = S S_total.  A non-finite Gram matrix or a non-positive pivot
+// rejects the block.  One workgroup; the 4 x 4 algebra runs in thread 0.
+// ---------------------------------------------------------------------------
+template <int ROUND>
+__global__ __launch_bounds__(256) void k_bchol(BlockArgs a) {
+  if (a.st->status != ST_ACTIVE || *a.flag) return;
+  __shared__ double sh[256];
+  __shared__ double sG[GSLOT];
+  const int tid = threadIdx.x;
+  for (int e = 0; e < GSLOT; ++e) {
+    double t = 0.0;
+    for (int g = tid; g < a.Gz; g += 256) t += a.partg[(size_t)g * GSLOT + e];
+    const double s = block_sum_256(t, sh);
+    if (tid == 0) sG[e] = s;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  double G[BPK][BPK], S[BPK][BPK], T[BPK][BPK];
+  bool ok = true;
+  for (int k = 0; k < BPK; ++k)
+    for (int l = 0; l < BPK; ++l) {
+      // symmetric part (the two triangles are sums of the same products)
+      G[k][l] = 0.5 * (sG[k * BPK + l] + sG[l * BPK + k]);
+      ok = ok && isfinite(G[k][l]);
+    }
+  if (ROUND == 0) {
+    double tr = 0.0;
+    for (int k = 0; k < BPK; ++k) tr += G[k][k];
+    const double s = 11.0 * ((double)a.n * BPK + BPK * (BPK + 1)) * 0x1p-53 * tr;
+    for (int k = 0; k < BPK; ++k) G[k][k] += s;
+  }
+  // G = S^T S, S upper triangular with a positive diagonal
+  for (int k = 0; k < BPK; ++k)
+    for (int l = 0; l < BPK; ++l) S[k][l] = 0.0;
+  for (int k = 0; k < BPK && ok; ++k) {
+    double d = G[k][k];
+    for (int i = 0; i < k; ++i) d -= S[i][k] * S[i][k];
+    if (!(d > 0.0) || !isfinite(d)) {
+      ok = false;
+      break;
+    }
+    S[k][k] = sqrt(d);
+    for (int l = k + 1; l < BPK; ++l) {
+      double v = G[k][l];
+      for (int i = 0; i < k; ++i) v -= S[i][k] * S[i][l];
+      S[k][l] = v / S[k][k];
+    }
+  }
+  if (!ok) {
+    *a.flag = 1;
+    return;
+  }
+  // T = S^{-1} (upper triangular), column by column: S T_{:,l} = e_l
+  for (int l = 0; l < BPK; ++l) {
+    for (int k = BPK - 1; k >= 0; --k) {
+      double v = (k == l) ? 1.0 : 0.0;
+      for (int i = k + 1; i <= l; ++i) v -= S[k][i] * T[i][l];
+      T[k][l] = (k <= l) ? v / S[k][k] : 0.0;
+    }
+  }
+  double *Stot = a.sm + SM_S;
+  double P[BPK][BPK];
+  for (int k = 0; k < BPK; ++k)
+    for (int l = 0; l < BPK; ++l) {
+      double v = 0.0;
+      if (ROUND == 0) {
+        v = S[k][l];
+      } else {
+        for (int i = k; i <= l; ++i) v += S[k][i] * Stot[i * BPK + l];
+      }
+      P[k][l] = v;
+    }
+  for (int k = 0; k < BPK; ++k)
+    for (int l = 0; l < BPK; ++l) {
+      Stot[k * BPK + l] = P[k][l];
+      a.sm[SM_T + k * BPK + l] = T[k][l];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Commit of an accepted block (one workgroup): breakdown test on the new
+// diagonal of beta, then beta's columns j .. j+BPK-1, sigma, H_bar's columns
+// j-1 .. j+BPK-2 (0-based) column by column, and the scalar state.  On
+// rejection nothing is written except the flag.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bcommit(BlockArgs a) {
+  DevState *st = a.st;
+  if (st->status != ST_ACTIVE || *a.flag) return;
+  __shared__ int s_ok;
+  const int tid = threadIdx.x;
+  const int j = a.j;
+  const double *Stot = a.sm + SM_S;
+  if (tid == 0) {
+    bool ok = true;
+    double xf = st->xfro2;
+    for (int k = 0; k < BPK; ++k) {
+      const double yk = a.sm[SM_YN2 + k];
+      ok = ok && isfinite(yk);
+      xf += yk;
+      const double skk = Stot[k * BPK + k];
+      ok = ok && isfinite(skk) && skk > st->tol * sqrt(xf);
+    }
+    for (int e = 0; e < j * BPK && ok; ++e) ok = isfinite(a.sm[SM_R + e]);
+    s_ok = ok ? 1 : 0;
+    if (!ok) *a.flag = 1;
+  }
+  __syncthreads();
+  if (!s_ok) return;
+  // beta's new columns: rows 0..j-1 from R, rows j..j+BPK-1 from S
+  for (int e = tid; e < j * BPK; e += 256) {
+    const int c = e / BPK, k = e % BPK;
+    a.beta[(size_t)(j + k) * a.ldB + c] = a.sm[SM_R + e];
+  }
+  if (tid < BPK * BPK) {
+    const int k = tid / BPK, l = tid % BPK;
+    if (k <= l) a.beta[(size_t)(j + l) * a.ldB + (j + k)] = Stot[k * BPK + l];
+  }
+  if (tid < BPK) a.sigma[j + tid] = 1.0;
+  __syncthreads();
+  // H_bar_{:,c} beta_{c,c} = beta_{:,c+1} - H_bar_{:,0:c-1} beta_{0:c-1,c} (0-based c)
+  for (int c = j - 1; c < j + BPK - 1; ++c) {
+    const double *bc = a.beta + (size_t)c * a.ldB;
+    const double *bn = a.beta + (size_t)(c + 1) * a.ldB;
+    const double inv = 1.0 / bc[c];
+    for (int i = tid; i <= c + 1; i += 256) {
+      double v = bn[i];
+      const int l0 = i > 0 ? i - 1 : 0;  // H_bar_{i,l} = 0 for l < i - 1
+      for (int l = l0; l < c; ++l) v -= a.H[(size_t)l * a.ldH + i] * bc[l];
+      a.H[(size_t)c * a.ldH + i] = v * inv;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double xf = st->xfro2;
+    for (int k = 0; k < BPK; ++k) xf += a.sm[SM_YN2 + k];
+    st->xfro2 = xf;
+    st->hlast = a.H[(size_t)(j + BPK - 2) * a.ldH + (j + BPK - 1)];
+    st->q = j + BPK;
+    st->pushes += BPK;
+  }
+}
+
+__global__ void k_bflag_clear(int *flag) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename TV, typename TX, int NW, int MODE, bool PREF>
+static hipError_t launch_bpass_q(int qw, int grid, const BlockArgs &a, hipStream_t s) {
+  constexpr int NT = NW * 64;
+  switch (qw) {
+    case 1: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 1, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 2, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 4, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 8, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    default:
+      if constexpr (NW * 16 * Vec<TV>::EPL <= 512)
+        hipLaunchKernelGGL((k_bpass<TV, TX, NW, 16, MODE, false>), dim3(grid), dim3(NT), 0, s, a);
+      else
+        return hipErrorInvalidValue;
+      break;
+  }
+  return hipGetLastError();
+}
+
+// Prefetch only where the doubled tile fits beside the BPK accumulators.
+template <typename TV, typename TX, int NW>
+static hipError_t launch_bpass_m(int mode, int qw, int grid, const BlockArgs &a, hipStream_t s) {
+  const bool pref = sizeof(TV) == 4 ? qw <= 8 : qw <= 4;
+  if (!block_supported(sizeof(TV) == 8, qw)) return hipErrorInvalidValue;
+  switch (mode) {
+    case BP_R1:
+      return pref ? launch_bpass_q<TV, TX, NW, BP_R1, true>(qw, grid, a, s)
+                  : launch_bpass_q<TV, TX, NW, BP_R1, false>(qw, grid, a, s);
+    case BP_Z1:
+      return pref ? launch_bpass_q<TV, TX, NW, BP_Z1, true>(qw, grid, a, s)
+                  : launch_bpass_q<TV, TX, NW, BP_Z1, false>(qw, grid, a, s);
+    default:
+      return pref ? launch_bpass_q<TV, double, NW, BP_Z2, true>(qw, grid, a, s)
+                  : launch_bpass_q<TV, double, NW, BP_Z2, false>(qw, grid, a, s);
+  }
+}
+
+// Basis sizes the block passes take: an FP64 basis beyond 256 columns needs
+// more accumulator registers than a 16-wavefront workgroup has (those pushes
+// run one snapshot at a time).
+bool block_supported(bool tv_f64, int qw) { return !tv_f64 || qw <= 8; }
+
+hipError_t launch_bpass(int mode, bool tv_f64, bool tx_f64, int qw, int grid, const BlockArgs &a, hipStream_t s) {
+  if (tv_f64)
+    return tx_f64 ? launch_bpass_m<double, double, 16>(mode, qw, grid, a, s)
+                  : launch_bpass_m<double, float, 16>(mode, qw, grid, a, s);
+  return tx_f64 ? launch_bpass_m<float, double, 8>(mode, qw, grid, a, s)
+                : launch_bpass_m<float, float, 8>(mode, qw, grid, a, s);
+}
+
+template <typename TV, typename TX>
+static hipError_t launch_zgram_t(int mode, int grid, const BlockArgs &a, hipStream_t s) {
+  switch (mode) {
+    case ZG_YNORM: hipLaunchKernelGGL((k_zgram<TV, TX, ZG_YNORM>), dim3(grid), dim3(256), 0, s, a); break;
+    case ZG_GRAM: hipLaunchKernelGGL((k_zgram<TV, TX, ZG_GRAM>), dim3(grid), dim3(256), 0, s, a); break;
+    case ZG_APPLY: hipLaunchKernelGGL((k_zgram<TV, TX, ZG_APPLY>), dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_zgram<TV, TX, ZG_WRITEV>), dim3(grid), dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zgram(int mode, bool tv_f64, bool tx_f64, int grid, const BlockArgs &a, hipStream_t s) {
+  if (tv_f64)
+    return tx_f64 ? launch_zgram_t<double, double>(mode, grid, a, s) : launch_zgram_t<double, float>(mode, grid, a, s);
+  return tx_f64 ? launch_zgram_t<float, double>(mode, grid, a, s) : launch_zgram_t<float, float>(mode, grid, a, s);
+}
+
+hipError_t launch_breduce(int mode, const BlockArgs &a, hipStream_t s) {
+  const int waves = a.j * BPK + (mode == 1 ? BPK : 0);
+  const int blocks = (waves + 3) / 4;
+  if (mode == 1)
+    hipLaunchKernelGGL(k_breduce<1>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_breduce<2>, dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bchol(int round, const BlockArgs &a, hipStream_t s) {
+  if (round == 0)
+    hipLaunchKernelGGL(k_bchol<0>, dim3(1), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_bchol<1>, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bcommit(const BlockArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_bcommit, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bflag_clear(int *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_bflag_clear, dim3(1), dim3(64), 0, s, flag);
+  return hipGetLastError();
+}
+
+}  // namespace foa

@@ -115,11 +115,46 @@ struct BatchArgs {
   int min_seg;               // fewest panels per workgroup
 };
 
+// ---- blocked form ------------------------------------------------------------
+constexpr int BPK = 4;  // snapshots per block
+// small-area offsets (doubles): R = R1 + R2 (n_max x BPK, [c * BPK + k]),
+// ||y_k||^2, S_total and T (BPK x BPK, row-major)
+constexpr int SM_R = 0;
+constexpr int SM_YN2 = SM_R + 512 * BPK;
+constexpr int SM_S = SM_YN2 + BPK;
+constexpr int SM_T = SM_S + BPK * BPK;
+constexpr int SM_TOTAL = SM_T + BPK * BPK;
+struct BlockArgs {
+  void *W;          // stored basis (panel layout)
+  const void *x;    // first snapshot of the block; snapshot k at x + k * ldx (elements)
+  int64_t ldx;
+  double *Z;        // n_pad x BPK block, panel layout [panel][k][64]
+  double *coef;     // pass coefficients, [c * BPK + k]
+  double *partb;    // block-pass partials, [(c * BPK + k) * ldg + slot]
+  double *partg;    // block Gram partials, [slot * BPK * BPK + k * BPK + l]
+  double *sm;       // small area (SM_* offsets)
+  int *flag;        // nonzero: the block (or an earlier one) was rejected
+  DevState *st;
+  double *H, *beta, *sigma;
+  int64_t n, P;
+  int j, n_max, ldg, ldH, ldB;
+  int G;            // workgroups of the block passes (partial slots)
+  int Gz;           // workgroups of the block Gram passes
+};
+
 // ---- launchers (defined in foa_kernels.hip) --------------------------------
 // tv_f64: V stored in FP64; tx_f64: snapshot in FP64.
 // nw: wavefronts per workgroup for an FP32 basis (8 or 16; FP64 uses 16).
 hipError_t launch_pass(int mode, bool tv_f64, bool tx_f64, bool prefetch, int nw, int grid,
                        const PassArgs &a, hipStream_t s);
+// blocked form (foa_block.hip)
+bool block_supported(bool tv_f64, int qw);
+hipError_t launch_bpass(int mode, bool tv_f64, bool tx_f64, int qw, int grid, const BlockArgs &a, hipStream_t s);
+hipError_t launch_zgram(int mode, bool tv_f64, bool tx_f64, int grid, const BlockArgs &a, hipStream_t s);
+hipError_t launch_breduce(int mode, const BlockArgs &a, hipStream_t s);
+hipError_t launch_bchol(int round, const BlockArgs &a, hipStream_t s);
+hipError_t launch_bcommit(const BlockArgs &a, hipStream_t s);
+hipError_t launch_bflag_clear(int *flag, hipStream_t s);
 // resident workgroups per CU of the row-pass kernel used at tile width qw
 int pass_occupancy(bool tv_f64, bool tx_f64, bool prefetch, int nw, int qw);
 hipError_t launch_reduce(int mode, const SmallArgs &a, hipStream_t s);

@@ -30,6 +30,17 @@ class FOAStream:
         for k in range(X.shape[0]):
             F.foa_push_snapshot(self.ctx, X[k])
 
+    def push_blocked(self, X):
+        """X: (p, n) tensor; blocked form (foa_push_blocked), 4 snapshots per
+        sweep of the basis.  The block workspace is allocated on first use."""
+        import torch
+
+        if getattr(self, "bws", None) is None:
+            nb = F.foa_block_workspace_bytes(self.n, self.n_max, self.prec)
+            self.bws = torch.empty(nb, dtype=torch.uint8, device=self.ws.device)
+        dt = F.FOA_F64 if str(X.dtype) == "torch.float64" else F.FOA_F32
+        return F.foa_push_blocked(self.ctx, X, X.stride(0), X.shape[0], dt, self.bws, self.bws.numel())
+
     def push_block(self, X):
         dt = F.FOA_F64 if str(X.dtype) == "torch.float64" else F.FOA_F32
         return F.foa_push_block(self.ctx, X, X.stride(0), X.shape[0], dt)

@@ -1,0 +1,177 @@
+"""Blocked form (foa_push_blocked, 4 snapshots per sweep of the basis) through
+the C ABI: against the blocked oracle (same algorithm, different summation
+order), against the sequential oracle within the O(eps kappa) bounds, and the
+fallbacks (breakdown, non-finite snapshots, an FP64 basis above 256 columns,
+trailing snapshots)."""
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+import oracle.blocked as ob
+from gpu_helpers import EPS32, EPS64, announce, kappa_of, rel
+from pins import match_eigs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _name_case(request):
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    announce(request.node.nodeid)
+    yield
+
+
+def _noisy(n, N, name="noisy_2p20x200"):
+    w = datagen.get_workload(name).with_n(n).with_N(N)
+    X, lam, b = datagen.snapshots_numpy(w, dtype="float64")
+    return X
+
+
+def _run_blocked(X, prec, tol=-1.0, split=None, snap_dtype=None):
+    """Blocked pushes of the columns of X; split: list of (kind, count) with
+    kind "b" (blocked) or "s" (single pushes), in order."""
+    import torch
+
+    from paper_1805_05821_amd.stream import FOAStream
+
+    n, N = X.shape
+    dt = snap_dtype or torch.float64
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to(device="cuda", dtype=dt)
+    s = FOAStream(n, N, prec=prec, breakdown_tol=tol, ws_fill=0xFF)
+    k = 0
+    for kind, cnt in (split or [("b", N)]):
+        if kind == "b":
+            s.push_blocked(Xd[k:k + cnt])
+        else:
+            s.push_all(Xd[k:k + cnt])
+        k += cnt
+    from paper_1805_05821_amd import foa as F
+
+    try:
+        st, q = s.sync()
+    except F.FOAError as e:
+        st = e.code
+    H, B, q, m = s.state()
+    V = s.basis(q).cpu().numpy().T if q > 0 else np.zeros((n, 0))
+    return dict(status=st, q=q, m=m, H=H, beta=B, V=V, stream=s)
+
+
+def _compare(g, ref, c, eps, name):
+    q = ref.q
+    assert g["q"] == q, (g["q"], q)
+    m = q - 1
+    kap = kappa_of(ref.beta[:m, :m])
+    tol = c * eps * kap * q
+    eH = rel(g["H"][:q, :m], ref.H[:q, :m])
+    eB = rel(g["beta"][:q, :q], ref.beta[:q, :q])
+    orth = np.linalg.norm(np.eye(q) - g["V"].T @ g["V"], 2)
+    announce(f"{name}: q={q} kappa={kap:.2e} relH={eH:.2e} relB={eB:.2e} orth={orth:.2e} tol={tol:.2e}")
+    assert eH <= tol and eB <= tol
+    return kap, orth
+
+
+@pytest.mark.parametrize("n,N", [(3037, 61), (20000, 121), (64 * 37 + 5, 45)])
+def test_blocked_f64_matches_blocked_oracle(n, N):
+    X = _noisy(n, N)
+    g = _run_blocked(X, "f64")
+    ref = ob.foa_blocked(X)
+    kap, orth = _compare(g, ref, 10.0, EPS64, "vs blocked oracle")
+    assert orth <= 10 * np.sqrt(g["q"]) * EPS64
+    seq = oracle.foa_batch(X)
+    _compare(g, seq, 10.0, EPS64, "vs sequential oracle")
+    g["stream"].close()
+
+
+@pytest.mark.parametrize("N", [61, 300])
+def test_blocked_f32_within_bound(N):
+    """FP32 basis: ||H32 - H64|| <= 10 eps32 kappa and orthogonality; N = 300
+    reaches the widest column tile."""
+    X = _noisy(5000, N, "noisy_2p24x500")
+    g = _run_blocked(X, "f32")
+    seq = oracle.foa_batch(X)
+    q = seq.q
+    m = q - 1
+    kap = kappa_of(seq.beta[:m, :m])
+    eH = np.linalg.norm(g["H"][:m, :m] - seq.H[:m, :m], 2) / np.linalg.norm(seq.H[:m, :m], 2)
+    orth = np.linalg.norm(np.eye(q) - g["V"].T @ g["V"], 2)
+    announce(f"f32 blocked N={N}: q={g['q']} kappa={kap:.2e} relH2={eH:.2e} (bound {10 * EPS32 * kap:.2e}) "
+             f"orth={orth:.2e}")
+    assert g["q"] == q
+    assert eH <= 10 * EPS32 * kap
+    assert orth <= 10 * np.sqrt(q) * EPS32
+    g["stream"].close()
+
+
+def test_blocked_f64_wide_basis_falls_back():
+    """FP64 basis beyond 256 columns: single pushes take over; results still
+    within the bound of the sequential oracle."""
+    X = _noisy(3000, 300)
+    g = _run_blocked(X, "f64")
+    seq = oracle.foa_batch(X)
+    _compare(g, seq, 10.0, EPS64, "f64 N=300")
+    g["stream"].close()
+
+
+def test_blocked_exact_rank_breakdown():
+    """The block that crosses the rank is taken one snapshot at a time: the
+    breakdown rule fires at snapshot 21 and the generating eigenvalues are exact."""
+    w = datagen.get_workload("exact_rank_4096x64")
+    X, lam, b = datagen.snapshots_numpy(w)
+    g = _run_blocked(X, "f64")
+    ref = oracle.foa_batch(X)
+    assert g["q"] == ref.q == 20
+    ev = np.linalg.eigvals(g["H"][:20, :20])
+    err = match_eigs(ev, np.concatenate([lam, np.conj(lam)]))
+    announce(f"exact rank: q={g['q']} status={g['status']} eig err={err:.2e}")
+    assert err <= 1e-9
+    g["stream"].close()
+
+
+def test_blocked_mixed_with_single_pushes():
+    """Single pushes, blocked pushes and a trailing part of fewer than 4, in
+    any order, continue one factorisation; FP32 snapshots."""
+    import torch
+
+    X = _noisy(4133, 50)
+    g = _run_blocked(X, "f64", split=[("s", 3), ("b", 10), ("s", 5), ("b", 23), ("b", 9)],
+                     snap_dtype=torch.float32)
+    ref = oracle.foa_batch(X.astype(np.float32).astype(np.float64))
+    _compare(g, ref, 10.0, EPS64, "mixed")
+    g["stream"].close()
+
+
+def test_blocked_nonfinite_snapshot():
+    """A NaN inside a block: the block is rejected, the sequential kernels
+    stop the stream before that snapshot."""
+    from paper_1805_05821_amd import foa as F
+
+    X = _noisy(2000, 20)
+    X[123, 10] = np.nan
+    g = _run_blocked(X, "f64")
+    ref = oracle.foa_batch(X)
+    assert ref.status == "nonfinite" and ref.q == 10
+    assert g["q"] == 10 and g["status"] == F.FOA_E_NONFINITE
+    assert np.abs(g["H"][:10, :9] - ref.H[:10, :9]).max() <= 1e-10 * np.abs(ref.H[:10, :9]).max()
+    g["stream"].close()
+
+
+def test_blocked_argument_errors():
+    import torch
+
+    from paper_1805_05821_amd import foa as F
+    from paper_1805_05821_amd.stream import FOAStream
+
+    s = FOAStream(1000, 8, prec="f32")
+    X = torch.zeros((9, 1000), dtype=torch.float32, device="cuda")
+    with pytest.raises(F.FOAError) as ei:
+        s.push_blocked(X)
+    assert ei.value.code == F.FOA_E_CAPACITY
+    small = torch.empty(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(F.FOAError) as ei:
+        F.foa_push_blocked(s.ctx, X, 1000, 4, F.FOA_F32, small, small.numel())
+    assert ei.value.code == F.FOA_E_NOMEM
+    s.close()
