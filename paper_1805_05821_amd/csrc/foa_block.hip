@@ -416,9 +416,9 @@ __global__ __launch_bounds__(256) void k_bchol(BlockArgs a) {
 
 // ---------------------------------------------------------------------------
 // Commit of an accepted block (one workgroup): breakdown test on the new
-// diagonal of beta, then beta's columns j .. j+BPK-1, sigma, H_bar's columns
-// j-1 .. j+BPK-2 (0-based) column by column, and the scalar state.  On
-// rejection nothing is written except the flag.
+// diagonal of beta, then beta's columns j .. j+BPK-1, sigma and the scalar
+// state.  On rejection nothing is written except the flag.  H_bar follows in
+// k_bcommit_h.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_bcommit(BlockArgs a) {
   DevState *st = a.st;
@@ -427,8 +427,11 @@ __global__ __launch_bounds__(256) void k_bcommit(BlockArgs a) {
   const int tid = threadIdx.x;
   const int j = a.j;
   const double *Stot = a.sm + SM_S;
+  int bad = 0;
+  for (int e = tid; e < j * BPK; e += 256) bad |= !isfinite(a.sm[SM_R + e]);
+  bad = __syncthreads_or(bad);
   if (tid == 0) {
-    bool ok = true;
+    bool ok = !bad;
     double xf = st->xfro2;
     for (int k = 0; k < BPK; ++k) {
       const double yk = a.sm[SM_YN2 + k];
@@ -437,7 +440,6 @@ __global__ __launch_bounds__(256) void k_bcommit(BlockArgs a) {
       const double skk = Stot[k * BPK + k];
       ok = ok && isfinite(skk) && skk > st->tol * sqrt(xf);
     }
-    for (int e = 0; e < j * BPK && ok; ++e) ok = isfinite(a.sm[SM_R + e]);
     s_ok = ok ? 1 : 0;
     if (!ok) *a.flag = 1;
   }
@@ -453,28 +455,62 @@ __global__ __launch_bounds__(256) void k_bcommit(BlockArgs a) {
     if (k <= l) a.beta[(size_t)(j + l) * a.ldB + (j + k)] = Stot[k * BPK + l];
   }
   if (tid < BPK) a.sigma[j + tid] = 1.0;
-  __syncthreads();
-  // H_bar_{:,c} beta_{c,c} = beta_{:,c+1} - H_bar_{:,0:c-1} beta_{0:c-1,c} (0-based c)
-  for (int c = j - 1; c < j + BPK - 1; ++c) {
-    const double *bc = a.beta + (size_t)c * a.ldB;
-    const double *bn = a.beta + (size_t)(c + 1) * a.ldB;
-    const double inv = 1.0 / bc[c];
-    for (int i = tid; i <= c + 1; i += 256) {
-      double v = bn[i];
-      const int l0 = i > 0 ? i - 1 : 0;  // H_bar_{i,l} = 0 for l < i - 1
-      for (int l = l0; l < c; ++l) v -= a.H[(size_t)l * a.ldH + i] * bc[l];
-      a.H[(size_t)c * a.ldH + i] = v * inv;
-    }
-    __syncthreads();
-  }
   if (tid == 0) {
     double xf = st->xfro2;
     for (int k = 0; k < BPK; ++k) xf += a.sm[SM_YN2 + k];
     st->xfro2 = xf;
-    st->hlast = a.H[(size_t)(j + BPK - 2) * a.ldH + (j + BPK - 1)];
     st->q = j + BPK;
     st->pushes += BPK;
   }
+}
+
+// ---------------------------------------------------------------------------
+// H_bar's new columns c = j-1 .. j+BPK-2 (0-based) of an accepted block, from
+// H_bar_{:,c} beta_{c,c} = beta_{:,c+1} - H_bar_{:,0:c-1} beta_{0:c-1,c}.  The
+// part of the sum over the old columns (l < j-1) is the same kind of product
+// for all BPK new columns, so it is formed first, for every row at once (64
+// rows x 4 l-slices per workgroup, slices combined in order); then each row
+// runs the BPK-step recurrence over the new columns by itself.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bcommit_h(BlockArgs a) {
+  DevState *st = a.st;
+  if (*a.flag || st->q != a.j + BPK) return;  // rejected, or nothing committed
+  __shared__ double sh[4][64][BPK];
+  const int j = a.j;
+  const int r = threadIdx.x & 63;
+  const int sl = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + r;  // 0-based row
+  const int rows = j + BPK;           // rows 0 .. j+BPK-1 carry the new columns
+  double t[BPK];
+#pragma unroll
+  for (int k = 0; k < BPK; ++k) t[k] = 0.0;
+  if (i < rows) {
+    const int lo = i > 0 ? i - 1 : 0;
+    const int hi = j - 1;  // old columns l < j-1
+    const int len = hi > lo ? hi - lo : 0;
+    const int a0 = lo + (len * sl) / 4;
+    const int a1 = lo + (len * (sl + 1)) / 4;
+    for (int l = a0; l < a1; ++l) {
+      const double h = a.H[(size_t)l * a.ldH + i];
+#pragma unroll
+      for (int k = 0; k < BPK; ++k) t[k] = fma(h, a.beta[(size_t)(j - 1 + k) * a.ldB + l], t[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < BPK; ++k) sh[sl][r][k] = t[k];
+  __syncthreads();
+  if (sl != 0 || i >= rows) return;
+  double hn[BPK];
+#pragma unroll
+  for (int k = 0; k < BPK; ++k) {
+    const int c = j - 1 + k;
+    double v = a.beta[(size_t)(c + 1) * a.ldB + i];
+    v -= ((sh[0][r][k] + sh[1][r][k]) + sh[2][r][k]) + sh[3][r][k];
+    for (int kk = 0; kk < k; ++kk) v -= hn[kk] * a.beta[(size_t)c * a.ldB + (j - 1 + kk)];
+    hn[k] = (i <= c + 1) ? v / a.beta[(size_t)c * a.ldB + c] : 0.0;
+    a.H[(size_t)c * a.ldH + i] = hn[k];
+  }
+  if (i == rows - 1) st->hlast = hn[BPK - 1];
 }
 
 __global__ void k_bflag_clear(int *flag) {
@@ -570,6 +606,7 @@ hipError_t launch_bchol(int round, const BlockArgs &a, hipStream_t s) {
 
 hipError_t launch_bcommit(const BlockArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_bcommit, dim3(1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_bcommit_h, dim3((a.j + BPK + 63) / 64), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
