@@ -11,6 +11,11 @@ q = 0.  The headline form stores the basis in FP32 with FP64 accumulation
 (CGS2); the plain FP64 form is timed on the same snapshots and reported
 beside it, with the FP32-vs-FP64 error and kappa_2.
 
+Further legs (each reported in its own object of the JSON line): the blocked
+form on the same snapshots (4 snapshots per sweep of the basis), the batched
+form on batched_256 (256 streams, one graph launch per step), the n = 1e8
+run with its FP32-MFMA mode reconstruction, and the CPU oracle on a sample.
+
 Output: one JSON line on stdout; progress on stderr.
 """
 
