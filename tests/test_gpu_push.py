@@ -235,3 +235,25 @@ def test_capacity_and_state_errors():
     s2.reset()
     s2.push_all(Xt[:5])
     assert s2.sync() == (F.FOA_OK, 5)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_max_capacity(prec):
+    """n_max = FOA_MAX_CAPACITY: all 512 snapshots (the widest column tile
+    full), Gaussian snapshots of n = 1500 rows (kappa_2 small)."""
+    from paper_1805_05821_amd import foa as F
+
+    N = F.FOA_MAX_CAPACITY
+    X = np.random.default_rng(512).standard_normal((1500, N))
+    st = oracle.foa_batch(X)
+    g = run_gpu(X, prec)
+    if prec == "f64":
+        _compare_f64(g, st)
+    else:
+        m = st.q - 1
+        kap = kappa_of(st.beta[:m, :m])
+        eH = np.linalg.norm(g["H"][:m, :m] - st.H[:m, :m], 2) / np.linalg.norm(st.H[:m, :m], 2)
+        orth = np.linalg.norm(np.eye(g["q"]) - g["V"].T @ g["V"], 2)
+        announce(f"f32 N={N}: kappa={kap:.2e} relH2={eH:.2e} orth={orth:.2e}")
+        assert g["q"] == N and eH <= 10 * EPS32 * kap and orth <= 10 * np.sqrt(N) * EPS32
+    g["stream"].close()
