@@ -211,7 +211,8 @@ const char *foa_last_error(foa_ctx ctx);
 /* Tuning knobs (tests and benchmarks): "grid" (workgroups of the row passes,
  * at most 1024; 0 = automatic: all the workgroups the pass kernel of the
  * current tile width keeps resident, at least two per CU), "prefetch" (0/1: register double buffering of the next
- * panel), "nw" (8 or 16: wavefronts per row-pass workgroup for an FP32 basis),
+ * panel), "nw" (0, 4, 8 or 16: wavefronts per row-pass workgroup for an FP32 basis;
+ * 0 = automatic: 4 up to 128 basis columns, 8 beyond),
  * "profile" (0/1: see foa_profile).  FOA_E_ARG for an unknown key. */
 foa_status foa_set_option(foa_ctx ctx, const char *key, int64_t value);
 

@@ -127,12 +127,14 @@ int pass_grid(foa_ctx_s *c, int j, bool x_f64) {
   int g = c->grid_opt;
   if (g <= 0) {
     const bool v64 = c->prec == FOA_PREC_F64;
-    const int cols = v64 ? 32 : c->nw * 4;
+    const int nw = pass_nw(v64, c->nw, j);
+    const int cols = v64 ? 32 : nw * 4;
     const int qw = pick_qw(j > 0 ? j : 1, cols);
     int qi = 0;
     while ((1 << qi) < qw) ++qi;
-    int &occ = c->occ_cache[x_f64 ? 1 : 0][qi];
-    if (occ <= 0) occ = pass_occupancy(v64, x_f64, c->prefetch, c->nw, qw);
+    const int ni = nw == 4 ? 0 : (nw == 8 ? 1 : 2);
+    int &occ = c->occ_cache[x_f64 ? 1 : 0][ni][qi];
+    if (occ <= 0) occ = pass_occupancy(v64, x_f64, c->prefetch, nw, qw);
     g = std::max(c->grid_auto, occ * c->cus);
   }
   if (g > kMaxGrid) g = kMaxGrid;
@@ -160,7 +162,7 @@ static hipError_t timed_pass(foa_ctx_s *c, int mode, bool v64, bool x64, bool pr
     e1 = take_event(c);
     if (e0 && e1) (void)hipEventRecord(e0, c->stream);
   }
-  hipError_t e = launch_pass(mode, v64, x64, pref, c->nw, G, pa, c->stream);
+  hipError_t e = launch_pass(mode, v64, x64, pref, pass_nw(v64, c->nw, pa.j), G, pa, c->stream);
   if (c->profile && e0 && e1) {
     (void)hipEventRecord(e1, c->stream);
     c->ev_pending.push_back({e0, e1, alg_bytes, 0});
@@ -360,7 +362,7 @@ foa_status foa_init(foa_ctx *out, int64_t n, int32_t n_max, foa_prec prec, void 
   c->cus = cus;
   c->grid_auto = 2 * cus;
   c->prefetch = true;  // register double buffering wherever the tile fits
-  c->nw = 8;           // FP32 basis: 8 wavefronts per row-pass workgroup
+  c->nw = 0;           // FP32 basis: wavefronts per row-pass workgroup chosen per basis size
   c->tol = breakdown_tol < 0 ? (double)n_max * std::ldexp(1.0, -52) : breakdown_tol;
   bind_pointers(c);
   foa_status r = reset_device_state(c);
@@ -385,7 +387,8 @@ foa_status foa_set_option(foa_ctx c, const char *key, int64_t value) {
     return FOA_OK;
   }
   if (!std::strcmp(key, "nw")) {
-    if (value != 8 && value != 16) return set_err(c, FOA_E_ARG, "nw must be 8 or 16");
+    if (value != 0 && value != 4 && value != 8 && value != 16)
+      return set_err(c, FOA_E_ARG, "nw must be 0 (automatic), 4, 8 or 16");
     c->nw = (int)value;
     std::memset(c->occ_cache, 0, sizeof c->occ_cache);
     return FOA_OK;

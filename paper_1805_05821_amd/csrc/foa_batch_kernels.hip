@@ -55,11 +55,6 @@ __device__ __forceinline__ int bucket_of(int j, int cols_per_qw) {
   return k;
 }
 
-template <int QW>
-constexpr int bucket_of_qw() {
-  return QW == 1 ? 1 : QW == 2 ? 2 : QW == 4 ? 3 : QW == 8 ? 4 : 5;
-}
-
 // Step state and bucket lists, one workgroup of 1024 threads.  Streams are
 // taken 1024 at a time; per bucket a wavefront prefix sum (count and panels)
 // plus the per-wavefront totals give each active stream its list position
@@ -200,9 +195,11 @@ __global__ __launch_bounds__(256) void k_batch_plan_ranges(BatchArgs b) {
   st->nseg = g1 - g0 + 1;
 }
 
-template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
+// Bucket BK's row pass.  The bucket fixes the basis-size range (tile width
+// BK's multiple of cols_per_qw); NW and QW are the kernel shape that covers it.
+template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF, int BK>
 __global__ __launch_bounds__(NW * 64) void k_pass_batch(BatchArgs b) {
-  constexpr int k = MODE == PM_INIT ? 0 : bucket_of_qw<QW>();
+  constexpr int k = MODE == PM_INIT ? 0 : BK;
   const int G = b.meta[2 * k + 1];
   if ((int)blockIdx.x >= G) return;
   const int cnt = b.meta[2 * k];
@@ -287,75 +284,95 @@ __global__ __launch_bounds__(256) void k_fill_random(float *out, int64_t n, uint
 
 int batch_cols_per_qw(bool tv_f64) { return tv_f64 ? 16 * 2 : 8 * 4; }
 
-template <typename TV, typename TX, int NW, int MODE, bool PREF>
-static hipError_t launch_batch_q(int qw, int grid, const BatchArgs &b, hipStream_t s) {
-  constexpr int NT = NW * 64;
-  switch (qw) {
-    case 1: hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 1, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b); break;
-    case 2: hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 2, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b); break;
-    case 4: hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 4, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b); break;
-    case 8: hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 8, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b); break;
-    default:
-      if constexpr (sizeof(TV) == 4 || !PREF)
-        hipLaunchKernelGGL((k_pass_batch<TV, TX, NW, 16, MODE, PREF>), dim3(grid), dim3(NT), 0, s, b);
-      else
-        return hipErrorInvalidValue;
-      break;
+// Kernel shape of bucket k (1..5: basis sizes up to 32, 64, 128, 256, 512
+// columns).  FP32 basis: 4 wavefronts with 2, 4, 8 groups for k <= 3, then 8
+// wavefronts with 8 and 16 groups (the single push's automatic choice); FP64
+// basis: 16 wavefronts with 1 .. 16 groups, 16 groups without prefetch.
+template <typename TV, typename TX, int MODE, int BK>
+static hipError_t launch_bucket(int grid, const BatchArgs &b, hipStream_t s) {
+  if constexpr (sizeof(TV) == 8) {
+    constexpr int QW = 1 << (BK - 1);
+    constexpr bool PREF = QW < 16;
+    hipLaunchKernelGGL((k_pass_batch<TV, TX, 16, QW, MODE, PREF, BK>), dim3(grid), dim3(16 * 64), 0, s, b);
+  } else if constexpr (BK <= 3) {
+    constexpr int QW = 2 << (BK - 1);
+    hipLaunchKernelGGL((k_pass_batch<TV, TX, 4, QW, MODE, true, BK>), dim3(grid), dim3(4 * 64), 0, s, b);
+  } else {
+    constexpr int QW = BK == 4 ? 8 : 16;
+    hipLaunchKernelGGL((k_pass_batch<TV, TX, 8, QW, MODE, true, BK>), dim3(grid), dim3(8 * 64), 0, s, b);
   }
   return hipGetLastError();
 }
 
-template <typename TV, typename TX, int NW>
-static hipError_t launch_batch_m(int mode, int qw, int grid, const BatchArgs &b, hipStream_t s) {
-  // FP64 tiles of 16 groups are not double buffered (register budget)
-  const bool pref = !(sizeof(TV) == 8 && qw >= 16);
-  switch (mode) {
-    case PM_INIT: return launch_batch_q<TV, TX, NW, PM_INIT, false>(1, grid, b, s);
-    case PM_A:
-      return pref ? launch_batch_q<TV, TX, NW, PM_A, true>(qw, grid, b, s)
-                  : launch_batch_q<TV, TX, NW, PM_A, false>(qw, grid, b, s);
-    case PM_B:
-      return pref ? launch_batch_q<TV, double, NW, PM_B, true>(qw, grid, b, s)
-                  : launch_batch_q<TV, double, NW, PM_B, false>(qw, grid, b, s);
-    default:
-      return pref ? launch_batch_q<TV, double, NW, PM_C, true>(qw, grid, b, s)
-                  : launch_batch_q<TV, double, NW, PM_C, false>(qw, grid, b, s);
+template <typename TV, typename TX, int MODE>
+static hipError_t launch_bucket_k(int k, int grid, const BatchArgs &b, hipStream_t s) {
+  switch (k) {
+    case 1: return launch_bucket<TV, TX, MODE, 1>(grid, b, s);
+    case 2: return launch_bucket<TV, TX, MODE, 2>(grid, b, s);
+    case 3: return launch_bucket<TV, TX, MODE, 3>(grid, b, s);
+    case 4: return launch_bucket<TV, TX, MODE, 4>(grid, b, s);
+    case 5: return launch_bucket<TV, TX, MODE, 5>(grid, b, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
-template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
-static int occ_batch() {
+template <typename TV, typename TX>
+static hipError_t launch_batch_t(int mode, int k, int grid, const BatchArgs &b, hipStream_t s) {
+  constexpr int NWI = sizeof(TV) == 8 ? 16 : 8;
+  switch (mode) {
+    case PM_INIT:
+      hipLaunchKernelGGL((k_pass_batch<TV, TX, NWI, 1, PM_INIT, false, 0>), dim3(grid), dim3(NWI * 64), 0, s, b);
+      return hipGetLastError();
+    case PM_A: return launch_bucket_k<TV, TX, PM_A>(k, grid, b, s);
+    case PM_B: return launch_bucket_k<TV, double, PM_B>(k, grid, b, s);
+    default: return launch_bucket_k<TV, double, PM_C>(k, grid, b, s);
+  }
+}
+
+hipError_t launch_batch_pass(int mode, bool tv_f64, bool tx_f64, int k, int grid, const BatchArgs &b,
+                             hipStream_t s) {
+  if (tv_f64)
+    return tx_f64 ? launch_batch_t<double, double>(mode, k, grid, b, s)
+                  : launch_batch_t<double, float>(mode, k, grid, b, s);
+  return tx_f64 ? launch_batch_t<float, double>(mode, k, grid, b, s)
+                : launch_batch_t<float, float>(mode, k, grid, b, s);
+}
+
+template <typename F>
+static int occ_of(F f, int threads) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void *>(&k_pass_batch<TV, TX, NW, QW, MODE, PREF>), NW * 64, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(f), threads, 0) !=
+      hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
-template <typename TV, int NW>
-static int occ_batch_k(int k) {
-  switch (k) {
-    case 0: return occ_batch<TV, float, NW, 1, PM_INIT, false>();
-    case 1: return occ_batch<TV, float, NW, 1, PM_A, true>();
-    case 2: return occ_batch<TV, float, NW, 2, PM_A, true>();
-    case 3: return occ_batch<TV, float, NW, 4, PM_A, true>();
-    case 4: return occ_batch<TV, float, NW, 8, PM_A, true>();
-    default: return occ_batch<TV, float, NW, 16, PM_A, sizeof(TV) == 4>();
+template <typename TV, int BK>
+static int occ_bucket() {
+  if constexpr (sizeof(TV) == 8) {
+    constexpr int QW = 1 << (BK - 1);
+    return occ_of(&k_pass_batch<TV, float, 16, QW, PM_A, (QW < 16), BK>, 16 * 64);
+  } else if constexpr (BK <= 3) {
+    return occ_of(&k_pass_batch<TV, float, 4, (2 << (BK - 1)), PM_A, true, BK>, 4 * 64);
+  } else {
+    return occ_of(&k_pass_batch<TV, float, 8, (BK == 4 ? 8 : 16), PM_A, true, BK>, 8 * 64);
   }
 }
 
-int batch_pass_occupancy(bool tv_f64, int k) {
-  return tv_f64 ? occ_batch_k<double, 16>(k) : occ_batch_k<float, 8>(k);
+template <typename TV>
+static int occ_batch_k(int k) {
+  constexpr int NWI = sizeof(TV) == 8 ? 16 : 8;
+  switch (k) {
+    case 0: return occ_of(&k_pass_batch<TV, float, NWI, 1, PM_INIT, false, 0>, NWI * 64);
+    case 1: return occ_bucket<TV, 1>();
+    case 2: return occ_bucket<TV, 2>();
+    case 3: return occ_bucket<TV, 3>();
+    case 4: return occ_bucket<TV, 4>();
+    default: return occ_bucket<TV, 5>();
+  }
 }
 
-hipError_t launch_batch_pass(int mode, bool tv_f64, bool tx_f64, int qw, int grid, const BatchArgs &b,
-                             hipStream_t s) {
-  if (tv_f64)
-    return tx_f64 ? launch_batch_m<double, double, 16>(mode, qw, grid, b, s)
-                  : launch_batch_m<double, float, 16>(mode, qw, grid, b, s);
-  return tx_f64 ? launch_batch_m<float, double, 8>(mode, qw, grid, b, s)
-                : launch_batch_m<float, float, 8>(mode, qw, grid, b, s);
-}
+int batch_pass_occupancy(bool tv_f64, int k) { return tv_f64 ? occ_batch_k<double>(k) : occ_batch_k<float>(k); }
 
 hipError_t launch_batch_plan(const BatchArgs &b, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, s, b);

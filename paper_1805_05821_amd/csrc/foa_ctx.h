@@ -56,7 +56,7 @@ struct foa_ctx_s {
   foa::SmallArgs sa{};
   // launch configuration
   int grid_auto = 0, grid_opt = 0;
-  int occ_cache[2][5] = {};  // resident pass-A workgroups per CU [x_f64][log2 qw]
+  int occ_cache[2][3][5] = {};  // resident pass-A workgroups per CU [x_f64][nw 4/8/16][log2 qw]
   bool prefetch = false;
   int nw = 16;  // wavefronts per row-pass workgroup (FP32 basis: 8 or 16)
   double tol = 0.0;

@@ -155,6 +155,8 @@ hipError_t launch_breduce(int mode, const BlockArgs &a, hipStream_t s);
 hipError_t launch_bchol(int round, const BlockArgs &a, hipStream_t s);
 hipError_t launch_bcommit(const BlockArgs &a, hipStream_t s);
 hipError_t launch_bflag_clear(int *flag, hipStream_t s);
+// wavefronts per row-pass workgroup at basis size j (nw_opt 0: automatic)
+int pass_nw(bool tv_f64, int nw_opt, int j);
 // resident workgroups per CU of the row-pass kernel used at tile width qw
 int pass_occupancy(bool tv_f64, bool tx_f64, bool prefetch, int nw, int qw);
 hipError_t launch_reduce(int mode, const SmallArgs &a, hipStream_t s);
@@ -182,7 +184,8 @@ int pick_qw(int j, int cols_per_qw);
 
 // batched form (one call per kernel of a step; all captured in one graph)
 hipError_t launch_batch_plan(const BatchArgs &b, hipStream_t s);
-hipError_t launch_batch_pass(int mode, bool tv_f64, bool tx_f64, int qw, int grid, const BatchArgs &b,
+// row pass of bucket k (0: the first push of a stream, PM_INIT)
+hipError_t launch_batch_pass(int mode, bool tv_f64, bool tx_f64, int k, int grid, const BatchArgs &b,
                              hipStream_t s);
 hipError_t launch_batch_reduce(int mode, const BatchArgs &b, hipStream_t s);
 hipError_t launch_batch_finalize(const BatchArgs &b, hipStream_t s);

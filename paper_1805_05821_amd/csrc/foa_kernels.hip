@@ -102,6 +102,7 @@ static bool prefetch_fits(int qw) {
 template <typename TV, typename TX, int NW>
 static hipError_t launch_pass_m(int mode, bool pref, int grid, const PassArgs &a, hipStream_t s) {
   const int qw = pick_qw(a.j, NW * Vec<TV>::EPL);
+  if (qw * NW * Vec<TV>::EPL < a.j) return hipErrorInvalidValue;  // tile narrower than the basis
   pref = pref && prefetch_fits<TV, NW>(qw);
   switch (mode) {
     case PM_INIT: return launch_pass_q<TV, TX, NW, PM_INIT, false>(1, grid, a, s);
@@ -117,12 +118,27 @@ static hipError_t launch_pass_m(int mode, bool pref, int grid, const PassArgs &a
   }
 }
 
+// Wavefronts per row-pass workgroup.  An FP64 basis always uses 16.  For an
+// FP32 basis nw_opt (4, 8 or 16) if set, else 4 up to 128 columns and 8
+// beyond: at small basis sizes a panel carries little data and the pass is
+// bound by the per-panel barrier and LDS round trips, which smaller,
+// independent workgroups overlap better.
+int pass_nw(bool tv_f64, int nw_opt, int j) {
+  if (tv_f64) return 16;
+  if (nw_opt == 4 && j > 256) return 8;  // 4 wavefronts cover at most 256 columns
+  if (nw_opt > 0) return nw_opt;
+  return j <= 128 ? 4 : 8;
+}
+
 hipError_t launch_pass(int mode, bool tv_f64, bool tx_f64, bool prefetch, int nw, int grid,
                        const PassArgs &a, hipStream_t s) {
   if (tv_f64) {
     return tx_f64 ? launch_pass_m<double, double, 16>(mode, prefetch, grid, a, s)
                   : launch_pass_m<double, float, 16>(mode, prefetch, grid, a, s);
   }
+  if (nw == 4)
+    return tx_f64 ? launch_pass_m<float, double, 4>(mode, prefetch, grid, a, s)
+                  : launch_pass_m<float, float, 4>(mode, prefetch, grid, a, s);
   if (nw == 8)
     return tx_f64 ? launch_pass_m<float, double, 8>(mode, prefetch, grid, a, s)
                   : launch_pass_m<float, float, 8>(mode, prefetch, grid, a, s);
@@ -157,6 +173,7 @@ static int occ_m(int qw, bool pref) {
 
 int pass_occupancy(bool tv_f64, bool tx_f64, bool prefetch, int nw, int qw) {
   if (tv_f64) return tx_f64 ? occ_m<double, double, 16>(qw, prefetch) : occ_m<double, float, 16>(qw, prefetch);
+  if (nw == 4) return tx_f64 ? occ_m<float, double, 4>(qw, prefetch) : occ_m<float, float, 4>(qw, prefetch);
   if (nw == 8) return tx_f64 ? occ_m<float, double, 8>(qw, prefetch) : occ_m<float, float, 8>(qw, prefetch);
   return tx_f64 ? occ_m<float, double, 16>(qw, prefetch) : occ_m<float, float, 16>(qw, prefetch);
 }

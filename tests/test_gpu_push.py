@@ -156,6 +156,23 @@ def test_grid_sizes_agree():
         _compare_f64(g, st)
 
 
+@pytest.mark.parametrize("nw", [0, 4, 8, 16])
+def test_f32_workgroup_shapes_agree(nw):
+    """FP32 basis, every workgroup shape of the row passes (0 = automatic: 4
+    wavefronts up to 128 columns, 8 beyond; 4 falls back to 8 above 256
+    columns), N = 300 spanning all column tiles: within the FP32 bound of the
+    oracle."""
+    X = _noisy(9000, 300)
+    st = oracle.foa_batch(X)
+    g = run_gpu(X, "f32", options={"nw": nw})
+    m = st.q - 1
+    kap = kappa_of(st.beta[:m, :m])
+    eH = np.linalg.norm(g["H"][:m, :m] - st.H[:m, :m], 2) / np.linalg.norm(st.H[:m, :m], 2)
+    orth = np.linalg.norm(np.eye(g["q"]) - g["V"].T @ g["V"], 2)
+    announce(f"nw={nw}: kappa={kap:.2e} relH2={eH:.2e} orth={orth:.2e}")
+    assert g["q"] == st.q and eH <= 10 * EPS32 * kap and orth <= 10 * np.sqrt(g["q"]) * EPS32
+
+
 def test_block_push_equals_single_pushes():
     X = _noisy(3000, 30)
     a = run_gpu(X, "f64")
