@@ -98,7 +98,7 @@ foa_status foa_block_workspace_bytes(int64_t n, int32_t n_max, foa_prec prec, si
   if (!bytes || n < 1 || n_max < 1 || n_max > FOA_MAX_CAPACITY ||
       (prec != FOA_PREC_F32 && prec != FOA_PREC_F64))
     return FOA_E_ARG;
-  *bytes = block_layout(n, n_max, 1024).total;
+  *bytes = block_layout(n, n_max, kStreamSlots).total;
   return FOA_OK;
 }
 

@@ -37,7 +37,7 @@ struct DmdCache {
 };
 
 // ldg: leading dimension (slots) of the partial-sum arrays.
-Layout make_layout(int64_t n, int n_max, foa_prec prec, int ldg = 1024);
+Layout make_layout(int64_t n, int n_max, foa_prec prec, int ldg = kStreamSlots);
 
 }  // namespace foa
 

@@ -95,6 +95,9 @@ struct BatchStream {
 // 1 + log2(QW) = basis size in the column-tile range of tile width QW.
 constexpr int NBUCKET = 6;
 constexpr int kMaxBatchGrid = 4096;
+// Partial-sum slots of a single stream (leading dimension of its pass
+// partials): the most workgroups a single-stream row pass may use.
+constexpr int kStreamSlots = 1024;
 // Per-step plan (device memory, rebuilt by the plan kernels every step): for
 // bucket k, the active streams in stream order with their panel prefix sums,
 // the number of workgroups that share the bucket's panels, and for each of
