@@ -20,7 +20,7 @@ using foa::DevState;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxGrid = kStreamSlots;  // leading dimension of the partial-sum arrays
+constexpr int kMaxGrid = foa::kStreamSlots;  // leading dimension of the partial-sum arrays
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
