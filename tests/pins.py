@@ -265,6 +265,55 @@ def pin_vandermonde_slope(O):
     return 0.6 <= slope <= 1.4, f"log-log slope {slope:.2f}"
 
 
+class _FlopArray(np.ndarray):
+    """ndarray that counts the arithmetic of the operations applied to it:
+    a matrix-vector or inner product with contracted length k costs 2k - 1
+    per output entry, an elementwise add/subtract/multiply/divide/sqrt one
+    per output entry."""
+
+    counter = [0]
+    _ARITH = (np.add, np.subtract, np.multiply, np.divide, np.true_divide, np.sqrt, np.negative)
+
+    def __array_ufunc__(self, ufunc, method, *inputs, **kw):
+        args = [np.asarray(x) if isinstance(x, _FlopArray) else x for x in inputs]
+        out = getattr(ufunc, method)(*args, **kw)
+        if method == "__call__":
+            if ufunc is np.matmul:
+                k = np.shape(args[0])[-1]
+                _FlopArray.counter[0] += int(np.size(out)) * (2 * k - 1)
+            elif ufunc in _FlopArray._ARITH:
+                _FlopArray.counter[0] += int(np.size(out))
+        return out.view(_FlopArray) if isinstance(out, np.ndarray) else out
+
+
+def pin_cost_model(O):
+    """Arithmetic of one iteration's length-n work (steps 9-15), counted on the
+    operations the oracle actually performs: the paper's per-step cost
+    (Appendix A.1: 2nj + n for step 9, 8nj + j for steps 10-14, 3n for step
+    15) plus 2n for ||psi||^2 of the breakdown reading, up to the O(j) terms
+    whose convention the paper leaves open."""
+    X = _noisy_small(n=300, N=12)
+    ok, msgs = True, []
+    for j in (3, 7, 11):
+        st = O.foa_batch(X[:, :j])
+        st.V = st.V.view(_FlopArray)
+        psi = np.ascontiguousarray(X[:, j]).view(_FlopArray)
+        cap = X.shape[1]
+        for name in ("V", "H", "beta"):
+            a = getattr(st, name)
+            big = np.zeros((a.shape[0], cap)) if name == "V" else np.zeros((cap, cap))
+            big[:a.shape[0], :a.shape[1]] = a
+            setattr(st, name, big.view(_FlopArray) if name == "V" else big)
+        _FlopArray.counter[0] = 0
+        O.foa._iteration(st, psi, j)
+        n = X.shape[0]
+        expect = 10 * n * j + 4 * n + 2 * n
+        got = _FlopArray.counter[0]
+        ok = ok and abs(got - expect) <= 4 * j + 4
+        msgs.append(f"j={j}: {got} vs {expect}")
+    return ok, "; ".join(msgs)
+
+
 def pin_state_rules(O):
     """Non-finite snapshot: nothing of it is kept; zero first snapshot: q = 0."""
     X = _noisy_small(n=200, N=10)
@@ -292,6 +341,7 @@ ALL = [
     pin_truncation_rank,
     pin_stream_equals_batch,
     pin_vandermonde_slope,
+    pin_cost_model,
     pin_state_rules,
 ]
 
