@@ -314,8 +314,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        log("bench.py measures the FOA step on one GPU only; runs on several GPUs are not "
-            "part of this build (the row-sharded design is described in DESIGN.md).")
+        log("bench.py measures the FOA step on one GPU only: several GPUs are not supported "
+            "(the rows would shard across GPUs, with one all-reduce of the pass partials per pass).")
         sys.exit(2)
 
     import numpy as np
