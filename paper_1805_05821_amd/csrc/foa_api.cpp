@@ -211,6 +211,9 @@ foa_status enqueue_push(foa_ctx_s *c, const void *x, bool x_f64) {
   pa.W = c->W;
   pa.x = x;
   pa.w = c->w;
+  pa.coef[0] = c->sa.coefA;
+  pa.coef[1] = c->sa.coefB;
+  pa.coef[2] = c->sa.coefC;
   pa.st = c->sa.st;
   pa.part = c->part;
   pa.partn = c->partn;
@@ -227,21 +230,17 @@ foa_status enqueue_push(foa_ctx_s *c, const void *x, bool x_f64) {
   const double nv = (double)c->n, sV = v64 ? 8.0 : 4.0, sX = x_f64 ? 8.0 : 4.0;
   const double vbytes = nv * j * sV;  // the j basis columns, read once per pass
   if (j == 0) {
-    pa.coef = sa.coefA;
     if ((e = timed_pass(c, PM_INIT, v64, x_f64, false, G, pa, nv * (sX + sV))) != hipSuccess)
       return hip_err(c, e, "pass init");
     if ((e = launch_finalize_init(sa, s)) != hipSuccess) return hip_err(c, e, "finalize init");
   } else {
-    pa.coef = sa.coefA;
     if ((e = timed_pass(c, PM_A, v64, x_f64, c->prefetch, G, pa, vbytes + nv * sX)) != hipSuccess)
       return hip_err(c, e, "pass A");
     if ((e = launch_reduce(1, sa, s)) != hipSuccess) return hip_err(c, e, "reduce A");
-    pa.coef = sa.coefB;
-    if ((e = timed_pass(c, PM_B, v64, true, c->prefetch, G, pa, vbytes)) != hipSuccess)
+    if ((e = timed_pass(c, PM_B, v64, x_f64, c->prefetch, G, pa, vbytes)) != hipSuccess)
       return hip_err(c, e, "pass B");
     if ((e = launch_reduce(2, sa, s)) != hipSuccess) return hip_err(c, e, "reduce B");
-    pa.coef = sa.coefC;
-    if ((e = timed_pass(c, PM_C, v64, true, c->prefetch, G, pa, vbytes + nv * sV)) != hipSuccess)
+    if ((e = timed_pass(c, PM_C, v64, x_f64, c->prefetch, G, pa, vbytes + nv * sV)) != hipSuccess)
       return hip_err(c, e, "pass C");
     if ((e = launch_finalize(sa, s)) != hipSuccess) return hip_err(c, e, "finalize");
   }

@@ -159,10 +159,10 @@ hipError_t enqueue_step(foa_batch_s *b, bool x_f64, hipStream_t s) {
     if ((e = launch_batch_pass(PM_A, v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess) return e;
   if ((e = launch_batch_reduce(1, a, s)) != hipSuccess) return e;
   for (int qw = 1, k = 1; qw <= qmax; qw *= 2, ++k)
-    if ((e = launch_batch_pass(PM_B, v64, true, k, a.gridb[k], a, s)) != hipSuccess) return e;
+    if ((e = launch_batch_pass(PM_B, v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess) return e;
   if ((e = launch_batch_reduce(2, a, s)) != hipSuccess) return e;
   for (int qw = 1, k = 1; qw <= qmax; qw *= 2, ++k)
-    if ((e = launch_batch_pass(PM_C, v64, true, k, a.gridb[k], a, s)) != hipSuccess) return e;
+    if ((e = launch_batch_pass(PM_C, v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess) return e;
   if ((e = launch_batch_finalize(a, s)) != hipSuccess) return e;
   return launch_batch_nextb(a, s);
 }

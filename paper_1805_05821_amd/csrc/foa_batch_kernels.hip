@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_batch_plan_ranges(BatchArgs b) {
     const int k = blockIdx.x;
     const int cnt = b.meta[2 * k], G = b.meta[2 * k + 1];
     const int64_t *pre = b.pre + (size_t)k * (b.S + 1);
-    const int64_t T = pre[cnt];
+    const int64_t T = uniform(pre[cnt]);
     for (int g = threadIdx.x; g < G; g += 256) {
       const int64_t lo = (int64_t)g * T / G;
       int a = 0, c = cnt - 1;  // largest i with pre[i] <= lo
@@ -197,38 +197,44 @@ __global__ __launch_bounds__(256) void k_batch_plan_ranges(BatchArgs b) {
 
 // Bucket BK's row pass.  The bucket fixes the basis-size range (tile width
 // BK's multiple of cols_per_qw); NW and QW are the kernel shape that covers it.
+// Every plan and stream value is read through uniform(): the kernel's stores
+// may alias the plan as far as the compiler can tell, so plain loads would
+// stay in vector registers, together with everything derived from them.
 template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF, int BK>
-__global__ __launch_bounds__(NW * 64) void k_pass_batch(BatchArgs b) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(pass_waves<TV, QW>())))
+void k_pass_batch(BatchArgs b) {
   constexpr int k = MODE == PM_INIT ? 0 : BK;
-  const int G = b.meta[2 * k + 1];
+  const int G = uniform(b.meta[2 * k + 1]);
   if ((int)blockIdx.x >= G) return;
-  const int cnt = b.meta[2 * k];
+  const int cnt = uniform(b.meta[2 * k]);
   const int64_t *pre = b.pre + (size_t)k * (b.S + 1);
   const int *list = b.list + (size_t)k * b.S;
   const int64_t T = pre[cnt];
-  int64_t lo = (int64_t)blockIdx.x * T / G;
-  const int64_t hi = (int64_t)(blockIdx.x + 1) * T / G;
-  int i = b.first[k * kMaxBatchGrid + blockIdx.x];
+  int64_t lo = uniform((int64_t)blockIdx.x * T / G);
+  const int64_t hi = uniform((int64_t)(blockIdx.x + 1) * T / G);
+  int i = uniform(b.first[k * kMaxBatchGrid + blockIdx.x]);
   while (lo < hi) {
-    const int s = list[i];
-    const int64_t ps = pre[i], pe = pre[i + 1];
+    const int s = uniform(list[i]);
+    const int64_t ps = uniform(pre[i]), pe = uniform(pre[i + 1]);
     const int64_t e = pe < hi ? pe : hi;
     const BatchStream &d = b.streams[s];
-    const DevState *st = d.st;
+    const DevState *st = uniform(d.st);
     PassArgs a{};
-    a.W = d.W;
-    a.x = b.xptrs[s];
-    a.w = d.w;
-    a.coef = MODE == PM_A ? d.coefA : (MODE == PM_B ? d.coefB : d.coefC);
+    a.W = uniform(d.W);
+    a.x = uniform(b.xptrs[s]);
+    a.w = uniform(d.w);
+    a.coef[0] = uniform(d.coefA);
+    a.coef[1] = uniform(d.coefB);
+    a.coef[2] = uniform(d.coefC);
     a.st = st;
-    a.part = d.part;
-    a.partn = d.partn;
-    a.n = d.n;
-    a.P = d.P;
-    a.j = st->jstep;
-    a.n_max = d.n_max;
-    a.ldg = d.ldg;
-    row_pass_body<TV, TX, NW, QW, MODE, PREF>(a, lo - ps, e - ps, 1, (int)blockIdx.x - st->seg0);
+    a.part = uniform(d.part);
+    a.partn = uniform(d.partn);
+    a.n = uniform(d.n);
+    a.P = uniform(d.P);
+    a.j = uniform(st->jstep);
+    a.n_max = uniform(d.n_max);
+    a.ldg = uniform(d.ldg);
+    row_pass_body<TV, TX, NW, QW, MODE, PREF>(a, lo - ps, e - ps, 1, (int)blockIdx.x - uniform(st->seg0));
     lo = e;
     ++i;
   }
@@ -324,8 +330,8 @@ static hipError_t launch_batch_t(int mode, int k, int grid, const BatchArgs &b, 
       hipLaunchKernelGGL((k_pass_batch<TV, TX, NWI, 1, PM_INIT, false, 0>), dim3(grid), dim3(NWI * 64), 0, s, b);
       return hipGetLastError();
     case PM_A: return launch_bucket_k<TV, TX, PM_A>(k, grid, b, s);
-    case PM_B: return launch_bucket_k<TV, double, PM_B>(k, grid, b, s);
-    default: return launch_bucket_k<TV, double, PM_C>(k, grid, b, s);
+    case PM_B: return launch_bucket_k<TV, TX, PM_B>(k, grid, b, s);
+    default: return launch_bucket_k<TV, TX, PM_C>(k, grid, b, s);
   }
 }
 

@@ -42,6 +42,20 @@ __device__ __forceinline__ double xor_sum(double v) {
   return __builtin_bit_cast(double, p) + __builtin_bit_cast(double, q);
 }
 
+// A value that is the same in every lane, moved to scalar registers.
+template <typename T>
+__device__ __forceinline__ T uniform(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+  } else {
+    const u32x2 w = __builtin_bit_cast(u32x2, v);
+    const u32x2 r = u32x2{(unsigned)__builtin_amdgcn_readfirstlane((int)w.x),
+                          (unsigned)__builtin_amdgcn_readfirstlane((int)w.y)};
+    return __builtin_bit_cast(T, r);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ double buf_load_scalar(__amdgpu_buffer_rsrc_t r, unsigned off);
 template <>
@@ -86,6 +100,16 @@ __device__ __forceinline__ void unpack16<double>(const u32x4 &v, double (&o)[2])
   o[1] = d.y;
 }
 
+// Register budget of the row-pass kernels, as waves per SIMD (amdgpu
+// attribute): FP32 tiles of 8 groups are held to 128 VGPRs and of 4 groups
+// to 96, the budgets at which passes A, B and C of one shape reach the same
+// occupancy.  The few values that do not fit are spilled outside the panel
+// loop (a reload inside it would wait for the prefetched tile).
+template <typename TV, int QW>
+constexpr int pass_waves() {
+  return sizeof(TV) == 4 ? (QW == 8 ? 4 : (QW == 4 ? 5 : 1)) : 1;
+}
+
 // ---------------------------------------------------------------------------
 // Fused row pass.
 //
@@ -94,12 +118,23 @@ __device__ __forceinline__ void unpack16<double>(const u32x4 &v, double (&o)[2])
 // g*NW + wave (g < QW); a group is the 1 KiB contiguous block of CPW columns
 // read by one 16-byte load per lane.  Lane l holds rows EPL*(l % LPC) .. +EPL-1
 // of column (group start) + l / LPC.
-//   phase 1 (row sums  u_r = sum_c V_rc coef_c): per-lane FMA over its groups,
-//            butterfly over the lanes sharing rows, then across wavefronts
-//            through LDS in wavefront order;
-//   update  (every wavefront, 64/NW rows each): w_r = (y_r - u_r) * scale;
+//   phase 1 (row sums  u_r = sum_c V_rc coef_c, for NC coefficient vectors at
+//            once): per-lane FMA over its groups, butterfly over the lanes
+//            sharing rows, then across wavefronts through LDS in wavefront
+//            order;
+//   update  (every wavefront, 64/NW rows each): w_r = (x_r - u0_r) * scale,
+//            then w_r -= u1_r (pass B) and w_r -= u2_r (pass C);
 //   phase 2 (column sums V^T w): per-lane FP64 accumulators that persist
 //            across panels; one butterfly per column at the end.
+// Work vector: for FP32 tiles of 2 to 8 groups (up to 256 columns) w never
+// goes to memory: passes B and C rebuild w_A (and w_B) row by row from the
+// snapshot and the earlier passes' coefficients, with the same operations in
+// the same order, so every pass sees bitwise the values the previous one
+// computed and the only store is the new basis column (pass C).  A stream of
+// small writes between the basis reads costs far more HBM bandwidth than its
+// size (about 15% at 64 columns).  For the other shapes (one group, sixteen
+// groups, FP64 tiles) the extra phase-1 work outweighs that, and passes A and
+// B store w (FP64) for the next pass to read.
 // With PREF the next panel's tile is loaded while the current one is reduced.
 // ---------------------------------------------------------------------------
 // One workgroup processes panels pstart, pstart + pstep, ... < pend of one
@@ -108,19 +143,30 @@ __device__ __forceinline__ void unpack16<double>(const u32x4 &v, double (&o)[2])
 template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
 __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart, int64_t pend, int64_t pstep,
                                               int slot) {
+  // w_A, w_B and w_C are each rounded to FP64 before the next subtraction,
+  // as they were when stored between passes: no implicit FMA contraction
+  // (the explicit fma() calls of the dot products are unaffected).
+#pragma clang fp contract(off)
   constexpr int EPL = Vec<TV>::EPL;
   constexpr int LPC = 64 / EPL;  // lanes per 64-row column segment
   static_assert(LPC == 16 || LPC == 32, "16-byte fragments of FP32 or FP64");
   constexpr int CPW = EPL;       // columns per wavefront load
   constexpr int JCAP = QW * NW * CPW;
   constexpr int RPW = PANEL / NW;  // rows updated by each wavefront
-  constexpr bool HAS_P1 = (MODE != PM_INIT);
+  // w rebuilt from the snapshot (RECOMP) or stored between passes
+  constexpr bool RECOMP = sizeof(TV) == 4 && QW >= 2 && QW <= 8;
+  // coefficient vectors K0 .. K1-1 of a.coef (b, h, s) enter phase 1
+  constexpr int K1 = MODE == PM_A ? 1 : (MODE == PM_B ? 2 : (MODE == PM_C ? 3 : 0));
+  constexpr int K0 = (RECOMP || K1 <= 1) ? 0 : K1 - 1;
+  constexpr int NC = K1 - K0;
+  constexpr bool SRC_X = K0 == 0;  // y is the snapshot, else the stored w
+  constexpr bool HAS_P1 = NC > 0;
   constexpr bool HAS_P2 = (MODE == PM_A || MODE == PM_B);
-  constexpr bool SRC_X = (MODE == PM_INIT || MODE == PM_A);
   constexpr int GSTRIDE = NW * CPW;  // columns between a wavefront's groups
+  constexpr int NCS = NC > 0 ? NC : 1;
 
-  __shared__ double s_coef[JCAP];
-  __shared__ double s_red[2][NW][PANEL];
+  __shared__ double s_coef[NCS][JCAP];
+  __shared__ double s_red[2][NCS][NW][PANEL];
   __shared__ double s_w[PANEL];
   __shared__ double s_nrm[NW];
 
@@ -133,8 +179,10 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
   const int j = a.j;
 
   __syncthreads();  // the previous call of this workgroup may still read LDS
-  for (int c = tid; c < JCAP; c += NW * 64) s_coef[c] = (c < j) ? a.coef[c] : 0.0;
-  const double scale = (MODE == PM_A) ? a.st->scaleA : 1.0;
+#pragma unroll
+  for (int k = 0; k < NC; ++k)
+    for (int c = tid; c < JCAP; c += NW * 64) s_coef[k][c] = (c < j) ? a.coef[K0 + k][c] : 0.0;
+  const double scale = (MODE == PM_INIT) ? 1.0 : uniform(a.st->scaleA);
   __syncthreads();
 
   const int cbase = wave * CPW + cs;  // column of this lane in group 0
@@ -184,7 +232,7 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
   }
   int par = 0;
   for (; p < pend; p += pstep) {
-    // y for the update rows of this wavefront (snapshot or work vector)
+    // y for the update rows of this wavefront (snapshot or stored w)
     double y;
     if (SRC_X) {
       const int64_t rem = a.n - p * PANEL;
@@ -203,35 +251,52 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
     }
 
     if (HAS_P1) {
-      double u[EPL];
+      double u[NCS][EPL];
 #pragma unroll
-      for (int e = 0; e < EPL; ++e) u[e] = 0.0;
+      for (int k = 0; k < NC; ++k) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) u[k][e] = 0.0;
+      }
 #pragma unroll
       for (int g = 0; g < QW; ++g) {
-        const double cf = s_coef[cbase + g * GSTRIDE];
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) u[e] = fma((double)t[g][e], cf, u[e]);
+        for (int k = 0; k < NC; ++k) {
+          const double cf = s_coef[k][cbase + g * GSTRIDE];
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) u[k][e] = fma((double)t[g][e], cf, u[k][e]);
+        }
       }
       // butterfly over the lanes sharing rows (distances LPC .. 32)
-      if constexpr (LPC <= 16) {
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) u[e] = xor_sum<16>(u[e]);
+      for (int k = 0; k < NC; ++k) {
+        if constexpr (LPC <= 16) {
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) u[k][e] = xor_sum<16>(u[k][e]);
+        }
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) u[k][e] = xor_sum<32>(u[k][e]);
       }
-#pragma unroll
-      for (int e = 0; e < EPL; ++e) u[e] = xor_sum<32>(u[e]);
       if (cs == 0) {
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) s_red[par][wave][rg * EPL + e] = u[e];
+        for (int k = 0; k < NC; ++k) {
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) s_red[par][k][wave][rg * EPL + e] = u[k][e];
+        }
       }
       __syncthreads();
     }
-    double us = 0.0;
+    // w_A = (x - V coef0) * scale; w_B = w_A - V coef1; w_C = w_B - V coef2
+    double wv = y;
     if (HAS_P1) {
 #pragma unroll
-      for (int w2 = 0; w2 < NW; ++w2) us += s_red[par][w2][urow];
+      for (int k = 0; k < NC; ++k) {
+        double us = 0.0;
+#pragma unroll
+        for (int w2 = 0; w2 < NW; ++w2) us += s_red[par][k][w2][urow];
+        wv = K0 + k == 0 ? (wv - us) * scale : wv - us;
+      }
     }
-    const double wv = (MODE == PM_A) ? (y - us) * scale : (y - us);
-    if (MODE == PM_A || MODE == PM_B) {
+    if (!RECOMP && (MODE == PM_A || MODE == PM_B)) {
       const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.w + p * PANEL, PANEL * 8);
       buf_store_scalar<double>(wv, rw, uact ? (unsigned)(urow * 8) : kOOR);
     }
@@ -241,7 +306,7 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
       buf_store_scalar<TV>((TV)wv, rv, uact ? (unsigned)(urow * sizeof(TV)) : kOOR);
     }
     if (uact) {
-      if (SRC_X) nrm = fma(y, y, nrm);
+      if (MODE == PM_INIT || MODE == PM_A) nrm = fma(y, y, nrm);
       if (MODE == PM_C) nrm = fma(wv, wv, nrm);
       if (HAS_P2) s_w[urow] = wv;
     }

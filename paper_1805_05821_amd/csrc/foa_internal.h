@@ -40,17 +40,17 @@ struct DevState {
 // Pass modes of the fused row kernel.
 enum PassMode : int {
   PM_INIT = 0,  // q = 0: V(:,0) <- x, partial ||x||^2            (steps 2-3)
-  PM_A = 1,     // w <- (x - V c) * scale, partial V^T w, ||x||^2  (steps 9-10)
-  PM_B = 2,     // w <- w - V c, partial V^T w                     (steps 11-12)
-  PM_C = 3,     // w <- w - V c, V(:,j) <- w, partial ||w||^2      (steps 14-15)
+  PM_A = 1,     // w_A = (x - V c0) * scale, partial V^T w_A, ||x||^2  (steps 9-10)
+  PM_B = 2,     // w_B = w_A - V c1, partial V^T w_B                  (steps 11-12)
+  PM_C = 3,     // w_C = w_B - V c2, V(:,j) <- w_C, partial ||w_C||^2 (steps 14-15)
 };
 
 struct PassArgs {
   const void *W;        // V storage (panel layout), element type TV
-  const void *x;        // snapshot (PM_INIT / PM_A), element type TX
-  double *w;            // FP64 work vector, n_pad entries
-  const double *coef;   // update coefficients, j entries (sigma-scaled)
-  const DevState *st;   // status (read) and scaleA (read for PM_A)
+  const void *x;        // snapshot, element type TX
+  double *w;            // FP64 work vector, n_pad entries (shapes that store w)
+  const double *coef[3];  // sigma o b, sigma o h, sigma o s (j entries each)
+  const DevState *st;   // status (read) and scaleA
   double *part;         // column partials, layout part[c * ldg + block]
   double *partn;        // norm partials, one per block
   int64_t n;            // valid rows

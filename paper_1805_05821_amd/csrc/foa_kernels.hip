@@ -33,7 +33,7 @@
 namespace foa {
 
 template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
-__global__ __launch_bounds__(NW * 64) void k_pass(PassArgs a) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(pass_waves<TV, QW>()))) void k_pass(PassArgs a) {
   if (a.st->status != ST_ACTIVE) return;
   row_pass_body<TV, TX, NW, QW, MODE, PREF>(a, blockIdx.x, a.P, gridDim.x, blockIdx.x);
 }
@@ -110,11 +110,11 @@ static hipError_t launch_pass_m(int mode, bool pref, int grid, const PassArgs &a
       return pref ? launch_pass_q<TV, TX, NW, PM_A, true>(qw, grid, a, s)
                   : launch_pass_q<TV, TX, NW, PM_A, false>(qw, grid, a, s);
     case PM_B:
-      return pref ? launch_pass_q<TV, double, NW, PM_B, true>(qw, grid, a, s)
-                  : launch_pass_q<TV, double, NW, PM_B, false>(qw, grid, a, s);
+      return pref ? launch_pass_q<TV, TX, NW, PM_B, true>(qw, grid, a, s)
+                  : launch_pass_q<TV, TX, NW, PM_B, false>(qw, grid, a, s);
     default:
-      return pref ? launch_pass_q<TV, double, NW, PM_C, true>(qw, grid, a, s)
-                  : launch_pass_q<TV, double, NW, PM_C, false>(qw, grid, a, s);
+      return pref ? launch_pass_q<TV, TX, NW, PM_C, true>(qw, grid, a, s)
+                  : launch_pass_q<TV, TX, NW, PM_C, false>(qw, grid, a, s);
   }
 }
 
