@@ -110,6 +110,16 @@ constexpr int pass_waves() {
   return sizeof(TV) == 4 ? (QW == 8 ? 4 : (QW == 4 ? 5 : 1)) : 1;
 }
 
+// Work-vector schemes of the row passes (see the fused row pass below).
+enum WScheme : int {
+  W_REBUILD = 0,   // nothing stored: B and C rebuild w_A (and w_B) from the snapshot
+  W_STORE_AB = 1,  // A stores w_A, B reads it and stores w_B, C reads w_B
+};
+template <typename TV, int QW>
+constexpr int w_scheme() {
+  return (sizeof(TV) == 4 && QW >= 2 && QW <= 8) ? W_REBUILD : W_STORE_AB;
+}
+
 // ---------------------------------------------------------------------------
 // Fused row pass.
 //
@@ -153,11 +163,13 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
   constexpr int CPW = EPL;       // columns per wavefront load
   constexpr int JCAP = QW * NW * CPW;
   constexpr int RPW = PANEL / NW;  // rows updated by each wavefront
-  // w rebuilt from the snapshot (RECOMP) or stored between passes
-  constexpr bool RECOMP = sizeof(TV) == 4 && QW >= 2 && QW <= 8;
+  // where w comes from: rebuilt from the snapshot in every pass, or stored
+  // by passes A and B for the next pass
+  constexpr bool REBUILD = w_scheme<TV, QW>() == W_REBUILD;
   // coefficient vectors K0 .. K1-1 of a.coef (b, h, s) enter phase 1
   constexpr int K1 = MODE == PM_A ? 1 : (MODE == PM_B ? 2 : (MODE == PM_C ? 3 : 0));
-  constexpr int K0 = (RECOMP || K1 <= 1) ? 0 : K1 - 1;
+  constexpr int K0 = (REBUILD || K1 <= 1) ? 0 : K1 - 1;
+  constexpr bool STORE_W = !REBUILD && (MODE == PM_A || MODE == PM_B);
   constexpr int NC = K1 - K0;
   constexpr bool SRC_X = K0 == 0;  // y is the snapshot, else the stored w
   constexpr bool HAS_P1 = NC > 0;
@@ -296,7 +308,7 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
         wv = K0 + k == 0 ? (wv - us) * scale : wv - us;
       }
     }
-    if (!RECOMP && (MODE == PM_A || MODE == PM_B)) {
+    if (STORE_W) {
       const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.w + p * PANEL, PANEL * 8);
       buf_store_scalar<double>(wv, rw, uact ? (unsigned)(urow * 8) : kOOR);
     }
