@@ -30,8 +30,9 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMinUnitPanels = 4;                 // smallest range: sizes the partial slots
-constexpr int kUnitCandidates[] = {4, 16, 64};
-constexpr int kTuneSteps = 48, kTuneTimed = 16;   // tuning run: last kTuneTimed of kTuneSteps steps
+constexpr int kUnitCandidates[] = {4, 16, 64};    // bucket mode: smallest range (panels)
+constexpr int kChunkCandidates[] = {16, 32, 64, 128};  // persistent mode: panels per work item at 64 columns
+constexpr int kTuneSamples = 8;                      // basis sizes timed per configuration
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -40,6 +41,8 @@ struct BatchLayout {
   std::vector<Layout> L;
   size_t states = 0, streams = 0, xptrs = 0, rblk_s = 0, rblk_c = 0, tune_x = 0, total = 0;
   size_t plist = 0, ppre = 0, pfirst = 0, pmeta = 0, pspos = 0;
+  size_t qtask = 0, qsync = 0, qctl = 0;  // persistent step
+  size_t qtasks = 0;                       // capacity of the work-item table
   size_t rblocks = 0;
   int64_t max_n = 0;
   int max_nmax = 0;
@@ -59,6 +62,7 @@ BatchLayout batch_layout(int S, const int64_t *n, const int32_t *n_max, foa_prec
     B.rblocks += (size_t)(n_max[s] + 1 + 3) / 4;
     B.max_n = std::max<int64_t>(B.max_n, n[s]);
     B.max_nmax = std::max<int>(B.max_nmax, n_max[s]);
+    B.qtasks += (size_t)((P + kMinChunk - 1) / kMinChunk);
   }
   auto take = [&](size_t bytes) {
     const size_t r = o;
@@ -72,6 +76,9 @@ BatchLayout batch_layout(int S, const int64_t *n, const int32_t *n_max, foa_prec
   B.pfirst = take((size_t)NBUCKET * kMaxBatchGrid * sizeof(int));
   B.pmeta = take((size_t)NBUCKET * 2 * sizeof(int));
   B.pspos = take((size_t)S * sizeof(int));
+  B.qtask = take(B.qtasks * sizeof(PersistTask));
+  B.qsync = take((size_t)4 * S * sizeof(int));
+  B.qctl = take(kCtlInts * sizeof(int));
   B.xptrs = take((size_t)S * sizeof(void *));
   B.rblk_s = take(B.rblocks * sizeof(int));
   B.rblk_c = take(B.rblocks * sizeof(int));
@@ -97,6 +104,8 @@ struct foa_batch_s {
   std::vector<foa_ctx_s *> views;
   BatchArgs args{};
   int unit_panels = 16, grid = 0;
+  bool persist = false;  // one persistent launch for the streams of up to kPersistCols columns
+  int pgrid = 0;         // its workgroups (resident complement)
   int occ[NBUCKET] = {};  // resident row-pass workgroups per CU, per bucket
   double tuned_ms = 0.0;
   hipGraph_t graph[2] = {nullptr, nullptr};
@@ -137,6 +146,7 @@ foa_status upload_config(foa_batch_s *b, int unit_panels) {
   if (e != hipSuccess) return FOA_E_DEVICE;
   b->unit_panels = unit_panels;
   b->args.min_seg = unit_panels;
+  b->args.p_unit = std::max(unit_panels, kMinChunk);
   // every bucket gets at least the tuned grid, and at least one workgroup
   // per resident slot of its kernel
   for (int k = 0; k < NBUCKET; ++k) {
@@ -147,22 +157,33 @@ foa_status upload_config(foa_batch_s *b, int unit_panels) {
 }
 
 // All kernels of one step, enqueued on stream s (direct launches or capture).
+// Bucket mode: per pass one row-pass launch per tile bucket, then the
+// reductions, finalize and next b.  Persistent mode (FP32 basis): the streams
+// of up to kPersistCols columns run in one persistent launch; first pushes
+// and wider bases take the bucket launches, which skip the others.
 hipError_t enqueue_step(foa_batch_s *b, bool x_f64, hipStream_t s) {
   const bool v64 = b->prec == FOA_PREC_F64;
   const int cols = batch_cols_per_qw(v64);
   const int qmax = pick_qw(std::max(b->B.max_nmax - 1, 1), cols);
+  const bool pers = b->persist && !v64;
+  // buckets run by launches: all, or in persistent mode only those wider than kPersistCols
+  int kfirst = 1;
+  if (pers)
+    for (int qw = 1; qw * cols <= kPersistCols; qw *= 2) ++kfirst;
   const BatchArgs &a = b->args;
   hipError_t e;
   if ((e = launch_batch_plan(a, s)) != hipSuccess) return e;
+  if (pers && (e = launch_persist_plan(a, s)) != hipSuccess) return e;
   if ((e = launch_batch_pass(PM_INIT, v64, x_f64, 1, a.gridb[0], a, s)) != hipSuccess) return e;
+  if (pers && (e = launch_step_persist(x_f64, b->pgrid, a, s)) != hipSuccess) return e;
   for (int qw = 1, k = 1; qw <= qmax; qw *= 2, ++k)
-    if ((e = launch_batch_pass(PM_A, v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess) return e;
+    if (k >= kfirst && (e = launch_batch_pass(PM_A, v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess) return e;
   if ((e = launch_batch_reduce(1, a, s)) != hipSuccess) return e;
   for (int qw = 1, k = 1; qw <= qmax; qw *= 2, ++k)
-    if ((e = launch_batch_pass(PM_B, v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess) return e;
+    if (k >= kfirst && (e = launch_batch_pass(PM_B, v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess) return e;
   if ((e = launch_batch_reduce(2, a, s)) != hipSuccess) return e;
   for (int qw = 1, k = 1; qw <= qmax; qw *= 2, ++k)
-    if ((e = launch_batch_pass(PM_C, v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess) return e;
+    if (k >= kfirst && (e = launch_batch_pass(PM_C, v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess) return e;
   if ((e = launch_batch_finalize(a, s)) != hipSuccess) return e;
   return launch_batch_nextb(a, s);
 }
@@ -199,6 +220,7 @@ foa_status ensure_graph(foa_batch_s *b, bool x_f64) {
 
 foa_status reset_states(foa_batch_s *b) {
   if (launch_batch_init_states(b->args, b->tol, b->stream) != hipSuccess) return FOA_E_DEVICE;
+  if (hipMemsetAsync(b->ws + b->B.qctl, 0, kCtlInts * sizeof(int), b->stream) != hipSuccess) return FOA_E_DEVICE;
   for (foa_ctx_s *v : b->views) {
     v->q_host = 0;
     v->dev_status = ST_ACTIVE;
@@ -214,7 +236,7 @@ foa_status reset_states(foa_batch_s *b) {
 // ---- autotuner table: {"entries": [{"key": K, "unit_panels": U, "grid": G, "ms_per_step": T}, ...]}
 struct TuneEntry {
   std::string key;
-  int unit = 0, grid = 0;
+  int unit = 0, grid = 0, persist = 0;
   double ms = 0;
 };
 
@@ -240,6 +262,7 @@ std::vector<TuneEntry> read_table(const std::string &path) {
     };
     e.unit = (int)num("\"unit_panels\"");
     e.grid = (int)num("\"grid\"");
+    e.persist = (int)num("\"persist\"");
     e.ms = num("\"ms_per_step\"");
     if (e.unit > 0 && e.grid > 0) out.push_back(e);
     pos = q2;
@@ -251,15 +274,20 @@ void write_table(const std::string &path, const std::vector<TuneEntry> &ents) {
   std::ofstream f(path);
   f << "{\"entries\": [\n";
   for (size_t i = 0; i < ents.size(); ++i)
-    f << "  {\"key\": \"" << ents[i].key << "\", \"unit_panels\": " << ents[i].unit << ", \"grid\": " << ents[i].grid
+    f << "  {\"key\": \"" << ents[i].key << "\", \"unit_panels\": " << ents[i].unit << ", \"grid\": " << ents[i].grid << ", \"persist\": " << ents[i].persist
       << ", \"ms_per_step\": " << ents[i].ms << "}" << (i + 1 < ents.size() ? "," : "") << "\n";
   f << "]}\n";
 }
 
-// Time kTuneTimed steps (after warm-up steps) of synthetic pushes for one
-// configuration; inputs are a hash sequence regenerated every step.
-foa_status time_config(foa_batch_s *b, int unit, int grid, double *ms_out) {
+// Estimated run time of one configuration: every stream from q = 0 to its
+// capacity, one snapshot per step.  The run's steps are cut into kTuneSamples
+// equal intervals; for each, the states are set to the interval's midpoint
+// basis size (streams already full are idle) and one step is timed after one
+// untimed step.  Inputs are a hash sequence; the basis contents are whatever
+// the workspace holds (timing only: every state is reset afterwards).
+foa_status time_config(foa_batch_s *b, int unit, int grid, bool persist, double *ms_out) {
   b->grid = std::min(grid, kMaxBatchGrid);
+  b->persist = persist;
   foa_status r = upload_config(b, unit);
   if (r != FOA_OK) return r;
   if ((r = reset_states(b)) != FOA_OK) return r;
@@ -268,24 +296,71 @@ foa_status time_config(foa_batch_s *b, int unit, int grid, double *ms_out) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FOA_E_DEVICE;
   hipError_t e = hipSuccess;
-  for (int step = 0; step < kTuneSteps && e == hipSuccess; ++step) {
-    for (int s = 0; s < b->S; ++s) ptrs[s] = step < b->nmax[s] ? (const void *)tx : nullptr;
+  const int T = b->B.max_nmax;
+  double est = 0.0;
+  for (int k = 0; k < kTuneSamples && e == hipSuccess; ++k) {
+    const int t = (int)(((2 * k + 1) * (int64_t)T) / (2 * kTuneSamples));
+    for (int s = 0; s < b->S; ++s) ptrs[s] = t < b->nmax[s] ? (const void *)tx : nullptr;
     e = hipMemcpyAsync(b->ws + b->B.xptrs, ptrs.data(), ptrs.size() * sizeof(void *), hipMemcpyHostToDevice,
                        b->stream);
-    if (e == hipSuccess) e = launch_fill_random(tx, b->B.max_n, (uint32_t)step, b->stream);
-    if (e == hipSuccess && step == kTuneSteps - kTuneTimed) e = hipEventRecord(e0, b->stream);
-    if (e == hipSuccess) e = enqueue_step(b, false, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // the host pointer array is reused
+    if (e == hipSuccess) e = launch_fill_random(tx, b->B.max_n, (uint32_t)k, b->stream);
+    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+      e = launch_tune_states(b->args, t, b->stream);
+      if (e == hipSuccess && rep == 1) e = hipEventRecord(e0, b->stream);
+      if (e == hipSuccess) e = enqueue_step(b, false, b->stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);  // the host pointer array is reused
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    est += (double)ms * T / kTuneSamples;
   }
-  if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
-  if (e == hipSuccess) e = hipEventSynchronize(e1);
-  float ms = 0.f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return FOA_E_DEVICE;
-  *ms_out = ms / kTuneTimed;
+  int err = 0;
+  if (hipMemcpy(&err, b->ws + b->B.qctl + kCtlErr * sizeof(int), sizeof(int), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return FOA_E_DEVICE;
+  if (err != 0) {
+    if (!persist) return FOA_E_DEVICE;
+    *ms_out = 1e300;  // the persistent step did not complete here: never chosen
+    return reset_states(b);
+  }
+  *ms_out = est;
   return FOA_OK;
+}
+
+// The XCD ids that workgroups of this device run on: the persistent step
+// keeps one work queue per XCD so that every exchange between its workgroups
+// stays inside one L2.  More ids than queues, or none: no persistent mode.
+foa_status probe_xcds(foa_batch_s *b) {
+  b->args.p_groups = 0;
+  b->args.p_xmap = ~0ull;
+  unsigned *mask = reinterpret_cast<unsigned *>(b->ws + b->B.qctl + kCtlProbe * sizeof(int));
+  unsigned m = 0;
+  if (hipMemsetAsync(mask, 0, sizeof(unsigned), b->stream) != hipSuccess ||
+      launch_xcc_probe(mask, 16 * b->cus, b->stream) != hipSuccess ||
+      hipMemcpyAsync(&m, mask, sizeof(unsigned), hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return FOA_E_DEVICE;
+  int g = 0;
+  uint64_t map = ~0ull;
+  for (int id = 0; id < 16; ++id)
+    if (m & (1u << id)) {
+      if (g == kMaxGroups) return FOA_OK;
+      map = (map & ~(0xFull << (4 * id))) | ((uint64_t)g << (4 * id));
+      ++g;
+    }
+  b->args.p_groups = g;
+  b->args.p_xmap = map;
+  return FOA_OK;
+}
+
+foa_status apply_config(foa_batch_s *b, int unit, int grid, bool persist) {
+  b->grid = std::min(grid, kMaxBatchGrid);
+  b->persist = persist && b->prec == FOA_PREC_F32 && b->args.p_groups > 0;
+  return upload_config(b, unit);
 }
 
 foa_status tune(foa_batch_s *b) {
@@ -294,31 +369,35 @@ foa_status tune(foa_batch_s *b) {
     table = read_table(b->tune_path);
     for (const TuneEntry &t : table)
       if (t.key == b->tune_key) {
-        b->grid = std::min(t.grid, kMaxBatchGrid);
         b->tuned_ms = t.ms;
-        return upload_config(b, t.unit);
+        return apply_config(b, t.unit, t.grid, t.persist != 0);
       }
   }
   double best = 1e300;
-  int bu = 16, bg = 2 * b->cus;
-  for (int unit : kUnitCandidates) {
-    for (int gm : {1, 2, 4}) {
-      double ms = 0;
-      foa_status r = time_config(b, unit, gm * b->cus, &ms);
-      if (r != FOA_OK) return r;
-      if (ms < best) {
-        best = ms;
-        bu = unit;
-        bg = gm * b->cus;
-      }
+  int bu = 16, bg = 2 * b->cus, bp = 0;
+  auto consider = [&](int unit, int grid, bool persist) -> foa_status {
+    double ms = 0;
+    foa_status r = time_config(b, unit, grid, persist, &ms);
+    if (r != FOA_OK) return r;
+    if (ms < best) {
+      best = ms;
+      bu = unit;
+      bg = grid;
+      bp = persist ? 1 : 0;
     }
-  }
-  b->grid = std::min(bg, kMaxBatchGrid);
+    return FOA_OK;
+  };
+  foa_status r;
+  for (int unit : kUnitCandidates)
+    for (int gm : {1, 2, 4})
+      if ((r = consider(unit, gm * b->cus, false)) != FOA_OK) return r;
+  if (b->prec == FOA_PREC_F32 && b->args.p_groups > 0)
+    for (int unit : kChunkCandidates)
+      if ((r = consider(unit, 2 * b->cus, true)) != FOA_OK) return r;
   b->tuned_ms = best;
-  foa_status r = upload_config(b, bu);
-  if (r != FOA_OK) return r;
+  if ((r = apply_config(b, bu, bg, bp != 0)) != FOA_OK) return r;
   if (!b->tune_path.empty()) {
-    table.push_back(TuneEntry{b->tune_key, bu, bg, best});
+    table.push_back(TuneEntry{b->tune_key, bu, bg, bp, best});
     write_table(b->tune_path, table);
   }
   return FOA_OK;
@@ -394,6 +473,9 @@ foa_status foa_batch_init(foa_batch *out, int32_t S, const int64_t *n, const int
   b->args.first = reinterpret_cast<int *>(b->ws + b->B.pfirst);
   b->args.meta = reinterpret_cast<int *>(b->ws + b->B.pmeta);
   b->args.spos = reinterpret_cast<int *>(b->ws + b->B.pspos);
+  b->args.p_task = reinterpret_cast<PersistTask *>(b->ws + b->B.qtask);
+  b->args.p_sync = reinterpret_cast<int *>(b->ws + b->B.qsync);
+  b->args.p_ctl = reinterpret_cast<int *>(b->ws + b->B.qctl);
   b->args.cols_per_qw = batch_cols_per_qw(prec == FOA_PREC_F64);
   b->args.xptrs = reinterpret_cast<const void *const *>(b->ws + b->B.xptrs);
   b->args.rblk_stream = reinterpret_cast<const int *>(b->ws + b->B.rblk_s);
@@ -424,7 +506,9 @@ foa_status foa_batch_init(foa_batch *out, int32_t S, const int64_t *n, const int
                 (long long)sum_n, max_nmax, cus);
   b->tune_key = key;
   if (tune_table_json) b->tune_path = tune_table_json;
-  foa_status r = tune(b);
+  b->pgrid = prec == FOA_PREC_F32 ? step_persist_occupancy() * cus : 0;
+  foa_status r = prec == FOA_PREC_F32 ? probe_xcds(b) : FOA_OK;
+  if (r == FOA_OK) r = tune(b);
   if (r == FOA_OK) r = reset_states(b);
   if (r == FOA_OK && hipStreamSynchronize(b->stream) != hipSuccess) r = FOA_E_DEVICE;
   if (r != FOA_OK) {
@@ -467,6 +551,10 @@ foa_status foa_batch_sync(foa_batch b, int32_t *h_q, int32_t *h_status) {
     if (h_q) h_q[s] = d.q;
     if (h_status) h_status[s] = (d.status == ST_ACTIVE && d.full) ? FOA_E_CAPACITY : map_status(d.status);
   }
+  int err = 0;  // the persistent step did not complete (a bounded wait ran out)
+  if (hipMemcpy(&err, b->ws + b->B.qctl + kCtlErr * sizeof(int), sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+      err != 0)
+    return FOA_E_DEVICE;
   return FOA_OK;
 }
 

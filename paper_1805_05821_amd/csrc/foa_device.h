@@ -120,6 +120,27 @@ constexpr int w_scheme() {
   return (sizeof(TV) == 4 && QW >= 2 && QW <= 8) ? W_REBUILD : W_STORE_AB;
 }
 
+// Coefficient vectors a pass of this shape uses: K0 .. K1-1 of PassArgs::coef
+// (b, h, s); REBUILD: w is rebuilt from the snapshot instead of stored.
+template <typename TV, int QW, int MODE>
+struct PassCoefs {
+  static constexpr bool REBUILD = w_scheme<TV, QW>() == W_REBUILD;
+  static constexpr int K1 = MODE == PM_A ? 1 : (MODE == PM_B ? 2 : (MODE == PM_C ? 3 : 0));
+  static constexpr int K0 = (REBUILD || K1 <= 1) ? 0 : K1 - 1;
+  static constexpr int NC = K1 - K0;
+  static constexpr int NCS = NC > 0 ? NC : 1;
+};
+
+// LDS of one row-pass call, in doubles: the norm slots, the update rows, the
+// coefficient vectors and two parity buffers of per-wavefront row sums (the
+// first push uses the norm slots only).
+template <typename TV, int NW, int QW, int MODE>
+constexpr int pass_lds_doubles() {
+  constexpr int NCS = PassCoefs<TV, QW, MODE>::NCS;
+  constexpr int JCAP = QW * NW * Vec<TV>::EPL;
+  return MODE == PM_INIT ? NW : NW + PANEL + NCS * JCAP + 2 * NCS * NW * PANEL;
+}
+
 // ---------------------------------------------------------------------------
 // Fused row pass.
 //
@@ -149,10 +170,11 @@ constexpr int w_scheme() {
 // ---------------------------------------------------------------------------
 // One workgroup processes panels pstart, pstart + pstep, ... < pend of one
 // stream and writes its partial sums to slot `slot`.  Called uniformly by
-// the whole workgroup (it synchronises).
+// the whole workgroup (it synchronises).  lds: pass_lds_doubles() doubles of
+// the caller's shared memory.
 template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
 __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart, int64_t pend, int64_t pstep,
-                                              int slot) {
+                                              int slot, double *lds) {
   // w_A, w_B and w_C are each rounded to FP64 before the next subtraction,
   // as they were when stored between passes: no implicit FMA contraction
   // (the explicit fma() calls of the dot products are unaffected).
@@ -164,23 +186,23 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
   constexpr int JCAP = QW * NW * CPW;
   constexpr int RPW = PANEL / NW;  // rows updated by each wavefront
   // where w comes from: rebuilt from the snapshot in every pass, or stored
-  // by passes A and B for the next pass
-  constexpr bool REBUILD = w_scheme<TV, QW>() == W_REBUILD;
-  // coefficient vectors K0 .. K1-1 of a.coef (b, h, s) enter phase 1
-  constexpr int K1 = MODE == PM_A ? 1 : (MODE == PM_B ? 2 : (MODE == PM_C ? 3 : 0));
-  constexpr int K0 = (REBUILD || K1 <= 1) ? 0 : K1 - 1;
+  // by passes A and B for the next pass; coefficient vectors K0 .. K1-1 of
+  // a.coef (b, h, s) enter phase 1
+  using PC = PassCoefs<TV, QW, MODE>;
+  constexpr bool REBUILD = PC::REBUILD;
+  constexpr int K0 = PC::K0;
   constexpr bool STORE_W = !REBUILD && (MODE == PM_A || MODE == PM_B);
-  constexpr int NC = K1 - K0;
+  constexpr int NC = PC::NC;
   constexpr bool SRC_X = K0 == 0;  // y is the snapshot, else the stored w
   constexpr bool HAS_P1 = NC > 0;
   constexpr bool HAS_P2 = (MODE == PM_A || MODE == PM_B);
   constexpr int GSTRIDE = NW * CPW;  // columns between a wavefront's groups
-  constexpr int NCS = NC > 0 ? NC : 1;
+  constexpr int NCS = PC::NCS;
 
-  __shared__ double s_coef[NCS][JCAP];
-  __shared__ double s_red[2][NCS][NW][PANEL];
-  __shared__ double s_w[PANEL];
-  __shared__ double s_nrm[NW];
+  double *s_nrm = lds;
+  double *s_w = lds + NW;
+  double (*s_coef)[JCAP] = reinterpret_cast<double (*)[JCAP]>(lds + NW + PANEL);
+  double (*s_red)[NCS][NW][PANEL] = reinterpret_cast<double (*)[NCS][NW][PANEL]>(lds + NW + PANEL + NCS * JCAP);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -419,11 +441,13 @@ __device__ inline void reduce_body(const SmallArgs &a, int c0) {
   }
 }
 
-__device__ inline double block_sum_256(double t, double *sh) {
+// Sum over a workgroup of NT threads (fixed tree order).
+template <int NT>
+__device__ inline double block_sum_t(double t, double *sh) {
   const int tid = threadIdx.x;
   sh[tid] = t;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if (tid < s) sh[tid] = sh[tid] + sh[tid + s];
     __syncthreads();
   }
@@ -432,9 +456,12 @@ __device__ inline double block_sum_256(double t, double *sh) {
   return r;
 }
 
-// Steps 15-18 plus the breakdown rule; single workgroup.
-__device__ inline void finalize_body(const SmallArgs &a) {
-  __shared__ double sh[256];
+__device__ inline double block_sum_256(double t, double *sh) { return block_sum_t<256>(t, sh); }
+
+// Steps 15-18 plus the breakdown rule; one workgroup of NT threads.
+template <int NT>
+__device__ inline void finalize_body_t(const SmallArgs &a) {
+  __shared__ double sh[NT];
   __shared__ int s_status;
   DevState *st = a.st;
   const int tid = threadIdx.x;
@@ -444,10 +471,10 @@ __device__ inline void finalize_body(const SmallArgs &a) {
   }
   const int j = a.j;
   double t = 0.0;
-  for (int g = tid; g < a.G; g += 256) t += a.partn[g];
-  const double wn2 = block_sum_256(t, sh);
+  for (int g = tid; g < a.G; g += NT) t += a.partn[g];
+  const double wn2 = block_sum_t<NT>(t, sh);
   int bad = 0;
-  for (int i = tid; i < j; i += 256) bad |= !isfinite(a.h[i]);
+  for (int i = tid; i < j; i += NT) bad |= !isfinite(a.h[i]);
   bad = __syncthreads_or(bad);
   const double bjj = a.beta[(size_t)(j - 1) * a.ldB + (j - 1)];
   if (tid == 0) {
@@ -473,7 +500,7 @@ __device__ inline void finalize_body(const SmallArgs &a) {
     }
     return;
   }
-  for (int i = tid; i < j; i += 256) {
+  for (int i = tid; i < j; i += NT) {
     const double hi = a.h[i];
     a.H[(size_t)(j - 1) * a.ldH + i] = hi;
     a.beta[(size_t)j * a.ldB + i] = a.bvec[i] + hi * bjj;  // steps 16-18
@@ -493,6 +520,8 @@ __device__ inline void finalize_body(const SmallArgs &a) {
     st->pushes += 1;
   }
 }
+
+__device__ inline void finalize_body(const SmallArgs &a) { finalize_body_t<256>(a); }
 
 // Steps 2-3 for the first snapshot.
 __device__ inline void finalize_init_body(const SmallArgs &a) {
@@ -524,15 +553,19 @@ __device__ inline void finalize_init_body(const SmallArgs &a) {
 
 // Steps 5-8 for the next push (J = q basis vectors):
 //   b_i = sum_{l = max(1, i-1)}^{J-1} h_{i,l} beta_{l,J}  (1-based), i = 1..J,
-// computed as 64 rows x 4 contiguous l-slices per block, slices combined in
-// order.  Also coefA = sigma o b and scaleA = 1 / beta_{J,J}.
-__device__ inline void nextb_body(const SmallArgs &a, int chunk) {
-  __shared__ double sh[4][64];
+// computed as 64 rows x 4 contiguous l-slices per 256 threads, slices
+// combined in order; a workgroup of NT threads takes NT / 256 consecutive
+// 64-row chunks from chunk0.  Also coefA = sigma o b and scaleA = 1 / beta_{J,J}.
+template <int NT>
+__device__ inline void nextb_body_t(const SmallArgs &a, int chunk0) {
+  __shared__ double sh[NT / 64][64];
   DevState *st = a.st;
   if (st->status != ST_ACTIVE) return;
   const int J = st->q;
   const int r = threadIdx.x & 63;
-  const int sl = threadIdx.x >> 6;
+  const int sl = (threadIdx.x >> 6) & 3;
+  const int sub = threadIdx.x >> 8;
+  const int chunk = chunk0 + sub;
   const int i = chunk * 64 + r;  // 0-based row
   double t = 0.0;
   if (i < J) {
@@ -544,15 +577,17 @@ __device__ inline void nextb_body(const SmallArgs &a, int chunk) {
     const double *bc = a.beta + (size_t)(J - 1) * a.ldB;
     for (int l = a0; l < a1; ++l) t = fma(a.H[(size_t)l * a.ldH + i], bc[l], t);
   }
-  sh[sl][r] = t;
+  sh[4 * sub + sl][r] = t;
   __syncthreads();
   if (sl == 0 && i < J) {
-    const double b = ((sh[0][r] + sh[1][r]) + sh[2][r]) + sh[3][r];
+    const double b = ((sh[4 * sub][r] + sh[4 * sub + 1][r]) + sh[4 * sub + 2][r]) + sh[4 * sub + 3][r];
     a.bvec[i] = b;
     a.coefA[i] = a.sigma[i] * b;
   }
   if (chunk == 0 && threadIdx.x == 0) st->scaleA = 1.0 / a.beta[(size_t)(J - 1) * a.ldB + (J - 1)];
 }
+
+__device__ inline void nextb_body(const SmallArgs &a, int chunk) { nextb_body_t<256>(a, chunk); }
 
 // Reset of one stream: scalar state, and zeros in every small array (the
 // entries of H_bar below the subdiagonal and of beta below the diagonal are
@@ -585,6 +620,7 @@ __device__ inline void init_state_body(const SmallArgs &a, double tol) {
     st->scaleA = 0.0;
     st->tol = tol;
     st->hlast = 0.0;
+    st->pers = 0;
   }
 }
 

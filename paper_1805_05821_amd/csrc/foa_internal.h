@@ -34,7 +34,8 @@ struct DevState {
   double hlast;   // last h_{j+1,j}
   int nseg;       // batched form: partial-sum slots written by this step's passes
   int seg0;       // batched form: first workgroup of this step's passes on the stream
-  double pad1;
+  int pers;       // batched form: this step is run by the persistent step kernel
+  int pad1;
 };
 
 // Pass modes of the fused row kernel.
@@ -81,6 +82,17 @@ struct SmallArgs {
   int j;           // basis size before this push (host's expectation)
 };
 
+// Persistent step: one work item = one chunk of panels of one stream in one
+// pass; the same table serves passes A, B and C.
+struct alignas(32) PersistTask {
+  int s;      // stream
+  int chunk;  // chunk index within the stream (its partial-sum slot)
+  int m;      // chunks of the stream
+  int cp;     // panels per chunk
+  int j;      // basis columns of the stream at this step
+  int pad[3];
+};
+
 // ---- batched form ----------------------------------------------------------
 // Per-stream descriptor (device memory).
 struct BatchStream {
@@ -116,7 +128,26 @@ struct BatchArgs {
   int cols_per_qw;           // basis columns per unit of tile width
   int gridb[NBUCKET];        // workgroups of the row-pass launches of bucket k
   int min_seg;               // fewest panels per workgroup
+  // persistent step (streams with 1..kPersistCols basis columns, FP32 basis):
+  PersistTask *p_task;       // one per chunk of a pass, streams in order
+  int *p_sync;               // 4 per stream: chunks done in passes A, B, C; passes reduced
+  int *p_ctl;                // kCtlInts control words (layout below)
+  int p_unit;                // panels per chunk at 64 basis columns (scaled by 64/(j+1), at least kMinChunk)
+  int p_groups;              // work queues, one per XCD the device showed (1..kMaxGroups)
+  uint64_t p_xmap;           // queue of each XCD id, 4 bits per id (15: none)
 };
+// Persistent step: widest basis it takes (FP32 tiles of up to 8 groups of
+// 8 wavefronts x 4 columns) and the smallest chunk (bounds the partial slots).
+constexpr int kPersistCols = 256;
+constexpr int kMinChunk = 4;
+// Persistent-step control words: [1] chunks per pass (all queues), [3]
+// error flag (a wait ran out, or a queue was left unfinished), [4]
+// workgroups done, [5] XCD-id mask of the probe; from kCtlGroup0, per queue:
+// next item, chunks per pass, first chunk, streams, streams completed.
+constexpr int kMaxGroups = 8;
+constexpr int kCtlErr = 3, kCtlExit = 4, kCtlProbe = 5;
+constexpr int kCtlGroup0 = 8, kCtlGroupStride = 8;
+constexpr int kCtlInts = kCtlGroup0 + kCtlGroupStride * kMaxGroups;
 
 // ---- blocked form ------------------------------------------------------------
 constexpr int BPK = 4;  // snapshots per block
@@ -187,6 +218,12 @@ int pick_qw(int j, int cols_per_qw);
 
 // batched form (one call per kernel of a step; all captured in one graph)
 hipError_t launch_batch_plan(const BatchArgs &b, hipStream_t s);
+hipError_t launch_persist_plan(const BatchArgs &b, hipStream_t s);
+hipError_t launch_tune_states(const BatchArgs &b, int t, hipStream_t s);
+hipError_t launch_step_persist(bool tx_f64, int grid, const BatchArgs &b, hipStream_t s);
+int step_persist_occupancy();
+// ORs 1 << (XCD id) into *mask from `blocks` one-wavefront workgroups
+hipError_t launch_xcc_probe(unsigned *mask, int blocks, hipStream_t s);
 // row pass of bucket k (0: the first push of a stream, PM_INIT)
 hipError_t launch_batch_pass(int mode, bool tv_f64, bool tx_f64, int k, int grid, const BatchArgs &b,
                              hipStream_t s);

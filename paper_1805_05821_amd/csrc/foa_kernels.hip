@@ -35,7 +35,8 @@ namespace foa {
 template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(pass_waves<TV, QW>()))) void k_pass(PassArgs a) {
   if (a.st->status != ST_ACTIVE) return;
-  row_pass_body<TV, TX, NW, QW, MODE, PREF>(a, blockIdx.x, a.P, gridDim.x, blockIdx.x);
+  __shared__ double lds[pass_lds_doubles<TV, NW, QW, MODE>()];
+  row_pass_body<TV, TX, NW, QW, MODE, PREF>(a, blockIdx.x, a.P, gridDim.x, blockIdx.x, lds);
 }
 
 template <int MODE>

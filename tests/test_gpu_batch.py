@@ -178,3 +178,113 @@ def test_batch_views_modes_and_tune_table(tmp_path):
     assert ei.value.code == F.FOA_E_STATE
     bt.close()
     bt2.close()
+
+
+def _forced_table(Xs, prec, tmp_path, persist, unit, name):
+    """A tune table whose entry for this batch forces one configuration
+    (the key comes from a first, tuned batch of the same shape)."""
+    import json
+
+    path = str(tmp_path / f"{name}.json")
+    bt, _, _ = _run_batch(Xs, prec, steps=2, nmax=[X.shape[1] for X in Xs], tune=path)  # same key
+    bt.close()
+    table = json.load(open(path))
+    e = table["entries"][0]
+    e.update(persist=int(persist), unit_panels=int(unit))
+    json.dump({"entries": [e]}, open(path, "w"))
+    return path
+
+
+def _streams_wide(seed=11):
+    """Mixed widths for the persistent step: most streams at most 256
+    columns, one beyond (taken by the bucket launches in persistent mode),
+    ragged n, one stream longer than one work item."""
+    Xs = _streams(S=6, seed=seed)
+    w = datagen.get_workload("noisy_2p20x200")
+    Xw, _, _ = datagen.snapshots_numpy(w.with_n(1500).with_N(290), dtype="float64")
+    Xl, _, _ = datagen.snapshots_numpy(w.with_n(64 * 300 + 17).with_N(40), dtype="float64")
+    return Xs + [Xw, Xl]
+
+
+@pytest.mark.parametrize("unit", [8, 64])
+def test_batch_persistent_f32_within_bound(tmp_path, unit):
+    """Persistent step (one launch for the streams of up to 256 columns):
+    every stream within the FP32 bound of the oracle; the run leaves the
+    wait-error flag clear (sync returns without error)."""
+    Xs = _streams_wide()
+    nmax = [X.shape[1] for X in Xs]
+    table = _forced_table(Xs, "f32", tmp_path, True, unit, "p")
+    bt, q, st = _run_batch(Xs, "f32", tune=table)
+    for s, X in enumerate(Xs):
+        ref = oracle.foa_batch(X)
+        H, B, qq, m, V = _view_state(bt, s)
+        assert qq == ref.q == nmax[s]
+        kap = kappa_of(ref.beta[:m, :m])
+        eH = np.linalg.norm(H[:m, :m] - ref.H[:m, :m], 2) / np.linalg.norm(ref.H[:m, :m], 2)
+        orth = np.linalg.norm(np.eye(qq) - V.T @ V, 2)
+        announce(f"persistent unit {unit} stream {s}: n={X.shape[0]} q={qq} kappa={kap:.1e} relH2={eH:.1e} orth={orth:.1e}")
+        assert eH <= 10 * EPS32 * kap
+        assert orth <= 10 * np.sqrt(qq) * EPS32
+    bt.close()
+
+
+def test_batch_persistent_replays_and_matches_buckets(tmp_path):
+    """Two persistent batches with the same configuration give bitwise-equal
+    results (partial sums go to slot = work item, whichever workgroup ran
+    it); the bucket launches give the same results to rounding."""
+    Xs = _streams_wide(seed=12)
+    tp = _forced_table(Xs, "f32", tmp_path, True, 16, "p")
+    tb = _forced_table(Xs, "f32", tmp_path, False, 16, "b")
+    a, qa, _ = _run_batch(Xs, "f32", tune=tp)
+    b, qb, _ = _run_batch(Xs, "f32", tune=tp)
+    c, qc, _ = _run_batch(Xs, "f32", tune=tb)
+    assert np.array_equal(qa, qb) and np.array_equal(qa, qc)
+    for s in range(len(Xs)):
+        Ha, Ba, _, m, _ = _view_state(a, s)
+        Hb, Bb, _, _, _ = _view_state(b, s)
+        Hc, Bc, _, _, _ = _view_state(c, s)
+        assert np.array_equal(Ha, Hb) and np.array_equal(Ba, Bb)
+        assert np.abs(Ha[:, :m] - Hc[:, :m]).max() <= 1e-5 * np.abs(Hc[:, :m]).max()
+    a.close()
+    b.close()
+    c.close()
+
+
+def test_batch_persistent_capacity_idle_and_nonfinite(tmp_path):
+    """Persistent step with a stream past its capacity, idle steps and a
+    non-finite snapshot: the same outcomes as the bucket launches."""
+    import json
+
+    import torch
+
+    from paper_1805_05821_amd import foa as F
+    from paper_1805_05821_amd.stream import FOABatch
+
+    Xs = _streams(S=3, seed=6)
+    Xs[1] = Xs[1].copy()
+    Xs[1][17, 4] = np.nan
+    n = [X.shape[0] for X in Xs]
+    N = [X.shape[1] for X in Xs]
+    nmax = [5, N[1], N[2]]
+    path = str(tmp_path / "t.json")
+    FOABatch(n, nmax, prec="f32", tune_table=path).close()
+    table = json.load(open(path))
+    table["entries"][0].update(persist=1, unit_panels=8)
+    json.dump(table, open(path, "w"))
+    dev = [torch.from_numpy(np.ascontiguousarray(X.T)).cuda() for X in Xs]
+    bt = FOABatch(n, nmax, prec="f32", tune_table=path)
+    for k in range(max(N)):
+        xs = [dev[s][k] if k < N[s] else None for s in range(3)]
+        if k % 3 == 1:
+            xs[2] = None
+        bt.push(xs)
+    q, st = bt.sync()
+    assert q[0] == 5 and st[0] == F.FOA_E_CAPACITY
+    assert q[1] == 4 and st[1] == F.FOA_E_NONFINITE
+    fed = [k for k in range(N[2]) if k % 3 != 1]
+    ref = oracle.foa_batch(Xs[2][:, fed])
+    H, B, qq, m, V = _view_state(bt, 2)
+    kap = kappa_of(ref.beta[:m, :m])
+    eH = np.linalg.norm(H[:m, :m] - ref.H[:m, :m], 2) / np.linalg.norm(ref.H[:m, :m], 2)
+    assert qq == ref.q and st[2] == 0 and eH <= 10 * EPS32 * kap
+    bt.close()
