@@ -31,7 +31,6 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kMinUnitPanels = 4;                 // smallest range: sizes the partial slots
 constexpr int kUnitCandidates[] = {4, 16, 64};    // bucket mode: smallest range (panels)
-constexpr int kChunkCandidates[] = {16, 32, 64, 128};  // persistent mode: panels per work item at 64 columns
 constexpr int kTuneSamples = 8;                      // basis sizes timed per configuration
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -41,8 +40,7 @@ struct BatchLayout {
   std::vector<Layout> L;
   size_t states = 0, streams = 0, xptrs = 0, rblk_s = 0, rblk_c = 0, tune_x = 0, total = 0;
   size_t plist = 0, ppre = 0, pfirst = 0, pmeta = 0, pspos = 0;
-  size_t qtask = 0, qsync = 0, qctl = 0;  // persistent step
-  size_t qtasks = 0;                       // capacity of the work-item table
+  size_t qlist = 0, qpre = 0, qsgrp = 0, qfirst = 0, qctl = 0;  // persistent step
   size_t rblocks = 0;
   int64_t max_n = 0;
   int max_nmax = 0;
@@ -62,7 +60,6 @@ BatchLayout batch_layout(int S, const int64_t *n, const int32_t *n_max, foa_prec
     B.rblocks += (size_t)(n_max[s] + 1 + 3) / 4;
     B.max_n = std::max<int64_t>(B.max_n, n[s]);
     B.max_nmax = std::max<int>(B.max_nmax, n_max[s]);
-    B.qtasks += (size_t)((P + kMinChunk - 1) / kMinChunk);
   }
   auto take = [&](size_t bytes) {
     const size_t r = o;
@@ -76,8 +73,10 @@ BatchLayout batch_layout(int S, const int64_t *n, const int32_t *n_max, foa_prec
   B.pfirst = take((size_t)NBUCKET * kMaxBatchGrid * sizeof(int));
   B.pmeta = take((size_t)NBUCKET * 2 * sizeof(int));
   B.pspos = take((size_t)S * sizeof(int));
-  B.qtask = take(B.qtasks * sizeof(PersistTask));
-  B.qsync = take((size_t)4 * S * sizeof(int));
+  B.qlist = take((size_t)S * sizeof(int));
+  B.qpre = take((size_t)(S + 1) * sizeof(int64_t));
+  B.qsgrp = take((size_t)S * sizeof(int));
+  B.qfirst = take((size_t)kMaxGroups * kMaxRanks * sizeof(int));
   B.qctl = take(kCtlInts * sizeof(int));
   B.xptrs = take((size_t)S * sizeof(void *));
   B.rblk_s = take(B.rblocks * sizeof(int));
@@ -146,7 +145,7 @@ foa_status upload_config(foa_batch_s *b, int unit_panels) {
   if (e != hipSuccess) return FOA_E_DEVICE;
   b->unit_panels = unit_panels;
   b->args.min_seg = unit_panels;
-  b->args.p_unit = std::max(unit_panels, kMinChunk);
+  b->args.p_unit = std::max(unit_panels, kMinUnitPanels);
   // every bucket gets at least the tuned grid, and at least one workgroup
   // per resident slot of its kernel
   for (int k = 0; k < NBUCKET; ++k) {
@@ -352,8 +351,13 @@ foa_status probe_xcds(foa_batch_s *b) {
       map = (map & ~(0xFull << (4 * id))) | ((uint64_t)g << (4 * id));
       ++g;
     }
+  // workgroups per XCD: the resident complement of the launch, split evenly
+  const int ranks = std::min(b->pgrid / g, kMaxRanks);
+  if (ranks < 1) return FOA_OK;
   b->args.p_groups = g;
   b->args.p_xmap = map;
+  b->args.p_ranks = ranks;
+  b->pgrid = ranks * g;
   return FOA_OK;
 }
 
@@ -392,7 +396,7 @@ foa_status tune(foa_batch_s *b) {
     for (int gm : {1, 2, 4})
       if ((r = consider(unit, gm * b->cus, false)) != FOA_OK) return r;
   if (b->prec == FOA_PREC_F32 && b->args.p_groups > 0)
-    for (int unit : kChunkCandidates)
+    for (int unit : kUnitCandidates)
       if ((r = consider(unit, 2 * b->cus, true)) != FOA_OK) return r;
   b->tuned_ms = best;
   if ((r = apply_config(b, bu, bg, bp != 0)) != FOA_OK) return r;
@@ -473,8 +477,10 @@ foa_status foa_batch_init(foa_batch *out, int32_t S, const int64_t *n, const int
   b->args.first = reinterpret_cast<int *>(b->ws + b->B.pfirst);
   b->args.meta = reinterpret_cast<int *>(b->ws + b->B.pmeta);
   b->args.spos = reinterpret_cast<int *>(b->ws + b->B.pspos);
-  b->args.p_task = reinterpret_cast<PersistTask *>(b->ws + b->B.qtask);
-  b->args.p_sync = reinterpret_cast<int *>(b->ws + b->B.qsync);
+  b->args.p_list = reinterpret_cast<int *>(b->ws + b->B.qlist);
+  b->args.p_pre = reinterpret_cast<int64_t *>(b->ws + b->B.qpre);
+  b->args.p_sgrp = reinterpret_cast<int *>(b->ws + b->B.qsgrp);
+  b->args.p_first = reinterpret_cast<int *>(b->ws + b->B.qfirst);
   b->args.p_ctl = reinterpret_cast<int *>(b->ws + b->B.qctl);
   b->args.cols_per_qw = batch_cols_per_qw(prec == FOA_PREC_F64);
   b->args.xptrs = reinterpret_cast<const void *const *>(b->ws + b->B.xptrs);

@@ -364,31 +364,29 @@ hipError_t launch_batch_pass(int mode, bool tv_f64, bool tx_f64, int k, int grid
 // ---------------------------------------------------------------------------
 // Persistent step: one launch runs passes A, B and C, their reductions, the
 // finalize and the next partial beta column of every stream whose basis has
-// 1..kPersistCols columns.  Work items are (pass, stream, chunk of panels).
+// 1..kPersistCols columns.
 //
-// Queues: the streams are split into one contiguous group per XCD (by chunk
-// count, so by bytes: chunks hold about the same bytes at every basis width,
-// panels scale with 64/(j+1)), and a workgroup takes items only from the
-// queue of the XCD it runs on (hardware XCC id).  Every exchange between
-// workgroups of one stream -- chunk partials, reduced coefficients, the
-// work vectors -- therefore stays inside one L2, where a release is the
-// completion of the stores (the vector L1 writes through) and an acquire is
-// an invalidation of the L1; no L2 write-back or invalidation is needed
-// until the kernel ends.
+// Groups: the streams are split into one contiguous group per XCD, balanced
+// by bytes (panels x (j + 1)), and a workgroup works only on the group of
+// the XCD it runs on (hardware XCC id), so each barrier involves the
+// workgroups of one XCD.  Partial sums, reduced coefficients and the other
+// values handed between workgroups inside the launch are stored and loaded
+// at device scope (they bypass the non-coherent caches; a plain store is
+// not seen by a workgroup on the same XCD that holds the line in its L2),
+// so a barrier needs no cache write-back or invalidation.
 //
-// Within a queue, items are numbered pass-major and taken from an atomic
-// counter; each workgroup fetches its next item while it runs the current
-// one.  A pass B or C item waits until its stream's previous pass is
-// reduced; the items of that pass have smaller numbers, so they were taken
-// earlier by running workgroups of the same XCD, and a workgroup only ever
-// holds items in increasing order: the smallest unfinished item always has
-// every dependency done, so every wait ends.  The workgroup that finishes a
-// stream's last chunk of a pass reduces the pass (after C: finalize and the
-// next b).  Partial sums go to slot = chunk, reduced in slot order, so the
-// results do not depend on which workgroup ran what.  Waits are bounded,
-// and the last workgroup to finish checks that every queue completed all of
-// its streams (a queue whose XCD received no workgroup would not): either
-// failure sets the error flag, which the host reports as a device error.
+// Phases, as in the bucket launches but separated by group barriers instead
+// of kernel boundaries: pass A | reduce A | pass B | reduce B | pass C |
+// finalize + next b.  In a pass, the group's concatenated panels are cut
+// into G equal contiguous ranges (G = min(workgroups per XCD, panels /
+// min_seg)); the workgroup of arrival rank r on its XCD takes range r and
+// writes its partial sums for a stream to slot r - seg0 of that stream.
+// Reductions take (stream, 8-column block) tasks r, r + G, ...; finalize and
+// next b take streams r, r + G, ...  A barrier waits until all G ranks have
+// finished the phase.  Ranks need G workgroups on the XCD, resident at once
+// (the launch is sized to the resident complement); waits are bounded, and
+// the last workgroup to finish checks that every group finalized all its
+// streams: either failure sets the error flag, which the host reports.
 // ---------------------------------------------------------------------------
 
 __device__ inline int xcc_id() {
@@ -400,138 +398,203 @@ __global__ void k_xcc_probe(unsigned *mask) {
   if (threadIdx.x == 0) atomicOr(mask, 1u << xcc_id());
 }
 
-// Plan of the persistent step, one workgroup, two sweeps over the streams:
-// the total chunk count, then the chunk descriptors in stream order, the
-// queue of each stream and each queue's range; sync words reset.
+__device__ inline bool persist_eligible(const DevState *st) {
+  return st->act && st->jstep >= 1 && st->jstep <= kPersistCols;
+}
+
+// Plan of the persistent step, one workgroup, three sweeps over the streams:
+// totals; the eligible list (stream order) with its panel prefix and the
+// group of each stream (by the middle of its byte range); per stream its
+// ranks (seg0, nseg), per group and rank its first list position.
 __global__ __launch_bounds__(1024) void k_persist_plan(BatchArgs b) {
-  __shared__ int s_wsum[16];
-  __shared__ int s_base, s_total;
-  __shared__ int s_glo[kMaxGroups], s_ghi[kMaxGroups], s_gcnt[kMaxGroups];
+  __shared__ int s_wc[16];
+  __shared__ int64_t s_wp[16], s_ww[16];
+  __shared__ int s_cbase;
+  __shared__ int64_t s_pbase, s_wbase, s_wtot;
+  __shared__ int s_glo[kMaxGroups], s_ghi[kMaxGroups], s_gj[kMaxGroups];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int G = b.p_groups;
+  const int NG = b.p_groups;
+  int *ctl = b.p_ctl;
   if (tid < kMaxGroups) {
     s_glo[tid] = INT_MAX;
     s_ghi[tid] = 0;
-    s_gcnt[tid] = 0;
+    s_gj[tid] = 0;
   }
-  if (tid == 0) s_total = 0;
+  if (tid == 0) s_wtot = 0;
   for (int sweep = 0; sweep < 2; ++sweep) {
-    if (tid == 0) s_base = 0;
+    if (tid == 0) {
+      s_cbase = 0;
+      s_pbase = 0;
+      s_wbase = 0;
+    }
     __syncthreads();
     for (int c0 = 0; c0 < b.S; c0 += 1024) {
       const int s = c0 + tid;
-      int m = 0, chunk = kMinChunk, j = 0;
+      int f = 0, j = 0;
+      int64_t P = 0, w = 0;
       if (s < b.S) {
         const BatchStream &d = b.streams[s];
-        const DevState *st = d.st;
-        j = st->jstep;
-        if (st->act && j >= 1 && j <= kPersistCols) {
-          const int c = (int)((64LL * b.p_unit) / (j + 1));
-          chunk = c > kMinChunk ? c : kMinChunk;
-          m = (int)((d.P + chunk - 1) / chunk);
+        if (persist_eligible(d.st)) {
+          f = 1;
+          j = d.st->jstep;
+          P = d.P;
+          w = P * (j + 1);
         }
       }
-      int mi = m;
+      int fi = f;
+      int64_t pi = P, wi = w;
 #pragma unroll
       for (int o = 1; o < 64; o <<= 1) {
-        const int tm = __shfl_up(mi, o, 64);
-        if (lane >= o) mi += tm;
-      }
-      if (lane == 63) s_wsum[wave] = mi;
-      __syncthreads();
-      if (sweep == 1 && s < b.S) {
-        int *sy = b.p_sync + 4 * (size_t)s;
-        sy[0] = 0;
-        sy[1] = 0;
-        sy[2] = 0;
-        sy[3] = 0;
-        if (m > 0) {
-          int wm = 0;
-          for (int w = 0; w < wave; ++w) wm += s_wsum[w];
-          const int first = s_base + wm + mi - m;
-          int g = (int)(((2LL * first + m) * G) / (2LL * s_total));  // queue of the stream's middle chunk
-          g = g < G - 1 ? g : G - 1;
-          b.streams[s].st->pers = 1;
-          for (int c = 0; c < m; ++c) {
-            PersistTask tk{};
-            tk.s = s;
-            tk.chunk = c;
-            tk.m = m;
-            tk.cp = chunk;
-            tk.j = j;
-            b.p_task[first + c] = tk;
-          }
-          atomicMin(&s_glo[g], first);
-          atomicMax(&s_ghi[g], first + m);
-          atomicAdd(&s_gcnt[g], 1);
+        const int tf = __shfl_up(fi, o, 64);
+        const int64_t tp = __shfl_up(pi, o, 64), tw = __shfl_up(wi, o, 64);
+        if (lane >= o) {
+          fi += tf;
+          pi += tp;
+          wi += tw;
         }
+      }
+      if (lane == 63) {
+        s_wc[wave] = fi;
+        s_wp[wave] = pi;
+        s_ww[wave] = wi;
+      }
+      __syncthreads();
+      if (sweep == 1 && f) {
+        int wc = 0;
+        int64_t wp = 0, ww = 0;
+        for (int q = 0; q < wave; ++q) {
+          wc += s_wc[q];
+          wp += s_wp[q];
+          ww += s_ww[q];
+        }
+        const int pos = s_cbase + wc + fi - 1;
+        const int64_t pfirst = s_pbase + wp + pi - P;
+        const int64_t wfirst = s_wbase + ww + wi - w;
+        int g = (int)(((2 * wfirst + w) * NG) / (2 * s_wtot));  // group of the stream's middle byte
+        g = g < NG - 1 ? g : NG - 1;
+        b.p_list[pos] = s;
+        b.p_pre[pos] = pfirst;
+        b.p_sgrp[pos] = g;
+        b.streams[s].st->pers = 1;
+        atomicMin(&s_glo[g], pos);
+        atomicMax(&s_ghi[g], pos + 1);
+        atomicMax(&s_gj[g], j);
       }
       __syncthreads();
       if (tid == 0) {
-        int t = 0;
-        for (int w = 0; w < 16; ++w) t += s_wsum[w];
-        s_base += t;
+        int tc = 0;
+        int64_t tp = 0, tw = 0;
+        for (int q = 0; q < 16; ++q) {
+          tc += s_wc[q];
+          tp += s_wp[q];
+          tw += s_ww[q];
+        }
+        s_cbase += tc;
+        s_pbase += tp;
+        s_wbase += tw;
       }
       __syncthreads();
     }
-    if (tid == 0) s_total = s_base;
+    if (tid == 0) {
+      s_wtot = s_wbase;
+      if (sweep == 1) b.p_pre[s_cbase] = s_pbase;
+    }
     __syncthreads();
   }
+  // per group: list range, panels, ranks, column blocks; counters reset
+  const int W = b.p_ranks;
   if (tid < kMaxGroups) {
-    int *gc = b.p_ctl + kCtlGroup0 + kCtlGroupStride * tid;
-    const int lo = s_glo[tid], hi = s_ghi[tid];
-    gc[0] = 0;                       // next item
-    gc[1] = lo < hi ? hi - lo : 0;   // chunks per pass
-    gc[2] = lo < hi ? lo : 0;        // first chunk
-    gc[3] = s_gcnt[tid];             // streams
-    gc[4] = 0;                       // streams completed
+    int *gc = ctl + kCtlGroup0 + kCtlGroupStride * tid;
+    const int lo = s_glo[tid] < s_ghi[tid] ? s_glo[tid] : 0;
+    const int hi = s_glo[tid] < s_ghi[tid] ? s_ghi[tid] : 0;
+    const int64_t T = b.p_pre[hi] - b.p_pre[lo];
+    int G = 0;
+    if (hi > lo && tid < NG) {
+      const int64_t gg = T / b.p_unit;
+      G = (int)(gg < 1 ? 1 : (gg > W ? W : gg));
+    }
+    gc[kGcLo] = lo;
+    gc[kGcCnt] = hi - lo;
+    gc[kGcRanks] = G;
+    gc[kGcBlocks] = (s_gj[tid] + 1 + kPersistNW - 1) / kPersistNW;
+    gc[kGcArrive] = 0;
+    for (int q = 0; q < kGcPhases; ++q) gc[kGcBar + q] = 0;
+    gc[kGcDone] = 0;
   }
   if (tid == 0) {
-    b.p_ctl[1] = s_total;
-    b.p_ctl[kCtlExit] = 0;
+    ctl[kCtlExit] = 0;
+    ctl[kCtlStreams] = s_cbase;
+  }
+  __syncthreads();
+  // per eligible stream: its ranks; per (group, rank): first list position
+  const int E = s_cbase;
+  for (int pos = tid; pos < E; pos += 1024) {
+    const int g = b.p_sgrp[pos];
+    const int *gc = ctl + kCtlGroup0 + kCtlGroupStride * g;
+    const int lo = gc[kGcLo], G = gc[kGcRanks];
+    const int64_t base = b.p_pre[lo], T = b.p_pre[lo + gc[kGcCnt]] - base;
+    const int64_t p0 = b.p_pre[pos] - base, p1 = b.p_pre[pos + 1] - base;
+    DevState *st = b.streams[b.p_list[pos]].st;
+    const int g0 = (int)(((p0 + 1) * G - 1) / T);
+    const int g1 = (int)((p1 * G - 1) / T);
+    st->seg0 = g0;
+    st->nseg = g1 - g0 + 1;
+  }
+  for (int q = tid; q < NG * kMaxRanks; q += 1024) {
+    const int g = q / kMaxRanks, r = q - g * kMaxRanks;
+    const int *gc = ctl + kCtlGroup0 + kCtlGroupStride * g;
+    const int G = gc[kGcRanks];
+    if (r >= G) continue;
+    const int lo = gc[kGcLo], cnt = gc[kGcCnt];
+    const int64_t base = b.p_pre[lo], T = b.p_pre[lo + cnt] - base;
+    const int64_t start = base + (int64_t)r * T / G;
+    int a = lo, c = lo + cnt - 1;  // largest list position i with pre[i] <= start
+    while (a < c) {
+      const int m = (a + c + 1) / 2;
+      if (b.p_pre[m] <= start)
+        a = m;
+      else
+        c = m - 1;
+    }
+    b.p_first[q] = a;
   }
 }
 
-constexpr int kPersistNW = 8;
 constexpr int kPersistThreads = kPersistNW * 64;
 constexpr int kPersistSpin = 1 << 22;  // polls of a wait before it gives up
 
-// Release / acquire between workgroups on one XCD.  Release: every wavefront
-// waits until its stores are complete in L2, then the workgroup syncs.
-// Acquire: one lane invalidates the CU's vector L1 (shared by the whole
-// workgroup), then the workgroup syncs; later loads read L2.
-__device__ inline void wg_release_xcd() {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-}
-__device__ inline void wg_acquire_xcd() {
-  if (threadIdx.x == 0) {
-    asm volatile("buffer_inv sc0" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(0);
-  }
+// Everything one workgroup hands to another inside the launch goes through
+// device-scope stores and loads (xst / xld), so a barrier needs no cache
+// maintenance: release = every wavefront waits until its stores are
+// complete (the asm statement also keeps the compiler from moving stores
+// past it), then the workgroup syncs.
+__device__ inline void wg_release() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 }
 
-// Wait (one lane polls, relaxed, with sleeps) until *flag >= want; false,
-// with the error flag set, at the bound or when an earlier wait already
-// failed.  Acquire on success.
-__device__ inline bool persist_wait(int *flag, int want, int *err, int *s_ok) {
+// Group barrier: this workgroup's phase is done (release, count), then wait
+// (one lane polls, relaxed, with sleeps) until all G ranks have counted.
+// False, with the error flag set, at the bound or when an earlier wait
+// already failed.
+__device__ inline bool group_barrier(int *cnt, int G, int *err, int *s_ok) {
+  wg_release();
   if (threadIdx.x == 0) {
+    atomicAdd(cnt, 1);
     int ok = 0;
     for (int it = 0; it < kPersistSpin; ++it) {
-      if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) {
+      if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= G) {
         ok = 1;
         break;
       }
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-      __builtin_amdgcn_s_sleep(8);
+      __builtin_amdgcn_s_sleep(2);
     }
     if (!ok) atomicOr(err, 1);
     *s_ok = ok;
   }
   __syncthreads();
   const int ok = *s_ok;
-  if (ok) wg_acquire_xcd();  // the reduced coefficients are read after this
   __syncthreads();
   return ok != 0;
 }
@@ -542,10 +605,48 @@ __device__ inline void persist_pass(int qw, const PassArgs &a, int64_t lo, int64
                     pass_lds_doubles<float, kPersistNW, 1, MODE>() <= pass_lds_doubles<float, kPersistNW, 8, PM_C>(),
                 "persistent step LDS");
   switch (qw) {
-    case 1: row_pass_body<float, TX, kPersistNW, 1, MODE, true>(a, lo, hi, 1, slot, lds); break;
-    case 2: row_pass_body<float, TX, kPersistNW, 2, MODE, true>(a, lo, hi, 1, slot, lds); break;
-    case 4: row_pass_body<float, TX, kPersistNW, 4, MODE, true>(a, lo, hi, 1, slot, lds); break;
-    default: row_pass_body<float, TX, kPersistNW, 8, MODE, true>(a, lo, hi, 1, slot, lds); break;
+    case 1: row_pass_body<float, TX, kPersistNW, 1, MODE, true, true>(a, lo, hi, 1, slot, lds); break;
+    case 2: row_pass_body<float, TX, kPersistNW, 2, MODE, true, true>(a, lo, hi, 1, slot, lds); break;
+    case 4: row_pass_body<float, TX, kPersistNW, 4, MODE, true, true>(a, lo, hi, 1, slot, lds); break;
+    default: row_pass_body<float, TX, kPersistNW, 8, MODE, true, true>(a, lo, hi, 1, slot, lds); break;
+  }
+}
+
+// Range `rank` of the group's concatenated panels, pass MODE.
+template <typename TX, int MODE>
+__device__ inline void persist_range(const BatchArgs &b, const int *gc, int rank, int g, double *lds) {
+  const int lo_pos = uniform(gc[kGcLo]), cnt = uniform(gc[kGcCnt]), G = uniform(gc[kGcRanks]);
+  const int64_t base = uniform(b.p_pre[lo_pos]);
+  const int64_t T = uniform(b.p_pre[lo_pos + cnt]) - base;
+  int64_t lo = base + (int64_t)rank * T / G;
+  const int64_t hi = base + (int64_t)(rank + 1) * T / G;
+  int i = uniform(b.p_first[g * kMaxRanks + rank]);
+  while (lo < hi) {
+    const int s = uniform(b.p_list[i]);
+    const int64_t ps = uniform(b.p_pre[i]), pe = uniform(b.p_pre[i + 1]);
+    const int64_t e = pe < hi ? pe : hi;
+    const BatchStream &d = b.streams[s];
+    const DevState *st = uniform(d.st);
+    PassArgs a{};
+    a.W = uniform(d.W);
+    a.x = uniform(b.xptrs[s]);
+    a.w = uniform(d.w);
+    a.coef[0] = uniform(d.coefA);
+    a.coef[1] = uniform(d.coefB);
+    a.coef[2] = uniform(d.coefC);
+    a.st = st;
+    a.part = uniform(d.part);
+    a.partn = uniform(d.partn);
+    a.n = uniform(d.n);
+    a.P = uniform(d.P);
+    a.j = uniform(st->jstep);
+    a.n_max = uniform(d.n_max);
+    a.ldg = uniform(d.ldg);
+    const int j = a.j;
+    const int qw = j <= 32 ? 1 : (j <= 64 ? 2 : (j <= 128 ? 4 : 8));
+    persist_pass<TX, MODE>(qw, a, lo - ps, e - ps, rank - uniform(st->seg0), lds);
+    lo = e;
+    ++i;
   }
 }
 
@@ -553,96 +654,68 @@ template <typename TX>
 __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_step_persist(BatchArgs b) {
   __shared__ double lds[pass_lds_doubles<float, kPersistNW, 8, PM_C>()];
-  __shared__ int s_t, s_last, s_ok;
+  __shared__ int s_rank, s_ok;
   int *ctl = b.p_ctl;
+  int *err = ctl + kCtlErr;
   const int g = (int)((b.p_xmap >> (4 * xcc_id())) & 15);
   if (g < b.p_groups) {
     int *gc = ctl + kCtlGroup0 + kCtlGroupStride * g;
-    const int M = uniform(gc[1]);
-    const int base = uniform(gc[2]);
-    if (threadIdx.x == 0) s_t = atomicAdd(gc, 1);
+    const int G = uniform(gc[kGcRanks]);
+    if (threadIdx.x == 0) s_rank = atomicAdd(gc + kGcArrive, 1);
     __syncthreads();
-    int t = uniform(s_t);
-    while (t < 3 * M) {
-      __syncthreads();  // every wavefront has read s_t
-      int nxt = 0;      // the next work item, fetched while this one runs
-      if (threadIdx.x == 0) nxt = atomicAdd(gc, 1);
-      const int ph = t / M;
-      const PersistTask *tp = b.p_task + base + (t - ph * M);
-      const int s = uniform(tp->s);
-      const int chunk = uniform(tp->chunk);
-      const int m = uniform(tp->m);
-      const int cp = uniform(tp->cp);
-      const int j = uniform(tp->j);
-      int *sy = b.p_sync + 4 * (size_t)s;
-      if (ph == 0 || persist_wait(sy + 3, ph, ctl + kCtlErr, &s_ok)) {
-        const BatchStream &d = b.streams[s];
-        const DevState *st = uniform(d.st);
-        PassArgs a{};
-        a.W = uniform(d.W);
-        a.x = uniform(b.xptrs[s]);
-        a.w = uniform(d.w);
-        a.coef[0] = uniform(d.coefA);
-        a.coef[1] = uniform(d.coefB);
-        a.coef[2] = uniform(d.coefC);
-        a.st = st;
-        a.part = uniform(d.part);
-        a.partn = uniform(d.partn);
-        a.n = uniform(d.n);
-        a.P = uniform(d.P);
-        a.j = j;
-        a.n_max = uniform(d.n_max);
-        a.ldg = uniform(d.ldg);
-        const int qw = j <= 32 ? 1 : (j <= 64 ? 2 : (j <= 128 ? 4 : 8));
-        const int64_t plo = (int64_t)chunk * cp;
-        const int64_t phi = plo + cp < a.P ? plo + cp : a.P;
+    const int rank = uniform(s_rank);
+    if (rank < G) {
+      const int lo_pos = uniform(gc[kGcLo]), cnt = uniform(gc[kGcCnt]), CB = uniform(gc[kGcBlocks]);
+      bool ok = true;
+      for (int ph = 0; ph < 3 && ok; ++ph) {
         if (ph == 0)
-          persist_pass<TX, PM_A>(qw, a, plo, phi, chunk, lds);
+          persist_range<TX, PM_A>(b, gc, rank, g, lds);
         else if (ph == 1)
-          persist_pass<TX, PM_B>(qw, a, plo, phi, chunk, lds);
+          persist_range<TX, PM_B>(b, gc, rank, g, lds);
         else
-          persist_pass<TX, PM_C>(qw, a, plo, phi, chunk, lds);
-        wg_release_xcd();  // this chunk's partial sums (and work vectors) before the count
-        if (threadIdx.x == 0) s_last = (atomicAdd(sy + ph, 1) == m - 1) ? 1 : 0;
-        __syncthreads();
-        if (s_last) {
-          wg_acquire_xcd();  // every chunk's partial sums are visible after this
-          SmallArgs sa = small_of(d);
-          sa.G = m;
-          sa.j = j;
-          if (ph == 0) {
-            for (int c = 0; c <= j; c += kPersistNW) reduce_body<1>(sa, c);
-          } else if (ph == 1) {
-            for (int c = 0; c < j; c += kPersistNW) reduce_body<2>(sa, c);
-          } else {
-            finalize_body_t<kPersistThreads>(sa);
+          persist_range<TX, PM_C>(b, gc, rank, g, lds);
+        ok = group_barrier(gc + kGcBar + 2 * ph, G, err, &s_ok);
+        if (!ok || ph == 2) break;
+        // reduce of pass ph: (stream, 8-column block) tasks rank, rank + G, ...
+        for (int t = rank; t < cnt * CB; t += G) {
+          const int i = t / CB, cb = t - i * CB;
+          const BatchStream &d = b.streams[uniform(b.p_list[lo_pos + i])];
+          const SmallArgs sa = small_of(d);
+          if (ph == 0)
+            reduce_body<1, true>(sa, cb * kPersistNW);
+          else
+            reduce_body<2, true>(sa, cb * kPersistNW);
+        }
+        ok = group_barrier(gc + kGcBar + 2 * ph + 1, G, err, &s_ok);
+      }
+      if (ok) {
+        // finalize and next b: streams rank, rank + G, ...
+        for (int i = rank; i < cnt; i += G) {
+          const BatchStream &d = b.streams[uniform(b.p_list[lo_pos + i])];
+          const SmallArgs sa = small_of(d);
+          finalize_body_t<kPersistThreads, true>(sa);
+          __syncthreads();
+          const int J = uniform(d.st->q);
+          for (int c = 0; c * 64 < J; c += kPersistThreads / 256) {
+            nextb_body_t<kPersistThreads>(sa, c);
             __syncthreads();
-            const int J = uniform(d.st->q);
-            for (int c = 0; c * 64 < J; c += kPersistThreads / 256) {
-              nextb_body_t<kPersistThreads>(sa, c);
-              __syncthreads();
-            }
-          }
-          wg_release_xcd();
-          if (threadIdx.x == 0) {
-            __hip_atomic_store(sy + 3, ph + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (ph == 2) atomicAdd(gc + 4, 1);
           }
         }
+        if (threadIdx.x == 0) atomicAdd(gc + kGcDone, 1);
       }
-      if (threadIdx.x == 0) s_t = nxt;
-      __syncthreads();
-      t = uniform(s_t);
     }
   }
-  // the last workgroup to finish checks that every queue completed its streams
+  // the last workgroup to finish checks that every group completed its ranks
+  // (the finished-rank count is complete before the exit count is taken:
+  // two relaxed atomics to different addresses may otherwise land in either
+  // order)
   __syncthreads();
+  if (threadIdx.x == 0) __builtin_amdgcn_s_waitcnt(0);
   if (threadIdx.x == 0 && atomicAdd(ctl + kCtlExit, 1) == (int)gridDim.x - 1) {
     for (int q = 0; q < b.p_groups; ++q) {
       int *gq = ctl + kCtlGroup0 + kCtlGroupStride * q;
-      if (__hip_atomic_load(gq + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
-          __hip_atomic_load(gq + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-        atomicOr(ctl + kCtlErr, 2);
+      if (__hip_atomic_load(gq + kGcDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != gq[kGcRanks])
+        atomicOr(err, 2);
     }
   }
 }

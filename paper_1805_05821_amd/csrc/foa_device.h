@@ -172,7 +172,27 @@ constexpr int pass_lds_doubles() {
 // stream and writes its partial sums to slot `slot`.  Called uniformly by
 // the whole workgroup (it synchronises).  lds: pass_lds_doubles() doubles of
 // the caller's shared memory.
-template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
+// Values exchanged between workgroups inside one launch (partial sums,
+// reduced coefficients): with COH they are stored and loaded at device
+// scope, which writes through and reads past the non-coherent caches, so a
+// barrier needs only store completion and no cache write-back or
+// invalidation.  Without COH (exchange across kernel boundaries) plain.
+template <bool COH>
+__device__ __forceinline__ double xld(const double *p) {
+  if constexpr (COH)
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void xst(double *p, double v) {
+  if constexpr (COH)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+
+template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF, bool COH = false>
 __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart, int64_t pend, int64_t pstep,
                                               int slot, double *lds) {
   // w_A, w_B and w_C are each rounded to FP64 before the next subtraction,
@@ -215,7 +235,7 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
   __syncthreads();  // the previous call of this workgroup may still read LDS
 #pragma unroll
   for (int k = 0; k < NC; ++k)
-    for (int c = tid; c < JCAP; c += NW * 64) s_coef[k][c] = (c < j) ? a.coef[K0 + k][c] : 0.0;
+    for (int c = tid; c < JCAP; c += NW * 64) s_coef[k][c] = (c < j) ? xld<COH>(a.coef[K0 + k] + c) : 0.0;
   const double scale = (MODE == PM_INIT) ? 1.0 : uniform(a.st->scaleA);
   __syncthreads();
 
@@ -388,7 +408,7 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
 #pragma unroll
       for (int m = 1; m < LPC; m <<= 1) v += xor_shfl(v, m);
       const int c = cbase + g * GSTRIDE;
-      if (rg == 0 && c < j) a.part[(size_t)c * a.ldg + slot] = v;
+      if (rg == 0 && c < j) xst<COH>(a.part + (size_t)c * a.ldg + slot, v);
     }
   }
   if (MODE != PM_B) {
@@ -399,7 +419,7 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
     if (tid == 0) {
       double t2 = 0.0;
       for (int w2 = 0; w2 < NW; ++w2) t2 += s_nrm[w2];
-      a.partn[slot] = t2;
+      xst<COH>(a.partn + slot, t2);
     }
   }
 }
@@ -410,34 +430,34 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
 // coefB = sigma o h, and the extra wavefront c == j reduces ||psi||^2.
 // MODE 2 (after pass B): s = sigma o t, h += s (step 13), coefC = sigma o s.
 // ---------------------------------------------------------------------------
-template <int MODE>
+template <int MODE, bool COH = false>
 __device__ inline void reduce_body(const SmallArgs &a, int c0) {
   const int lane = threadIdx.x & 63;
   const int c = c0 + (threadIdx.x >> 6);
   if (c < a.j) {
     const double *pc = a.part + (size_t)c * a.ldg;
     double t = 0.0;
-    for (int g = lane; g < a.G; g += 64) t += pc[g];
+    for (int g = lane; g < a.G; g += 64) t += xld<COH>(pc + g);
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) t += xor_shfl(t, m);
     if (lane == 0) {
       const double sg = a.sigma[c];
       const double v = sg * t;
       if (MODE == 1) {
-        a.h[c] = v;
-        a.coefB[c] = sg * v;
+        xst<COH>(a.h + c, v);
+        xst<COH>(a.coefB + c, sg * v);
       } else {
-        a.s[c] = v;
-        a.h[c] = a.h[c] + v;
-        a.coefC[c] = sg * v;
+        xst<COH>(a.s + c, v);
+        xst<COH>(a.h + c, xld<COH>(a.h + c) + v);
+        xst<COH>(a.coefC + c, sg * v);
       }
     }
   } else if (MODE == 1 && c == a.j) {
     double t = 0.0;
-    for (int g = lane; g < a.G; g += 64) t += a.partn[g];
+    for (int g = lane; g < a.G; g += 64) t += xld<COH>(a.partn + g);
 #pragma unroll
     for (int m = 1; m < 64; m <<= 1) t += xor_shfl(t, m);
-    if (lane == 0) a.st->xn2 = t;
+    if (lane == 0) xst<COH>(&a.st->xn2, t);
   }
 }
 
@@ -459,7 +479,7 @@ __device__ inline double block_sum_t(double t, double *sh) {
 __device__ inline double block_sum_256(double t, double *sh) { return block_sum_t<256>(t, sh); }
 
 // Steps 15-18 plus the breakdown rule; one workgroup of NT threads.
-template <int NT>
+template <int NT, bool COH = false>
 __device__ inline void finalize_body_t(const SmallArgs &a) {
   __shared__ double sh[NT];
   __shared__ int s_status;
@@ -471,15 +491,15 @@ __device__ inline void finalize_body_t(const SmallArgs &a) {
   }
   const int j = a.j;
   double t = 0.0;
-  for (int g = tid; g < a.G; g += NT) t += a.partn[g];
+  for (int g = tid; g < a.G; g += NT) t += xld<COH>(a.partn + g);
   const double wn2 = block_sum_t<NT>(t, sh);
   int bad = 0;
-  for (int i = tid; i < j; i += NT) bad |= !isfinite(a.h[i]);
+  for (int i = tid; i < j; i += NT) bad |= !isfinite(xld<COH>(a.h + i));
   bad = __syncthreads_or(bad);
   const double bjj = a.beta[(size_t)(j - 1) * a.ldB + (j - 1)];
   if (tid == 0) {
     const double hn = sqrt(wn2);
-    const double xn2 = st->xn2;
+    const double xn2 = xld<COH>(&st->xn2);
     int status = ST_ACTIVE;
     if (bad || !isfinite(hn) || !isfinite(xn2)) {
       status = ST_NONFINITE;
@@ -501,7 +521,7 @@ __device__ inline void finalize_body_t(const SmallArgs &a) {
     return;
   }
   for (int i = tid; i < j; i += NT) {
-    const double hi = a.h[i];
+    const double hi = xld<COH>(a.h + i);
     a.H[(size_t)(j - 1) * a.ldH + i] = hi;
     a.beta[(size_t)j * a.ldB + i] = a.bvec[i] + hi * bjj;  // steps 16-18
   }

@@ -82,17 +82,6 @@ struct SmallArgs {
   int j;           // basis size before this push (host's expectation)
 };
 
-// Persistent step: one work item = one chunk of panels of one stream in one
-// pass; the same table serves passes A, B and C.
-struct alignas(32) PersistTask {
-  int s;      // stream
-  int chunk;  // chunk index within the stream (its partial-sum slot)
-  int m;      // chunks of the stream
-  int cp;     // panels per chunk
-  int j;      // basis columns of the stream at this step
-  int pad[3];
-};
-
 // ---- batched form ----------------------------------------------------------
 // Per-stream descriptor (device memory).
 struct BatchStream {
@@ -129,24 +118,31 @@ struct BatchArgs {
   int gridb[NBUCKET];        // workgroups of the row-pass launches of bucket k
   int min_seg;               // fewest panels per workgroup
   // persistent step (streams with 1..kPersistCols basis columns, FP32 basis):
-  PersistTask *p_task;       // one per chunk of a pass, streams in order
-  int *p_sync;               // 4 per stream: chunks done in passes A, B, C; passes reduced
+  int *p_list;               // S: its streams, in stream order
+  int64_t *p_pre;            // S + 1: their panel prefix sums
+  int *p_sgrp;               // S: group of each listed stream
+  int *p_first;              // kMaxGroups x kMaxRanks: first list position of each rank's range
   int *p_ctl;                // kCtlInts control words (layout below)
-  int p_unit;                // panels per chunk at 64 basis columns (scaled by 64/(j+1), at least kMinChunk)
-  int p_groups;              // work queues, one per XCD the device showed (1..kMaxGroups)
-  uint64_t p_xmap;           // queue of each XCD id, 4 bits per id (15: none)
+  int p_unit;                // fewest panels per rank
+  int p_ranks;               // workgroups per XCD in the launch (at most kMaxRanks)
+  int p_groups;              // groups, one per XCD the device showed (1..kMaxGroups)
+  uint64_t p_xmap;           // group of each XCD id, 4 bits per id (15: none)
 };
 // Persistent step: widest basis it takes (FP32 tiles of up to 8 groups of
-// 8 wavefronts x 4 columns) and the smallest chunk (bounds the partial slots).
+// 8 wavefronts x 4 columns) and its workgroup shape.
 constexpr int kPersistCols = 256;
-constexpr int kMinChunk = 4;
-// Persistent-step control words: [1] chunks per pass (all queues), [3]
-// error flag (a wait ran out, or a queue was left unfinished), [4]
-// workgroups done, [5] XCD-id mask of the probe; from kCtlGroup0, per queue:
-// next item, chunks per pass, first chunk, streams, streams completed.
+constexpr int kPersistNW = 8;
+// Persistent-step control words: [2] listed streams, [3] error flag (a
+// wait ran out, or a group left ranks unfinished), [4] workgroups done, [5]
+// XCD-id mask of the probe; from kCtlGroup0, per group (kGc* offsets): its
+// list range, ranks, column blocks of the reductions, arrival counter,
+// phase barrier counters and finished ranks.
 constexpr int kMaxGroups = 8;
-constexpr int kCtlErr = 3, kCtlExit = 4, kCtlProbe = 5;
-constexpr int kCtlGroup0 = 8, kCtlGroupStride = 8;
+constexpr int kMaxRanks = 256;
+constexpr int kCtlStreams = 2, kCtlErr = 3, kCtlExit = 4, kCtlProbe = 5;
+constexpr int kCtlGroup0 = 8, kCtlGroupStride = 16;
+constexpr int kGcLo = 0, kGcCnt = 1, kGcRanks = 2, kGcBlocks = 3, kGcArrive = 4, kGcBar = 5, kGcPhases = 5,
+              kGcDone = 10;
 constexpr int kCtlInts = kCtlGroup0 + kCtlGroupStride * kMaxGroups;
 
 // ---- blocked form ------------------------------------------------------------
