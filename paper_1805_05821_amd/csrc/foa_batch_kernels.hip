@@ -309,7 +309,9 @@ int batch_cols_per_qw(bool tv_f64) { return tv_f64 ? 16 * 2 : 8 * 4; }
 
 // Kernel shape of bucket k (1..5: basis sizes up to 32, 64, 128, 256, 512
 // columns).  FP32 basis: one wavefront with 8 groups for k = 1, 4 wavefronts
-// with 4 and 8 groups for k = 2, 3, then 8 wavefronts with 8 and 16 groups;
+// with 4 and 8 groups for k = 2, 3, then 8 wavefronts with 8 and 16 groups
+// (16 wavefronts of 8 groups, the single push's choice above 256 columns,
+// measured 0.5-1.5% slower here over the whole run);
 // FP64 basis: 16 wavefronts with 1 .. 16 groups, 16 groups without prefetch.
 // Up to 32 columns a panel carries too little data to pay for the
 // cross-wavefront reduction and barriers of a wider workgroup: one-wavefront
