@@ -121,16 +121,17 @@ static hipError_t launch_pass_m(int mode, bool pref, int grid, const PassArgs &a
 
 // Wavefronts per row-pass workgroup.  An FP64 basis always uses 16.  For an
 // FP32 basis nw_opt (4, 8 or 16) if set, else 4 up to 128 columns, 8 up to
-// 256 and 16 beyond: at small basis sizes a panel carries little data and
+// 320 and 16 beyond: at small basis sizes a panel carries little data and
 // the pass is bound by the per-panel barrier and LDS round trips, which
-// smaller, independent workgroups overlap better; above 256 columns 16
+// smaller, independent workgroups overlap better; above 320 columns 16
 // wavefronts of 8 groups (128 VGPRs, 4 wavefronts per SIMD) beat 8 of 16
-// groups (one workgroup of 8 per CU), by 3-10% at 320-500 columns.
+// groups (one workgroup of 8 per CU).  Between 257 and 320 columns the
+// 8-group tile is half empty and the n = 1e8 run was 2.5% slower with it.
 int pass_nw(bool tv_f64, int nw_opt, int j) {
   if (tv_f64) return 16;
   if (nw_opt == 4 && j > 256) return 8;  // 4 wavefronts cover at most 256 columns
   if (nw_opt > 0) return nw_opt;
-  return j <= 128 ? 4 : (j <= 256 ? 8 : 16);
+  return j <= 128 ? 4 : (j <= 320 ? 8 : 16);
 }
 
 hipError_t launch_pass(int mode, bool tv_f64, bool tx_f64, bool prefetch, int nw, int grid,
