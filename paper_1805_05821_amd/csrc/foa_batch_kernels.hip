@@ -55,10 +55,11 @@ __device__ __forceinline__ int bucket_of(int j, int cols_per_qw) {
   return k;
 }
 
-// Step state and bucket lists, one workgroup of 1024 threads.  Streams are
-// taken 1024 at a time; per bucket a wavefront prefix sum (count and panels)
-// plus the per-wavefront totals give each active stream its list position
-// and panel offset.
+// Step state, bucket lists and workgroup ranges, one workgroup of 1024
+// threads.  Streams are taken 1024 at a time; per bucket a wavefront prefix
+// sum (count and panels) plus the per-wavefront totals give each active
+// stream its list position and panel offset; a last sweep cuts each
+// bucket's panels into its workgroups' ranges.
 __global__ __launch_bounds__(1024) void k_batch_plan(BatchArgs b) {
   __shared__ int s_wcnt[16][NBUCKET];
   __shared__ int64_t s_wpan[16][NBUCKET];
@@ -141,6 +142,7 @@ __global__ __launch_bounds__(1024) void k_batch_plan(BatchArgs b) {
     }
     __syncthreads();
   }
+  __shared__ int s_G[NBUCKET];
   if (tid < NBUCKET) {
     const int c = s_cnt[tid];
     const int64_t T = s_tot[tid];
@@ -152,48 +154,31 @@ __global__ __launch_bounds__(1024) void k_batch_plan(BatchArgs b) {
     }
     b.meta[2 * tid] = c;
     b.meta[2 * tid + 1] = G;
+    s_G[tid] = G;
   }
-}
-
-// Workgroup g of bucket k covers panels [g T / G, (g + 1) T / G) of the
-// bucket's concatenation; the workgroup holding panel p is
-// ((p + 1) G - 1) / T.  Blocks 0..NBUCKET-1: first stream of every
-// workgroup (binary search in the prefix); the rest: per stream, its first
-// workgroup and the number of workgroups (partial slots) on it.
-__global__ __launch_bounds__(256) void k_batch_plan_ranges(BatchArgs b) {
-  if (blockIdx.x < NBUCKET) {
-    const int k = blockIdx.x;
-    const int cnt = b.meta[2 * k], G = b.meta[2 * k + 1];
+  __syncthreads();
+  // Ranges: workgroup g of bucket k covers panels [g T / G, (g + 1) T / G)
+  // of the bucket's concatenation, so the workgroup holding panel p is
+  // ((p + 1) G - 1) / T.  Per active stream (panels [p0, p1) of its bucket):
+  // its first workgroup and workgroup count, and it is the first stream of
+  // workgroups ceil(p0 G / T) .. ceil(p1 G / T) - 1 (those whose range
+  // starts inside it).
+  for (int s = tid; s < b.S; s += 1024) {
+    DevState *st = b.streams[s].st;
+    if (!st->act) continue;
+    const int code = b.spos[s];
+    const int k = code >> 24, pos = code & 0xFFFFFF;
+    const int G = s_G[k];
+    const int64_t T = s_tot[k];
     const int64_t *pre = b.pre + (size_t)k * (b.S + 1);
-    const int64_t T = uniform(pre[cnt]);
-    for (int g = threadIdx.x; g < G; g += 256) {
-      const int64_t lo = (int64_t)g * T / G;
-      int a = 0, c = cnt - 1;  // largest i with pre[i] <= lo
-      while (a < c) {
-        const int m = (a + c + 1) / 2;
-        if (pre[m] <= lo)
-          a = m;
-        else
-          c = m - 1;
-      }
-      b.first[k * kMaxBatchGrid + g] = a;
-    }
-    return;
+    const int64_t p0 = pre[pos], p1 = pre[pos + 1];
+    const int g0 = (int)(((p0 + 1) * G - 1) / T);
+    const int g1 = (int)((p1 * G - 1) / T);
+    st->seg0 = g0;
+    st->nseg = g1 - g0 + 1;
+    const int f0 = (int)((p0 * G + T - 1) / T), f1 = (int)((p1 * G + T - 1) / T);
+    for (int g = f0; g < f1 && g < G; ++g) b.first[k * kMaxBatchGrid + g] = pos;
   }
-  const int s = (blockIdx.x - NBUCKET) * 256 + threadIdx.x;
-  if (s >= b.S) return;
-  DevState *st = b.streams[s].st;
-  if (!st->act) return;
-  const int code = b.spos[s];
-  const int k = code >> 24, pos = code & 0xFFFFFF;
-  const int cnt = b.meta[2 * k], G = b.meta[2 * k + 1];
-  const int64_t *pre = b.pre + (size_t)k * (b.S + 1);
-  const int64_t T = pre[cnt];
-  const int64_t p0 = pre[pos], p1 = pre[pos + 1];
-  const int g0 = (int)(((p0 + 1) * G - 1) / T);
-  const int g1 = (int)((p1 * G - 1) / T);
-  st->seg0 = g0;
-  st->nseg = g1 - g0 + 1;
 }
 
 // Bucket BK's row pass.  The bucket fixes the basis-size range (tile width
@@ -388,14 +373,14 @@ hipError_t launch_batch_pass(int mode, bool tv_f64, bool tx_f64, int k, int grid
 // of kernel boundaries: pass A | reduce A | pass B | reduce B | pass C |
 // finalize + next b.  In a pass, the group's concatenated panels are cut
 // into G equal contiguous ranges (G = min(workgroups per XCD, panels /
-// min_seg)); the workgroup of arrival rank r on its XCD takes range r and
+// p_unit)); the workgroup of arrival rank r on its XCD takes range r and
 // writes its partial sums for a stream to slot r - seg0 of that stream.
 // Reductions take (stream, 8-column block) tasks r, r + G, ...; finalize and
 // next b take streams r, r + G, ...  A barrier waits until all G ranks have
 // finished the phase.  Ranks need G workgroups on the XCD, resident at once
 // (the launch is sized to the resident complement); waits are bounded, and
-// the last workgroup to finish checks that every group finalized all its
-// streams: either failure sets the error flag, which the host reports.
+// the last workgroup to finish checks that all G ranks of every group ran
+// to the end: either failure sets the error flag, which the host reports.
 // ---------------------------------------------------------------------------
 
 __device__ inline int xcc_id() {
@@ -789,7 +774,6 @@ hipError_t launch_step_persist(bool tx_f64, int grid, const BatchArgs &b, hipStr
 
 hipError_t launch_batch_plan(const BatchArgs &b, hipStream_t s) {
   hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(1024), 0, s, b);
-  hipLaunchKernelGGL(k_batch_plan_ranges, dim3(NBUCKET + (b.S + 255) / 256), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 
