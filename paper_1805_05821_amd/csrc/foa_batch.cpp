@@ -107,8 +107,10 @@ struct foa_batch_s {
   int pgrid = 0;         // its workgroups (resident complement)
   int occ[NBUCKET] = {};  // resident row-pass workgroups per CU, per bucket
   double tuned_ms = 0.0;
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  // one captured step per snapshot dtype and widest bucket that can be in use
+  hipGraph_t graph[2][NBUCKET] = {};
+  hipGraphExec_t exec[2][NBUCKET] = {};
+  int pushes = 0;  // foa_batch_push calls since the last reset
   std::string tune_path, tune_key;
   std::vector<DevState> hstates;
 };
@@ -156,11 +158,11 @@ foa_status upload_config(foa_batch_s *b, int unit_panels) {
 }
 
 // All kernels of one step, enqueued on stream s (direct launches or capture).
-// Bucket mode: per pass one row-pass launch per tile bucket, then the
-// reductions, finalize and next b.  Persistent mode (FP32 basis): the streams
-// of up to kPersistCols columns run in one persistent launch; first pushes
-// and wider bases take the bucket launches, which skip the others.
-hipError_t enqueue_step(foa_batch_s *b, bool x_f64, hipStream_t s) {
+// Bucket mode: per pass one row-pass launch per tile bucket up to kmax, then
+// the reductions, finalize and next b.  Persistent mode (FP32 basis): the
+// streams of up to kPersistCols columns run in one persistent launch; first
+// pushes and wider bases take the bucket launches, which skip the others.
+hipError_t enqueue_step(foa_batch_s *b, bool x_f64, hipStream_t s, int kmax) {
   const bool v64 = b->prec == FOA_PREC_F64;
   const int cols = batch_cols_per_qw(v64);
   const int qmax = pick_qw(std::max(b->B.max_nmax - 1, 1), cols);
@@ -175,32 +177,47 @@ hipError_t enqueue_step(foa_batch_s *b, bool x_f64, hipStream_t s) {
   if (pers && (e = launch_persist_plan(a, s)) != hipSuccess) return e;
   if ((e = launch_batch_pass(PM_INIT, v64, x_f64, 1, a.gridb[0], a, s)) != hipSuccess) return e;
   if (pers && (e = launch_step_persist(x_f64, b->pgrid, a, s)) != hipSuccess) return e;
-  for (int qw = 1, k = 1; qw <= qmax; qw *= 2, ++k)
+  for (int qw = 1, k = 1; qw <= qmax && k <= kmax; qw *= 2, ++k)
     if (k >= kfirst && (e = launch_batch_pass(PM_A, v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess) return e;
   if ((e = launch_batch_reduce(1, a, s)) != hipSuccess) return e;
-  for (int qw = 1, k = 1; qw <= qmax; qw *= 2, ++k)
+  for (int qw = 1, k = 1; qw <= qmax && k <= kmax; qw *= 2, ++k)
     if (k >= kfirst && (e = launch_batch_pass(PM_B, v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess) return e;
   if ((e = launch_batch_reduce(2, a, s)) != hipSuccess) return e;
-  for (int qw = 1, k = 1; qw <= qmax; qw *= 2, ++k)
+  for (int qw = 1, k = 1; qw <= qmax && k <= kmax; qw *= 2, ++k)
     if (k >= kfirst && (e = launch_batch_pass(PM_C, v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess) return e;
   if ((e = launch_batch_finalize(a, s)) != hipSuccess) return e;
   return launch_batch_nextb(a, s);
 }
 
 void drop_graphs(foa_batch_s *b) {
-  for (int k = 0; k < 2; ++k) {
-    if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
-    if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
-    b->exec[k] = nullptr;
-    b->graph[k] = nullptr;
-  }
+  for (int x = 0; x < 2; ++x)
+    for (int k = 0; k < NBUCKET; ++k) {
+      if (b->exec[x][k]) (void)hipGraphExecDestroy(b->exec[x][k]);
+      if (b->graph[x][k]) (void)hipGraphDestroy(b->graph[x][k]);
+      b->exec[x][k] = nullptr;
+      b->graph[x][k] = nullptr;
+    }
 }
 
-foa_status ensure_graph(foa_batch_s *b, bool x_f64) {
-  const int k = x_f64 ? 1 : 0;
-  if (b->exec[k]) return FOA_OK;
+// Widest bucket any stream can be in at the next push: a stream's basis
+// grows by at most one column per push, so after p pushes since the reset no
+// basis is wider than min(p, largest capacity - 1).  (Views cannot push and
+// nothing else changes a basis size.)  Buckets above it are certainly empty
+// and their launches are left out of that push's graph.
+int widest_bucket(const foa_batch_s *b) {
+  const int j = std::min(b->pushes, std::max(b->B.max_nmax - 1, 0));
+  if (j == 0) return 0;
+  const int cols = batch_cols_per_qw(b->prec == FOA_PREC_F64);
+  int k = 1;
+  for (int qw = 1; qw < 16 && qw * cols < j; qw *= 2) ++k;
+  return k;
+}
+
+foa_status ensure_graph(foa_batch_s *b, bool x_f64, int kmax) {
+  hipGraphExec_t &slot = b->exec[x_f64 ? 1 : 0][kmax];
+  if (slot) return FOA_OK;
   if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return FOA_E_DEVICE;
-  hipError_t e = enqueue_step(b, x_f64, b->cap);
+  hipError_t e = enqueue_step(b, x_f64, b->cap, kmax);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->cap, &g);
   if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -212,13 +229,14 @@ foa_status ensure_graph(foa_batch_s *b, bool x_f64) {
     (void)hipGraphDestroy(g);
     return FOA_E_DEVICE;
   }
-  b->graph[k] = g;
-  b->exec[k] = x;
+  b->graph[x_f64 ? 1 : 0][kmax] = g;
+  slot = x;
   return FOA_OK;
 }
 
 foa_status reset_states(foa_batch_s *b) {
   if (launch_batch_init_states(b->args, b->tol, b->stream) != hipSuccess) return FOA_E_DEVICE;
+  b->pushes = 0;
   if (hipMemsetAsync(b->ws + b->B.qctl, 0, kCtlInts * sizeof(int), b->stream) != hipSuccess) return FOA_E_DEVICE;
   for (foa_ctx_s *v : b->views) {
     v->q_host = 0;
@@ -306,7 +324,7 @@ foa_status time_config(foa_batch_s *b, int unit, int grid, bool persist, double 
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
       e = launch_tune_states(b->args, t, b->stream);
       if (e == hipSuccess && rep == 1) e = hipEventRecord(e0, b->stream);
-      if (e == hipSuccess) e = enqueue_step(b, false, b->stream);
+      if (e == hipSuccess) e = enqueue_step(b, false, b->stream, NBUCKET - 1);
     }
     if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);  // the host pointer array is reused
@@ -528,12 +546,14 @@ foa_status foa_batch_init(foa_batch *out, int32_t S, const int64_t *n, const int
 foa_status foa_batch_push(foa_batch b, const void *const *d_x_ptrs, foa_dtype x_dtype) {
   if (!b) return FOA_E_ARG;
   if (!d_x_ptrs || (x_dtype != FOA_F32 && x_dtype != FOA_F64)) return FOA_E_ARG;
-  foa_status r = ensure_graph(b, x_dtype == FOA_F64);
+  const int kmax = widest_bucket(b);
+  foa_status r = ensure_graph(b, x_dtype == FOA_F64, kmax);
   if (r != FOA_OK) return r;
   if (hipMemcpyAsync(b->ws + b->B.xptrs, d_x_ptrs, (size_t)b->S * sizeof(void *), hipMemcpyDeviceToDevice,
                      b->stream) != hipSuccess)
     return FOA_E_DEVICE;
-  if (hipGraphLaunch(b->exec[x_dtype == FOA_F64 ? 1 : 0], b->stream) != hipSuccess) return FOA_E_DEVICE;
+  if (hipGraphLaunch(b->exec[x_dtype == FOA_F64 ? 1 : 0][kmax], b->stream) != hipSuccess) return FOA_E_DEVICE;
+  ++b->pushes;
   for (foa_ctx_s *v : b->views) {
     v->mirror_valid = false;
     v->dmd.valid = false;
