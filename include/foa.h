@@ -240,8 +240,10 @@ foa_status foa_batch_workspace_bytes(int32_t S, const int64_t *n, const int32_t 
 
 /* Create S independent streams sharing one workspace and one hipStream_t.
  * Every push advances all streams by one snapshot in a single graph launch.
- * The launch configuration (row-pass grid and smallest panel range per
- * workgroup) is chosen by timing candidates at init, or read from
+ * The launch configuration -- bucket launches with their row-pass grid and
+ * smallest panel range per workgroup, or (FP32 basis) the persistent
+ * one-launch step with its smallest range -- is chosen at init by timing each
+ * candidate at 8 basis sizes spread over the run, or read from
  * tune_table_json: path of an autotuner table (read, and appended to when the
  * shape is new), or NULL to time the candidates at every init.  The
  * configuration fixes the summation order of the row passes: the same
@@ -253,10 +255,13 @@ foa_status foa_batch_init(foa_batch *b, int32_t S, const int64_t *n, const int32
 
 /* Advance every stream by one snapshot.  d_x_ptrs: DEVICE array of S device
  * pointers (FP32 or FP64 per x_dtype); a NULL entry leaves that stream idle.
- * Asynchronous (one hipGraphLaunch). */
+ * Asynchronous (one hipGraphLaunch; the graph leaves out the tile buckets no
+ * stream can occupy yet, one graph per widest bucket, captured on first use). */
 foa_status foa_batch_push(foa_batch b, const void *const *d_x_ptrs, foa_dtype x_dtype);
 
-/* Wait; h_q / h_status (may be NULL) receive per-stream q and status. */
+/* Wait; h_q / h_status (may be NULL) receive per-stream q and status.
+ * FOA_E_DEVICE also when the persistent step reported that one of its bounded
+ * waits ran out or that a group of its workgroups did not complete. */
 foa_status foa_batch_sync(foa_batch b, int32_t *h_q, int32_t *h_status);
 
 /* Context view of stream s for get_state / copy_basis / truncate / modes /
