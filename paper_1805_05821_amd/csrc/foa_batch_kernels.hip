@@ -293,16 +293,17 @@ __global__ __launch_bounds__(256) void k_fill_random(float *out, int64_t n, uint
 int batch_cols_per_qw(bool tv_f64) { return tv_f64 ? 16 * 2 : 8 * 4; }
 
 // Kernel shape of bucket k (1..5: basis sizes up to 32, 64, 128, 256, 512
-// columns).  FP32 basis: one wavefront with 8 groups for k = 1, 4 wavefronts
-// with 4 and 8 groups for k = 2, 3, then 8 wavefronts with 8 and 16 groups
-// (16 wavefronts of 8 groups, the single push's choice above 256 columns,
+// columns).  FP32 basis: 1 and 2 wavefronts with 8 groups for k = 1, 2, 4
+// wavefronts with 8 groups for k = 3, then 8 wavefronts with 8 and 16 groups
+// (16 wavefronts of 8 groups, the single push's choice above 320 columns,
 // measured 0.5-1.5% slower here over the whole run);
 // FP64 basis: 16 wavefronts with 1 .. 16 groups, 16 groups without prefetch.
 // Up to 32 columns a panel carries too little data to pay for the
 // cross-wavefront reduction and barriers of a wider workgroup: one-wavefront
 // workgroups (16 per CU) keep many more panels in flight (single-stream
 // passes at 4, 8, 16 and 32 columns: 1.85, 1.49, 1.24 and 1.08 times the
-// rate of 4-wavefront workgroups).
+// rate of 4-wavefront workgroups); at 33-64 columns 2-wavefront workgroups of
+// 8 groups took the batched run's steps there from 55.4 to 51.6 ms.
 template <typename TV, typename TX, int MODE, int BK>
 static hipError_t launch_bucket(int grid, const BatchArgs &b, hipStream_t s) {
   if constexpr (sizeof(TV) == 8) {
@@ -311,6 +312,8 @@ static hipError_t launch_bucket(int grid, const BatchArgs &b, hipStream_t s) {
     hipLaunchKernelGGL((k_pass_batch<TV, TX, 16, QW, MODE, PREF, BK>), dim3(grid), dim3(16 * 64), 0, s, b);
   } else if constexpr (BK == 1) {
     hipLaunchKernelGGL((k_pass_batch<TV, TX, 1, 8, MODE, true, BK>), dim3(grid), dim3(64), 0, s, b);
+  } else if constexpr (BK == 2) {
+    hipLaunchKernelGGL((k_pass_batch<TV, TX, 2, 8, MODE, true, BK>), dim3(grid), dim3(128), 0, s, b);
   } else if constexpr (BK <= 3) {
     constexpr int QW = 2 << (BK - 1);
     hipLaunchKernelGGL((k_pass_batch<TV, TX, 4, QW, MODE, true, BK>), dim3(grid), dim3(4 * 64), 0, s, b);
@@ -730,6 +733,8 @@ static int occ_bucket() {
     return occ_of(&k_pass_batch<TV, float, 16, QW, PM_A, (QW < 16), BK>, 16 * 64);
   } else if constexpr (BK == 1) {
     return occ_of(&k_pass_batch<TV, float, 1, 8, PM_A, true, BK>, 64);
+  } else if constexpr (BK == 2) {
+    return occ_of(&k_pass_batch<TV, float, 2, 8, PM_A, true, BK>, 128);
   } else if constexpr (BK <= 3) {
     return occ_of(&k_pass_batch<TV, float, 4, (2 << (BK - 1)), PM_A, true, BK>, 4 * 64);
   } else {
