@@ -102,6 +102,44 @@ def test_batch_f32_within_bound():
     bt.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_batch_late_starting_streams(prec):
+    """Streams that start several pushes after the reset (idle before), next
+    to one long stream whose basis grows past 128 columns: each push's graph
+    leaves out only the buckets that no stream can have reached by then, so
+    the lagging streams still find their narrower buckets launched.  Every
+    stream against the oracle on its own snapshots."""
+    import torch
+
+    from paper_1805_05821_amd.stream import FOABatch
+
+    Xs = _streams(S=4, seed=7)
+    bw = datagen.get_workload("batched_256")
+    w = datagen.batched_streams(bw, streams=1)[0]
+    Xl, _, _ = datagen.snapshots_numpy(w.with_n(64 * 31 + 9).with_N(150), dtype="float64")
+    Xs.append(Xl)
+    off = [0, 9, 33, 70, 0]
+    S = len(Xs)
+    n = [X.shape[0] for X in Xs]
+    N = [X.shape[1] for X in Xs]
+    dev = [torch.from_numpy(np.ascontiguousarray(X.T)).cuda() for X in Xs]
+    bt = FOABatch(n, N, prec=prec, ws_fill=0xFF)
+    T = max(o + m for o, m in zip(off, N))
+    for k in range(T):
+        bt.push([dev[s][k - off[s]] if off[s] <= k < off[s] + N[s] else None for s in range(S)])
+    q, st = bt.sync()
+    for s, X in enumerate(Xs):
+        ref = oracle.foa_batch(X)
+        H, B, qq, m, V = _view_state(bt, s)
+        assert qq == q[s] == ref.q, (s, qq, q[s], ref.q)
+        kap = kappa_of(ref.beta[:m, :m])
+        eH = np.linalg.norm(H[:m, :m] - ref.H[:m, :m], 2) / np.linalg.norm(ref.H[:m, :m], 2)
+        announce(f"{prec} stream {s}: start {off[s]} n={n[s]} q={qq} kappa={kap:.1e} relH2={eH:.1e}")
+        eps = EPS64 if prec == "f64" else EPS32
+        assert eH <= (100 * qq if prec == "f64" else 10) * eps * kap
+    bt.close()
+
+
 def test_batch_equals_single_streams_and_replays(tmp_path):
     """Same results as single streams (to rounding), and bitwise-equal results
     from two batches with the same launch configuration (the second reads the
