@@ -8,12 +8,12 @@
  * Arnoldi basis V (n x q), the upper Hessenberg projected matrix H_bar
  * (q x (q-1)) and the upper triangular beta (q x q) with X_1^q = V beta.
  * Each push takes one snapshot psi_{q+1} through one iteration of the loop of
- * Algorithm 1 (steps 5-18): partial beta column (eq. betacolumnupdate),
- * w = A v_q formed from the snapshot (step 9, eq. avpsijp1beta), classical
- * Gram-Schmidt with one reorthogonalisation (steps 10-14), normalisation and
- * append (step 15) and beta completion (steps 16-18).  Eigenvalues, modes,
- * rank truncation, error indicators and coefficients follow Algorithm 1 steps
- * 20-28, Algorithm 3, Section 3.2.3 and Section 3.2.4.
+ * Algorithm 1: partial beta column (eq. betacolumnupdate), w = A v_q formed
+ * from the snapshot (eq. avpsijp1beta), classical Gram-Schmidt with one
+ * reorthogonalisation, normalisation and append, and beta completion.
+ * Eigenvalues, modes, rank truncation, error indicators and coefficients
+ * follow the post-processing of Algorithm 1, Algorithm 3, Section 3.2.3 and
+ * Section 3.2.4.
  *
  * Conventions
  *  - Every function returns foa_status: 0 success, > 0 information,
@@ -88,8 +88,8 @@ foa_status foa_workspace_bytes(int64_t n, int32_t n_max, foa_prec prec, size_t *
 foa_status foa_init(foa_ctx *ctx, int64_t n, int32_t n_max, foa_prec prec, void *d_workspace,
                     size_t ws_bytes, void *hip_stream, double breakdown_tol);
 
-/* Push one snapshot (Algorithm 4 with p = 1; for q = 0 steps 2-3 of
- * Algorithm 1, else one iteration of its loop).  d_x: device vector of n
+/* Push one snapshot (Algorithm 4 with p = 1; for q = 0 the first-snapshot
+ * normalisation of Algorithm 1, else one iteration of its loop).  d_x: device vector of n
  * entries of type x_dtype.  Asynchronous.  FOA_E_CAPACITY when q = n_max,
  * FOA_E_STATE after the stream became invariant or failed (as known to the
  * host at the last synchronising call; pushes enqueued after an undetected
@@ -160,7 +160,7 @@ foa_status foa_copy_basis(foa_ctx ctx, void *d_V, int64_t ld, foa_dtype dtype, i
 foa_status foa_copy_basis_rows(foa_ctx ctx, int64_t r0, int64_t nrows, void *d_V, int64_t ld,
                                foa_dtype dtype, int32_t ncols);
 
-/* Rank truncation (Algorithm 1 steps 21-23, Algorithm 3 lines 8-9): SVD of
+/* Rank truncation (Algorithm 1 and Algorithm 3, truncated DMD): SVD of
  * beta_m (m as in foa_get_state) on the host in FP64; r = number of singular
  * values above rel_tol * sigma_1, or, for rel_tol < 0, above
  * N * eps_s(sigma_1) (N = snapshots taken, eps_s the spacing at sigma_1 in
@@ -171,7 +171,7 @@ foa_status foa_copy_basis_rows(foa_ctx ctx, int64_t r0, int64_t nrows, void *d_V
 foa_status foa_truncate(foa_ctx ctx, double rel_tol, int32_t r_force, int32_t *r_out,
                         double *h_sigma);
 
-/* DMD eigenvalues and modes (Algorithm 1 steps 24-28): eigenpairs (lambda, z)
+/* DMD eigenvalues and modes (post-processing of Algorithm 1): eigenpairs (lambda, z)
  * of H_m (or of U_r^T H_m U_r after foa_truncate), z of unit 2-norm with the
  * entry of largest modulus real positive.  One entry per real eigenvalue and
  * per conjugate pair (its member with Im > 0), ordered by decreasing |c_j|,

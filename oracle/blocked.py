@@ -25,8 +25,8 @@ A block is committed only when every new diagonal entry S_kk of beta lies
 above the breakdown threshold of the sequential form (tol * ||X_1^{q+k}||_F)
 and the three Cholesky factorisations succeed; otherwise its snapshots are
 taken one at a time by the sequential oracle (foa.py), which applies the
-paper's breakdown and non-finite rules.  The first snapshot (steps 2-3 of
-Algorithm 1) is always taken by the sequential oracle.
+paper's breakdown and non-finite rules.  The first snapshot (its
+normalisation in Algorithm 1) is always taken by the sequential oracle.
 
 Parity status: pinned against the sequential oracle (the same exact-arithmetic
 factors: tests compare H_bar and beta with foa.foa_batch within O(eps kappa))

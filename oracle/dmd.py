@@ -1,5 +1,5 @@
 """DMD eigenvalues, modes, error indicators and coefficients from the FOA
-state: Algorithm 1 steps 20-28 (Algorithm 3 lines 5-15), Section 3.2.3
+state: the post-processing of Algorithm 1 and Algorithm 3, Section 3.2.3
 (error indicators) and Section 3.2.4 (coefficients of the first snapshot,
 eqs. exrecon / exreconwrt).  Plain NumPy float64; test infrastructure only.
 
@@ -68,7 +68,7 @@ def _order(lam, c):
 
 
 def dmd_untruncated(st):
-    """Steps 26-28: eig(H_m); indicators |h_{m+1,m}| |e_m^T z_i| (eq. errordmdvec);
+    """Untruncated DMD of Algorithm 1: eig(H_m); indicators |h_{m+1,m}| |e_m^T z_i| (eq. errordmdvec);
     coefficients [z]{c} = ||psi_1|| e_1 (eq. exrecon)."""
     m = projected_size(st)
     Hm = st.H[:m, :m].copy()
@@ -92,7 +92,7 @@ def dmd_untruncated(st):
 
 
 def dmd_truncated(st, r: int):
-    """Steps 21-25: SVD of beta_m, U_r^T H_m U_r, its eigenpairs; indicators
+    """Truncated DMD of Algorithm 1: SVD of beta_m, U_r^T H_m U_r, its eigenpairs; indicators
     ||[(I - U_r U_r^T) H_m ; h_{m+1,m} e_m^T] U_r z_i||_2 (Section 3.2.3);
     coefficients [z]{c} = ||psi_1|| U_r^T e_1 (eq. exreconwrt)."""
     m = projected_size(st)

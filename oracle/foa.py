@@ -74,11 +74,13 @@ def _new_state(n: int, cap: int, tol) -> FOAState:
 
 # ---------------------------------------------------------------------------
 # One iteration j (1-based) of Algorithm 1 / Algorithm 4, split into the
-# paper's steps.  Each helper does exactly the operations of its steps.
+# paper's stages in its order: partial beta column, w from the snapshot,
+# CGS2, normalisation, beta completion.  Each helper does exactly the
+# operations of its stage.
 # ---------------------------------------------------------------------------
 
 def _beta_partial(H, beta, j):
-    """Steps 5-8 (eq. betacolumnupdate without its last term):
+    """Partial beta column (eq. betacolumnupdate without its last term):
     beta_{1,j+1} = h_{1,1:j-1} beta_{1:j-1,j};
     beta_{i,j+1} = h_{i,i-1:j-1} beta_{i-1:j-1,j}, i = 2..j."""
     beta[0, j] = H[0, 0:j - 1] @ beta[0:j - 1, j - 1]
@@ -87,34 +89,34 @@ def _beta_partial(H, beta, j):
 
 
 def _form_w(V, beta, psi, j):
-    """Step 9: w = (psi_{j+1} - sum_{i<=j} beta_{i,j+1} v_i) / beta_{j,j},
+    """w from the snapshot: w = (psi_{j+1} - sum_{i<=j} beta_{i,j+1} v_i) / beta_{j,j},
     which equals A v_j (eq. avpsijp1beta)."""
     return (psi - V[:, :j] @ beta[:j, j]) / beta[j - 1, j - 1]
 
 
 def _cgs2(V, w, j):
-    """Steps 10-14: classical Gram-Schmidt with one reorthogonalisation."""
-    h = V[:, :j].T @ w          # step 10
-    w = w - V[:, :j] @ h        # step 11
-    s = V[:, :j].T @ w          # step 12
-    h = h + s                   # step 13
-    w = w - V[:, :j] @ s        # step 14
+    """Classical Gram-Schmidt with one reorthogonalisation (Algorithm 1)."""
+    h = V[:, :j].T @ w          # projection
+    w = w - V[:, :j] @ h        # first orthogonalisation
+    s = V[:, :j].T @ w          # reprojection
+    h = h + s                   # corrected Hessenberg column
+    w = w - V[:, :j] @ s        # second orthogonalisation
     return h, w
 
 
 def _norm(w):
-    """2-norm (step 15, steps 2-3)."""
+    """2-norm (the normalisation of w, and of the first snapshot)."""
     return float(np.sqrt(w @ w))
 
 
 def _beta_complete(H, beta, j):
-    """Steps 16-18: beta_{i,j+1} += h_{i,j} beta_{j,j}, i = 1..j+1."""
+    """Beta completion: beta_{i,j+1} += h_{i,j} beta_{j,j}, i = 1..j+1."""
     for i in range(1, j + 2):
         beta[i - 1, j] = beta[i - 1, j] + H[i - 1, j - 1] * beta[j - 1, j - 1]
 
 
 def _first(st: FOAState, psi1):
-    """Steps 2-3 of Algorithm 1 (lines 4-7 of Algorithm 4)."""
+    """First snapshot of Algorithm 1 / Algorithm 4: beta_11 = ||psi_1||, v_1 = psi_1 / beta_11."""
     nrm2 = float(psi1 @ psi1)
     st.pushes += 1
     if not np.isfinite(nrm2):
@@ -157,14 +159,14 @@ def _iteration(st: FOAState, psi, j):
         _beta_complete(H, beta, j)
         st.status = INVARIANT
         return
-    H[j, j - 1] = hn              # step 15
+    H[j, j - 1] = hn              # normalisation
     V[:, j] = w / hn
-    _beta_complete(H, beta, j)    # steps 16-18
+    _beta_complete(H, beta, j)
     st.q = j + 1
 
 
 def foa_batch(X, tol=None, capacity=None) -> FOAState:
-    """Algorithm 1, steps 1-19 (batch form), for X = [psi_1 .. psi_N] (n x N)."""
+    """Algorithm 1 up to the basis (its snapshot loop), for X = [psi_1 .. psi_N] (n x N)."""
     X = np.asarray(X, dtype=np.float64)
     n, N = X.shape
     cap = N if capacity is None else int(capacity)
@@ -179,7 +181,7 @@ def foa_batch(X, tol=None, capacity=None) -> FOAState:
 
 
 def foa_stream_init(n: int, capacity: int, tol=None) -> FOAState:
-    """Line 1 of Algorithm 3 (q = 0) with storage for ``capacity`` snapshots."""
+    """Initial state of Algorithm 3 (q = 0) with storage for ``capacity`` snapshots."""
     return _new_state(int(n), int(capacity), tol)
 
 
@@ -187,7 +189,7 @@ def foa_stream_update(st: FOAState, Xp) -> FOAState:
     """Algorithm 4: process the p new snapshots in the columns of ``Xp``.
 
     The storage is preallocated to the capacity, so 'expanding' H, V and beta
-    (line 2) only widens the logical extent.  For a given total number of
+    for new snapshots only widens the logical extent.  For a given total number of
     snapshots the result equals Algorithm 1 bit for bit (same operations in
     the same order, Section 3.1).
     """
@@ -216,7 +218,7 @@ def foa_stream_update(st: FOAState, Xp) -> FOAState:
 # ---------------------------------------------------------------------------
 
 def arnoldi_known_A(A, psi1, N):
-    """Steps 2-10 of Algorithm 2 with CGS2 orthogonalisation.
+    """Algorithm 2's Arnoldi loop with CGS2 orthogonalisation.
 
     Returns (V (n x N), H_bar (N x (N-1)))."""
     A = np.asarray(A, dtype=np.float64)
@@ -225,13 +227,13 @@ def arnoldi_known_A(A, psi1, N):
     H = np.zeros((N, N - 1), order="F")
     V[:, 0] = psi1 / _norm(psi1)
     for j in range(1, N):
-        w = A @ V[:, j - 1]                 # step 4
-        h = V[:, :j].T @ w                  # step 5
-        w = w - V[:, :j] @ h                # step 6
-        s = V[:, :j].T @ w                  # step 7
-        h = h + s                           # step 8
-        w = w - V[:, :j] @ s                # step 9
-        hn = _norm(w)                       # step 10
+        w = A @ V[:, j - 1]                 # Krylov step
+        h = V[:, :j].T @ w                  # projection
+        w = w - V[:, :j] @ h                # first orthogonalisation
+        s = V[:, :j].T @ w                  # reprojection
+        h = h + s
+        w = w - V[:, :j] @ s                # second orthogonalisation
+        hn = _norm(w)
         H[:j, j - 1] = h
         H[j, j - 1] = hn
         V[:, j] = w / hn

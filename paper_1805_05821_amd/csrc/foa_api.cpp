@@ -201,8 +201,8 @@ void release_events(foa_ctx_s *c) {
   c->ev_free.clear();
 }
 
-// Enqueue one push of snapshot x (Algorithm 1: steps 2-3 for q = 0, else one
-// loop iteration, steps 5-18).
+// Enqueue one push of snapshot x (Algorithm 1: the first-snapshot
+// normalisation for q = 0, else one iteration of its snapshot loop).
 foa_status enqueue_push(foa_ctx_s *c, const void *x, bool x_f64) {
   const bool v64 = c->prec == FOA_PREC_F64;
   const int j = c->q_host;

@@ -1,4 +1,4 @@
-// Batched form of the FOA push (Algorithm 1 steps 5-18 for many independent
+// Batched form of the FOA push (one iteration of Algorithm 1 for many independent
 // streams per step): the per-step plan, the row passes over the planned
 // segments, and the per-stream reductions and small kernels.
 #include "foa_device.h"

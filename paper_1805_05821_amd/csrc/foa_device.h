@@ -1,4 +1,4 @@
-// Device bodies of the FOA push kernels (Algorithm 1 steps 5-18), shared
+// Device bodies of the FOA push kernels (one iteration of Algorithm 1), shared
 // by the single-stream kernels and the batched kernels.
 #pragma once
 
@@ -428,7 +428,7 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
 // Column reduction of the pass partials, one wavefront per column (fixed order:
 // lane-strided sums, then a butterfly).  MODE 1 (after pass A): h = sigma o t,
 // coefB = sigma o h, and the extra wavefront c == j reduces ||psi||^2.
-// MODE 2 (after pass B): s = sigma o t, h += s (step 13), coefC = sigma o s.
+// MODE 2 (after pass B): s = sigma o t, h += s, coefC = sigma o s.
 // ---------------------------------------------------------------------------
 template <int MODE, bool COH = false>
 __device__ inline void reduce_body(const SmallArgs &a, int c0) {
@@ -478,7 +478,7 @@ __device__ inline double block_sum_t(double t, double *sh) {
 
 __device__ inline double block_sum_256(double t, double *sh) { return block_sum_t<256>(t, sh); }
 
-// Steps 15-18 plus the breakdown rule; one workgroup of NT threads.
+// Normalisation, beta completion and the breakdown rule; one workgroup of NT threads.
 template <int NT, bool COH = false>
 __device__ inline void finalize_body_t(const SmallArgs &a) {
   __shared__ double sh[NT];
@@ -523,7 +523,7 @@ __device__ inline void finalize_body_t(const SmallArgs &a) {
   for (int i = tid; i < j; i += NT) {
     const double hi = xld<COH>(a.h + i);
     a.H[(size_t)(j - 1) * a.ldH + i] = hi;
-    a.beta[(size_t)j * a.ldB + i] = a.bvec[i] + hi * bjj;  // steps 16-18
+    a.beta[(size_t)j * a.ldB + i] = a.bvec[i] + hi * bjj;  // beta completion
   }
   if (tid == 0) {
     if (status == ST_INVARIANT) {
@@ -543,7 +543,7 @@ __device__ inline void finalize_body_t(const SmallArgs &a) {
 
 __device__ inline void finalize_body(const SmallArgs &a) { finalize_body_t<256>(a); }
 
-// Steps 2-3 for the first snapshot.
+// Normalisation of the first snapshot.
 __device__ inline void finalize_init_body(const SmallArgs &a) {
   __shared__ double sh[256];
   DevState *st = a.st;
@@ -571,7 +571,7 @@ __device__ inline void finalize_init_body(const SmallArgs &a) {
   }
 }
 
-// Steps 5-8 for the next push (J = q basis vectors):
+// Partial beta column for the next push (eq. betacolumnupdate, J = q basis vectors):
 //   b_i = sum_{l = max(1, i-1)}^{J-1} h_{i,l} beta_{l,J}  (1-based), i = 1..J,
 // computed as 64 rows x 4 contiguous l-slices per 256 threads, slices
 // combined in order; a workgroup of NT threads takes NT / 256 consecutive

@@ -29,7 +29,7 @@ struct DevState {
   int full;       // batched form: a snapshot arrived after the capacity was reached
   double xfro2;   // ||X_1^q||_F^2 of the committed snapshots
   double xn2;     // ||x||^2 of the snapshot being pushed
-  double scaleA;  // 1 / beta_{q,q}: scale of step 9 for the next push
+  double scaleA;  // 1 / beta_{q,q}: scale of w for the next push (eq. avpsijp1beta)
   double tol;     // breakdown tolerance (relative to ||X||_F)
   double hlast;   // last h_{j+1,j}
   int nseg;       // batched form: partial-sum slots written by this step's passes
@@ -40,10 +40,10 @@ struct DevState {
 
 // Pass modes of the fused row kernel.
 enum PassMode : int {
-  PM_INIT = 0,  // q = 0: V(:,0) <- x, partial ||x||^2            (steps 2-3)
-  PM_A = 1,     // w_A = (x - V c0) * scale, partial V^T w_A, ||x||^2  (steps 9-10)
-  PM_B = 2,     // w_B = w_A - V c1, partial V^T w_B                  (steps 11-12)
-  PM_C = 3,     // w_C = w_B - V c2, V(:,j) <- w_C, partial ||w_C||^2 (steps 14-15)
+  PM_INIT = 0,  // q = 0: V(:,0) <- x, partial ||x||^2            (first snapshot)
+  PM_A = 1,     // w_A = (x - V c0) * scale, partial V^T w_A, ||x||^2  (w and its projection)
+  PM_B = 2,     // w_B = w_A - V c1, partial V^T w_B                  (orthogonalisation, reprojection)
+  PM_C = 3,     // w_C = w_B - V c2, V(:,j) <- w_C, partial ||w_C||^2 (reorthogonalisation, norm)
 };
 
 struct PassArgs {
@@ -67,7 +67,7 @@ struct SmallArgs {
   double *H;       // H_bar, ldH rows
   double *beta;    // beta, ldB rows
   double *sigma;   // per-column scale: v_c = sigma_c * stored column c
-  double *bvec;    // partial beta column of the current push (steps 5-8)
+  double *bvec;    // partial beta column of the current push (eq. betacolumnupdate)
   double *h;       // h_{1:j,j}
   double *s;       // s_{1:j}
   double *coefA;   // sigma o b

@@ -1,27 +1,31 @@
-// HIP kernels (gfx950) of one FOA push: Algorithm 1 steps 5-18 of
-// Anantharamu & Mahesh, restructured as three fused row passes over the basis.
+// HIP kernels (gfx950) of one FOA push: one iteration of the snapshot loop of
+// Algorithm 1 of Anantharamu & Mahesh, restructured as three fused row passes
+// over the basis.
 //
-// The paper's literal schedule sweeps V five times per snapshot (steps 9, 10,
-// 11, 12 and 14).  Each of steps (9,10), (11,12) and (14,15) is "apply a
-// row-local update with coefficients known before the pass, then reduce over
-// the rows", so one pass over V serves both halves; the two projections must
-// finish globally before the next update, so three sweeps is the minimum for
-// classical Gram-Schmidt with one reorthogonalisation.
+// The paper's literal schedule sweeps V five times per snapshot (forming w,
+// the projection, the first orthogonalisation, the reprojection and the
+// second orthogonalisation).  Each pair -- w and its projection, the first
+// orthogonalisation and the reprojection, the second orthogonalisation and
+// the norm -- is "apply a row-local update with coefficients known before the
+// pass, then reduce over the rows", so one pass over V serves both halves;
+// the two projections must finish globally before the next update, so three
+// sweeps is the minimum for classical Gram-Schmidt with one
+// reorthogonalisation.
 //
 //   pass A : w = (psi - V b) / beta_jj ; partial V^T w ; partial ||psi||^2
-//   reduce : h = V^T w                           (step 10)
-//   pass B : w = w - V h ; partial V^T w         (steps 11-12)
-//   reduce : s = V^T w ; h = h + s               (step 13)
-//   pass C : w = w - V s ; v_{j+1} <- w ; partial ||w||^2   (steps 14-15)
-//   finalize: h_{j+1,j} = ||w||, breakdown test, H_bar column, beta column
-//             (steps 15-18), then the next push's partial beta column
-//             (steps 5-8, eq. betacolumnupdate) in a small multi-block kernel.
+//   reduce : h = V^T w
+//   pass B : w = w - V h ; partial V^T w
+//   reduce : s = V^T w ; h = h + s
+//   pass C : w = w - V s ; v_{j+1} <- w ; partial ||w||^2
+//   finalize: h_{j+1,j} = ||w||, breakdown test, H_bar column, beta
+//             completion, then the next push's partial beta column
+//             (eq. betacolumnupdate) in a small multi-block kernel.
 //
 // The basis is stored unnormalised: column c holds fl(w_c) and
 // v_c = sigma_c * column_c with sigma_c = 1 / h_{c,c-1} (sigma_1 = 1/beta_11).
 // Every coefficient vector handed to a pass is pre-multiplied by sigma and every
-// projection is post-multiplied by sigma, so step 15's division never needs its
-// own sweep over n.  All dot products, norms and small-matrix arithmetic are FP64.
+// projection is post-multiplied by sigma, so the normalisation's division
+// never needs its own sweep over n.  All dot products, norms and small-matrix arithmetic are FP64.
 //
 // Reductions are deterministic: every partial sum has a fixed association
 // (per-lane register sums in panel order, butterfly within a wavefront, fixed

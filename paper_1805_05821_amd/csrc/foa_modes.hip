@@ -1,4 +1,4 @@
-// Mode reconstruction Phi = V B (Algorithm 1 steps 25 and 28): the panel-layout
+// Mode reconstruction Phi = V B (the modes of Algorithm 1): the panel-layout
 // basis W (n x k columns in use, FP32 or FP64) times the k x r coefficient
 // matrix B (FP64, sigma folded in, packed real columns).  An FP32 basis with
 // FP32 output runs on FP32 MFMA; every other combination uses the FP64-

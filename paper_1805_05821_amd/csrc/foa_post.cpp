@@ -1,8 +1,7 @@
-// Host FP64 post-processing of the FOA state: rank truncation (Algorithm 1
-// steps 21-23), eigenpairs of the projected matrix (steps 24 and 27), error
+// Host FP64 post-processing of the FOA state (Algorithm 1 after its snapshot
+// loop): rank truncation, eigenpairs of the projected matrix, error
 // indicators (Section 3.2.3), coefficients of the first snapshot and mode
-// ordering (Section 3.2.4), and the mode matrix V B on the device (steps 25
-// and 28).
+// ordering (Section 3.2.4), and the mode matrix V B on the device.
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -73,7 +72,7 @@ foa_status compute_dmd(foa_ctx_s *c) {
   const int rr = c->trunc_r;
   std::vector<cd> Z;
   if (rr > 0) {
-    // U_r^T H_m U_r (Algorithm 1 step 23)
+    // U_r^T H_m U_r (truncated DMD, Algorithm 1)
     const std::vector<double> &U = c->Ur;  // m x r
     std::vector<double> HU((size_t)m * rr, 0.0), Ht((size_t)rr * rr, 0.0);
     for (int j = 0; j < rr; ++j)

@@ -217,7 +217,7 @@ def pin_reconstruction(O, N=12):
 
 def pin_truncation_rank(O):
     """Exact-rank data without the breakdown stop: the numerical-rank rule
-    (Section 4.1) picks r = 2M and the truncated Ritz values (steps 21-25) are
+    (Section 4.1) picks r = 2M and the truncated Ritz values of Algorithm 1 are
     the generating eigenvalues."""
     w = datagen.get_workload("exact_rank_4096x64")
     X, lam, _ = datagen.snapshots_numpy(w)
@@ -287,11 +287,12 @@ class _FlopArray(np.ndarray):
 
 
 def pin_cost_model(O):
-    """Arithmetic of one iteration's length-n work (steps 9-15), counted on the
-    operations the oracle actually performs: the paper's per-step cost
-    (Appendix A.1: 2nj + n for step 9, 8nj + j for steps 10-14, 3n for step
-    15) plus 2n for ||psi||^2 of the breakdown reading, up to the O(j) terms
-    whose convention the paper leaves open."""
+    """Arithmetic of one iteration's length-n work (forming w through the
+    normalisation), counted on the operations the oracle actually performs:
+    the paper's per-stage cost (Appendix A.1: 2nj + n for forming w, 8nj + j
+    for the CGS2 sweeps, 3n for the normalisation) plus 2n for ||psi||^2 of
+    the breakdown reading, up to the O(j) terms whose convention the paper
+    leaves open."""
     X = _noisy_small(n=300, N=12)
     ok, msgs = True, []
     for j in (3, 7, 11):

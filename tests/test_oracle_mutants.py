@@ -2,7 +2,7 @@
 least one pin fails for each: evidence that the pins would catch a dropped
 term, a wrong sign or index, or a transposed operand.
 
-Not listed: dropping step 13 (h += s).  After one classical Gram-Schmidt
+Not listed: dropping the Hessenberg correction h += s.  After one classical Gram-Schmidt
 pass the correction s = V^T w is of rounding size (||s|| ~ eps ||w||), so that
 mutant changes H only at the level of ordinary rounding, which no
 mathematical pin can separate from a correct run (an equivalent mutant)."""
