@@ -261,7 +261,9 @@ foa_status foa_batch_push(foa_batch b, const void *const *d_x_ptrs, foa_dtype x_
 
 /* Wait; h_q / h_status (may be NULL) receive per-stream q and status.
  * FOA_E_DEVICE also when the persistent step reported that one of its bounded
- * waits ran out or that a group of its workgroups did not complete. */
+ * waits ran out or that a group of its workgroups did not complete (the
+ * bound, 2^22 polls, can be lowered for tests with the environment variable
+ * FOA_PERSIST_SPIN, read at foa_batch_init). */
 foa_status foa_batch_sync(foa_batch b, int32_t *h_q, int32_t *h_status);
 
 /* Context view of stream s for get_state / copy_basis / truncate / modes /

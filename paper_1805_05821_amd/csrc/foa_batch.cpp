@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -501,6 +502,11 @@ foa_status foa_batch_init(foa_batch *out, int32_t S, const int64_t *n, const int
   b->args.p_first = reinterpret_cast<int *>(b->ws + b->B.qfirst);
   b->args.p_ctl = reinterpret_cast<int *>(b->ws + b->B.qctl);
   b->args.cols_per_qw = batch_cols_per_qw(prec == FOA_PREC_F64);
+  // Test hook: FOA_PERSIST_SPIN bounds the persistent step's barrier waits
+  // (0 makes every wait give up at once, so the error path can be exercised
+  // with every kernel still ending normally).
+  b->args.p_spin = kPersistSpin;
+  if (const char *e = std::getenv("FOA_PERSIST_SPIN")) b->args.p_spin = std::max(0, std::atoi(e));
   b->args.xptrs = reinterpret_cast<const void *const *>(b->ws + b->B.xptrs);
   b->args.rblk_stream = reinterpret_cast<const int *>(b->ws + b->B.rblk_s);
   b->args.rblk_c0 = reinterpret_cast<const int *>(b->ws + b->B.rblk_c);

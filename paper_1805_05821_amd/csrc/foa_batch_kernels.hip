@@ -558,7 +558,6 @@ __global__ __launch_bounds__(1024) void k_persist_plan(BatchArgs b) {
 }
 
 constexpr int kPersistThreads = kPersistNW * 64;
-constexpr int kPersistSpin = 1 << 22;  // polls of a wait before it gives up
 
 // Everything one workgroup hands to another inside the launch goes through
 // device-scope stores and loads (xst / xld), so a barrier needs no cache
@@ -574,12 +573,12 @@ __device__ inline void wg_release() {
 // (one lane polls, relaxed, with sleeps) until all G ranks have counted.
 // False, with the error flag set, at the bound or when an earlier wait
 // already failed.
-__device__ inline bool group_barrier(int *cnt, int G, int *err, int *s_ok) {
+__device__ inline bool group_barrier(int *cnt, int G, int *err, int spin, int *s_ok) {
   wg_release();
   if (threadIdx.x == 0) {
     atomicAdd(cnt, 1);
     int ok = 0;
-    for (int it = 0; it < kPersistSpin; ++it) {
+    for (int it = 0; it < spin; ++it) {
       if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= G) {
         ok = 1;
         break;
@@ -654,6 +653,7 @@ void k_step_persist(BatchArgs b) {
   __shared__ int s_rank, s_ok;
   int *ctl = b.p_ctl;
   int *err = ctl + kCtlErr;
+  const int spin = b.p_spin;
   const int g = (int)((b.p_xmap >> (4 * xcc_id())) & 15);
   if (g < b.p_groups) {
     int *gc = ctl + kCtlGroup0 + kCtlGroupStride * g;
@@ -671,7 +671,7 @@ void k_step_persist(BatchArgs b) {
           persist_range<TX, PM_B>(b, gc, rank, g, lds);
         else
           persist_range<TX, PM_C>(b, gc, rank, g, lds);
-        ok = group_barrier(gc + kGcBar + 2 * ph, G, err, &s_ok);
+        ok = group_barrier(gc + kGcBar + 2 * ph, G, err, spin, &s_ok);
         if (!ok || ph == 2) break;
         // reduce of pass ph: (stream, 8-column block) tasks rank, rank + G, ...
         for (int t = rank; t < cnt * CB; t += G) {
@@ -683,7 +683,7 @@ void k_step_persist(BatchArgs b) {
           else
             reduce_body<2, true>(sa, cb * kPersistNW);
         }
-        ok = group_barrier(gc + kGcBar + 2 * ph + 1, G, err, &s_ok);
+        ok = group_barrier(gc + kGcBar + 2 * ph + 1, G, err, spin, &s_ok);
       }
       if (ok) {
         // finalize and next b: streams rank, rank + G, ...

@@ -126,6 +126,7 @@ struct BatchArgs {
   int p_unit;                // fewest panels per rank
   int p_ranks;               // workgroups per XCD in the launch (at most kMaxRanks)
   int p_groups;              // groups, one per XCD the device showed (1..kMaxGroups)
+  int p_spin;                // polls of a barrier wait before it gives up (kPersistSpin)
   uint64_t p_xmap;           // group of each XCD id, 4 bits per id (15: none)
 };
 // Persistent step: widest basis it takes (FP32 tiles of up to 8 groups of
@@ -139,6 +140,7 @@ constexpr int kPersistNW = 8;
 // phase barrier counters and finished ranks.
 constexpr int kMaxGroups = 8;
 constexpr int kMaxRanks = 256;
+constexpr int kPersistSpin = 1 << 22;  // default polls of a persistent-step barrier wait
 constexpr int kCtlStreams = 2, kCtlErr = 3, kCtlExit = 4, kCtlProbe = 5;
 constexpr int kCtlGroup0 = 8, kCtlGroupStride = 16;
 constexpr int kGcLo = 0, kGcCnt = 1, kGcRanks = 2, kGcBlocks = 3, kGcArrive = 4, kGcBar = 5, kGcPhases = 5,

@@ -326,3 +326,23 @@ def test_batch_persistent_capacity_idle_and_nonfinite(tmp_path):
     eH = np.linalg.norm(H[:m, :m] - ref.H[:m, :m], 2) / np.linalg.norm(ref.H[:m, :m], 2)
     assert qq == ref.q and st[2] == 0 and eH <= 10 * EPS32 * kap
     bt.close()
+
+
+def test_batch_persistent_wait_bound_reports_error(tmp_path, monkeypatch):
+    """A persistent-step barrier wait that gives up sets the error flag, and
+    foa_batch_sync reports it as a device error.  The host forces it by
+    bounding every wait to zero polls (FOA_PERSIST_SPIN=0), so every kernel
+    still ends normally.  A batch made without the bound then runs to
+    completion."""
+    from paper_1805_05821_amd import foa as F
+
+    Xs = _streams(S=3, seed=13)
+    table = _forced_table(Xs, "f32", tmp_path, True, 8, "spin")
+    monkeypatch.setenv("FOA_PERSIST_SPIN", "0")
+    with pytest.raises(F.FOAError) as err:
+        _run_batch(Xs, "f32", tune=table)
+    assert err.value.code == F.FOA_E_DEVICE
+    monkeypatch.delenv("FOA_PERSIST_SPIN")
+    bt, q, st = _run_batch(Xs, "f32", tune=table)
+    assert list(q) == [X.shape[1] for X in Xs] and not any(st)
+    bt.close()
