@@ -17,6 +17,11 @@
       of COPY_BYTES bytes, next to the algorithmic bytes per launch that the
       benchmark printed in BENCH_LOG (its JSON line); written to OUT_JSON with
       the SHA-256 of the kernel source it describes.
+  python -m paper_1805_05821_amd.rocprof_summary batched FETCH_DIR WRITE_DIR \
+         FETCH_SCALE WRITE_SCALE STEPS
+      HBM bytes of the batched form's last run: FETCH_SIZE and WRITE_SIZE of
+      every batched kernel dispatched from the STEPS-th last plan dispatch on,
+      scaled by the calibration factors (bytes per counter unit), per kernel.
 """
 
 import csv
@@ -187,6 +192,36 @@ def window(d, prefix, start, count):
             f"{len(sel)} dispatches, total {sum(ms):.2f} ms, average {sum(ms) / max(len(ms), 1):.4f} ms")
 
 
+def batched_traffic(fetch_dir, write_dir, fetch_scale, write_scale, steps):
+    """Per-kernel HBM bytes of the batched form's last run of STEPS steps."""
+    lines, total = [], 0.0
+    for d, counter, scale in ((fetch_dir, "FETCH_SIZE", float(fetch_scale)),
+                              (write_dir, "WRITE_SIZE", float(write_scale))):
+        per, name = defaultdict(float), {}
+        for f in _find(d, "counter_collection.csv"):
+            for r in csv.DictReader(open(f)):
+                if _col(r, "Counter_Name") != counter:
+                    continue
+                di = int(_col(r, "Dispatch_Id"))
+                per[di] += float(_col(r, "Counter_Value"))
+                name[di] = _col(r, "Kernel_Name")
+        plans = sorted(di for di, n in name.items() if n.startswith("foa::k_batch_plan"))
+        first = plans[-int(steps)]
+        tot = defaultdict(float)
+        for di, v in per.items():
+            n = name[di]
+            if di >= first and ("batch" in n.lower() or "persist" in n):
+                tot[n.split("(")[0]] += v * scale
+        sub = sum(tot.values())
+        total += sub
+        lines.append(f"{counter}: {sub / 1e9:.1f} GB")
+        for k, v in sorted(tot.items(), key=lambda kv: -kv[1]):
+            if v >= 1e8:
+                lines.append(f"    {v / 1e9:9.1f} GB  {k}")
+    lines.append(f"total: {total / 1e9:.1f} GB")
+    return "\n".join(lines)
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "kernels":
         print(summarize_kernels(argv[1]))
@@ -194,6 +229,8 @@ def main(argv):
         print(window(argv[1], argv[2], argv[3], argv[4]))
     elif len(argv) >= 3 and argv[0] == "counter":
         print(summarize_counter(argv[1], argv[2]))
+    elif len(argv) >= 6 and argv[0] == "batched":
+        print(batched_traffic(*argv[1:6]))
     elif len(argv) >= 8 and argv[0] == "traffic":
         import json
 
