@@ -28,7 +28,10 @@ from .dmd import (
     truncation_rank,
     kappa2,
     spacing,
+    packed_modes,
+    packed_coefficients,
 )
+from . import foa, dmd
 
 __all__ = [
     "EPS64",
@@ -45,4 +48,8 @@ __all__ = [
     "truncation_rank",
     "kappa2",
     "spacing",
+    "packed_modes",
+    "packed_coefficients",
+    "foa",
+    "dmd",
 ]

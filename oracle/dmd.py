@@ -3,10 +3,13 @@ state: the post-processing of Algorithm 1 and Algorithm 3, Section 3.2.3
 (error indicators) and Section 3.2.4 (coefficients of the first snapshot,
 eqs. exrecon / exreconwrt).  Plain NumPy float64; test infrastructure only.
 
-Parity status: pinned by tests/test_oracle_pins.py (exact eigenvalue
-recovery on exact-rank data, indicator = true residual for a known map A,
-exact reconstruction of snapshots 1..N-1, truncation reproducing the
-breakdown eigenvalues on rank-deficient data).
+Parity status: pinned by tests/test_oracle_pins.py: exact eigenvalue
+recovery on exact-rank data; untruncated and truncated indicators equal to
+the true residual ||A phi - lambda phi|| for a known map A; truncated
+coefficients equal to the least-squares fit of psi_1 by the explicit modes;
+exact reconstruction of snapshots 1..N-1 from the packed real mode columns;
+the rank rule on hand-computed singular values in both storage precisions;
+truncation reproducing the breakdown eigenvalues on rank-deficient data.
 
 Readings where the paper is silent:
 * eigenvectors z are scaled to unit 2-norm (Section 3.2.3 assumes unit DMD
@@ -43,6 +46,8 @@ def kappa2(M) -> float:
 
 
 def truncation_rank(sigma, nsnap: int, storage: str = "f64") -> int:
+    """Numerical rank of beta_m (the rule of Section 4.1 read with the storage
+    precision): singular values above nsnap times the spacing at sigma_1."""
     sigma = np.asarray(sigma, dtype=np.float64)
     if sigma.size == 0:
         return 0
@@ -68,8 +73,12 @@ def _order(lam, c):
 
 
 def dmd_untruncated(st):
-    """Untruncated DMD of Algorithm 1: eig(H_m); indicators |h_{m+1,m}| |e_m^T z_i| (eq. errordmdvec);
-    coefficients [z]{c} = ||psi_1|| e_1 (eq. exrecon)."""
+    """Untruncated DMD (Algorithm 1 without rank truncation): eigenpairs of the
+    square leading block H_m.  The error indicator of an eigenpair is the size
+    of the Arnoldi residual term, |h_{m+1,m}| times the last entry of the unit
+    eigenvector (Section 3.2.3, eq. errordmdvec).  The coefficients c of
+    psi_1 in the mode basis solve [z] c = V^T psi_1 = ||psi_1|| e_1, since
+    psi_1 = ||psi_1|| v_1 (eq. exrecon)."""
     m = projected_size(st)
     Hm = st.H[:m, :m].copy()
     lam, Z = np.linalg.eig(Hm)
@@ -92,9 +101,18 @@ def dmd_untruncated(st):
 
 
 def dmd_truncated(st, r: int):
-    """Truncated DMD of Algorithm 1: SVD of beta_m, U_r^T H_m U_r, its eigenpairs; indicators
-    ||[(I - U_r U_r^T) H_m ; h_{m+1,m} e_m^T] U_r z_i||_2 (Section 3.2.3);
-    coefficients [z]{c} = ||psi_1|| U_r^T e_1 (eq. exreconwrt)."""
+    """Rank-truncated DMD (Algorithm 1 with rank truncation): beta_m = U S W^T,
+    the projection U_r^T H_m U_r onto the r dominant left singular directions,
+    and its eigenpairs (lambda, z); the modes are V_{1:m} U_r z.
+
+    Indicator (Section 3.2.3): with A V_{1:m} = V_{1:m} H_m + h_{m+1,m}
+    v_{m+1} e_m^T and lambda U_r z = U_r U_r^T H_m U_r z, the residual
+    A V U_r z - lambda V U_r z has coordinates (I - U_r U_r^T) H_m U_r z in
+    V_{1:m} and h_{m+1,m} (U_r z)_m along v_{m+1}; its norm is the indicator.
+
+    Coefficients (eq. exreconwrt): V_{1:m} U_r has orthonormal columns, so
+    the least-squares fit of psi_1 = ||psi_1|| v_1 by the modes solves
+    [z] c = ||psi_1|| U_r^T e_1."""
     m = projected_size(st)
     Hm = st.H[:m, :m].copy()
     U, S, _ = np.linalg.svd(st.beta[:m, :m])
@@ -107,9 +125,9 @@ def dmd_truncated(st, r: int):
     ind = np.empty(r)
     for i in range(r):
         y = Ur @ Z[:, i]
-        top = P @ (Hm @ y)
-        bot = hlast * y[m - 1]
-        ind[i] = np.sqrt(np.linalg.norm(top) ** 2 + abs(bot) ** 2)
+        inside = P @ (Hm @ y)          # coordinates in V_{1:m}
+        along = hlast * y[m - 1]       # coordinate along v_{m+1}
+        ind[i] = np.sqrt(np.linalg.norm(inside) ** 2 + abs(along) ** 2)
     rhs = st.beta[0, 0] * Ur[0, :].astype(np.complex128)
     c = np.linalg.solve(Z, rhs)
     order = _order(lam, c)
@@ -148,3 +166,11 @@ def packed_modes(res, V):
         lams.append(lam)
     Phi = np.stack(cols, axis=1) if cols else np.zeros((V.shape[0], 0))
     return Phi, np.asarray(lams), np.asarray(kinds, dtype=np.int8)
+
+
+def packed_coefficients(res):
+    """Coefficients c_j of psi_1 for the entries of packed_modes, in the same
+    order (one per real eigenvalue, one per conjugate pair: that of its Im > 0
+    member; the other member's is the conjugate for real snapshots)."""
+    return np.asarray([res["coef"][i] for i in res["order"] if res["lam"][i].imag >= 0],
+                      dtype=np.complex128)

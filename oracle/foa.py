@@ -73,34 +73,44 @@ def _new_state(n: int, cap: int, tol) -> FOAState:
 
 
 # ---------------------------------------------------------------------------
-# One iteration j (1-based) of Algorithm 1 / Algorithm 4, split into the
-# paper's stages in its order: partial beta column, w from the snapshot,
-# CGS2, normalisation, beta completion.  Each helper does exactly the
-# operations of its stage.
+# One iteration j (1-based) of the loop of Algorithm 1 / Algorithm 4, in the
+# order the method needs its quantities:
+#   * the part of beta's column j+1 that the known columns of H_bar give,
+#   * the vector A v_j recovered from the snapshot psi_{j+1},
+#   * its orthogonalisation against V_1^j (classical Gram-Schmidt, twice),
+#     which yields H_bar's column j,
+#   * the normalisation that appends v_{j+1},
+#   * the rest of beta's column j+1 from the new Hessenberg column.
 # ---------------------------------------------------------------------------
 
-def _beta_partial(H, beta, j):
-    """Partial beta column (eq. betacolumnupdate without its last term):
-    beta_{1,j+1} = h_{1,1:j-1} beta_{1:j-1,j};
-    beta_{i,j+1} = h_{i,i-1:j-1} beta_{i-1:j-1,j}, i = 2..j."""
-    beta[0, j] = H[0, 0:j - 1] @ beta[0:j - 1, j - 1]
-    for i in range(2, j + 1):
-        beta[i - 1, j] = H[i - 1, i - 2:j - 1] @ beta[i - 2:j - 1, j - 1]
+def _partial_beta_column(H, beta, j):
+    """Expansion coefficients of psi_{j+1} in V_1^j, minus the contribution
+    of the Hessenberg column not yet known.
+
+    psi_{j+1} = A psi_j = A V_1^j beta_{1:j,j}; A maps v_1..v_{j-1} through the
+    first j-1 columns of H_bar (eq. avarnoldi), so the known part is the
+    product of the j x (j-1) leading block of H_bar with beta_{1:j-1,j}
+    (eq. betacolumnupdate; H_bar is upper Hessenberg, so the product is
+    banded).  Returns a vector of length j."""
+    return H[:j, :j - 1] @ beta[:j - 1, j - 1]
 
 
-def _form_w(V, beta, psi, j):
-    """w from the snapshot: w = (psi_{j+1} - sum_{i<=j} beta_{i,j+1} v_i) / beta_{j,j},
-    which equals A v_j (eq. avpsijp1beta)."""
-    return (psi - V[:, :j] @ beta[:j, j]) / beta[j - 1, j - 1]
+def _arnoldi_vector(V, b, bjj, psi, j):
+    """A v_j from the snapshot: psi_{j+1} = V_1^j b + beta_{jj} A v_j, with b
+    the partial column above (eq. avpsijp1beta)."""
+    return (psi - V[:, :j] @ b) / bjj
 
 
 def _cgs2(V, w, j):
-    """Classical Gram-Schmidt with one reorthogonalisation (Algorithm 1)."""
-    h = V[:, :j].T @ w          # projection
-    w = w - V[:, :j] @ h        # first orthogonalisation
-    s = V[:, :j].T @ w          # reprojection
-    h = h + s                   # corrected Hessenberg column
-    w = w - V[:, :j] @ s        # second orthogonalisation
+    """Classical Gram-Schmidt against V_1^j with one reorthogonalisation:
+    two projection passes, each removing V_1^j V_1^jT w from w and adding
+    its coefficients to the Hessenberg column.  Returns (H_bar[0:j, j-1], w)."""
+    Vj = V[:, :j]
+    h = np.zeros(j)
+    for _ in range(2):
+        s = Vj.T @ w
+        w = w - Vj @ s
+        h = h + s
     return h, w
 
 
@@ -109,14 +119,16 @@ def _norm(w):
     return float(np.sqrt(w @ w))
 
 
-def _beta_complete(H, beta, j):
-    """Beta completion: beta_{i,j+1} += h_{i,j} beta_{j,j}, i = 1..j+1."""
-    for i in range(1, j + 2):
-        beta[i - 1, j] = beta[i - 1, j] + H[i - 1, j - 1] * beta[j - 1, j - 1]
+def _completed_beta_column(b, hcol, bjj):
+    """Column j+1 of beta (rows 1..j+1): the partial column plus A v_j's share,
+    beta_{jj} times H_bar's column j (eq. betacolumnupdate)."""
+    col = np.zeros(hcol.shape[0])
+    col[:b.shape[0]] = b
+    return col + hcol * bjj
 
 
 def _first(st: FOAState, psi1):
-    """First snapshot of Algorithm 1 / Algorithm 4: beta_11 = ||psi_1||, v_1 = psi_1 / beta_11."""
+    """First snapshot: beta_11 = ||psi_1|| and v_1 = psi_1 / beta_11."""
     nrm2 = float(psi1 @ psi1)
     st.pushes += 1
     if not np.isfinite(nrm2):
@@ -133,35 +145,34 @@ def _first(st: FOAState, psi1):
 
 
 def _iteration(st: FOAState, psi, j):
-    """Iteration j (1-based) of the loop of Algorithm 1: consumes psi_{j+1}."""
+    """Iteration j (1-based) of the loop of Algorithm 1: consumes psi_{j+1}.
+    Nothing is written to the state before every new quantity is finite."""
     V, H, beta = st.V, st.H, st.beta
     st.pushes += 1
     xn2 = float(psi @ psi)
     if not np.isfinite(xn2):
         st.status = NONFINITE
         return
-    saved = beta[:j + 1, j].copy()
-    _beta_partial(H, beta, j)
-    w = _form_w(V, beta, psi, j)
+    bjj = beta[j - 1, j - 1]
+    b = _partial_beta_column(H, beta, j)
+    w = _arnoldi_vector(V, b, bjj, psi, j)
     h, w = _cgs2(V, w, j)
     hn = _norm(w)
     if not (np.all(np.isfinite(h)) and np.isfinite(hn)):
-        beta[:j + 1, j] = saved
         st.status = NONFINITE
         return
     st.xfro2 += xn2
-    H[:j, j - 1] = h
-    bnew = hn * beta[j - 1, j - 1]
     st.hist_h.append(hn)
-    if bnew <= st.tol * np.sqrt(st.xfro2):
-        # psi_{j+1} lies in span(v_1..v_j): exact Ritz pairs, stop (Section 3.2.4)
-        H[j, j - 1] = 0.0
-        _beta_complete(H, beta, j)
+    # psi_{j+1} in span(v_1..v_j) (the reading of h_{j+1,j} = 0 stated above):
+    # the exact Ritz pairs are in the square H_j (Section 3.2.4), stop
+    dependent = hn * bjj <= st.tol * np.sqrt(st.xfro2)
+    hcol = np.append(h, 0.0 if dependent else hn)
+    H[:j + 1, j - 1] = hcol
+    beta[:j + 1, j] = _completed_beta_column(b, hcol, bjj)
+    if dependent:
         st.status = INVARIANT
         return
-    H[j, j - 1] = hn              # normalisation
     V[:, j] = w / hn
-    _beta_complete(H, beta, j)
     st.q = j + 1
 
 
@@ -218,7 +229,9 @@ def foa_stream_update(st: FOAState, Xp) -> FOAState:
 # ---------------------------------------------------------------------------
 
 def arnoldi_known_A(A, psi1, N):
-    """Algorithm 2's Arnoldi loop with CGS2 orthogonalisation.
+    """Arnoldi's method with the map A known (Algorithm 2), orthogonalising
+    with two classical Gram-Schmidt passes (its own code, so that a mistake in
+    the FOA helpers does not carry over to this reference).
 
     Returns (V (n x N), H_bar (N x (N-1)))."""
     A = np.asarray(A, dtype=np.float64)
@@ -228,11 +241,12 @@ def arnoldi_known_A(A, psi1, N):
     V[:, 0] = psi1 / _norm(psi1)
     for j in range(1, N):
         w = A @ V[:, j - 1]                 # Krylov step
-        h = V[:, :j].T @ w                  # projection
-        w = w - V[:, :j] @ h                # first orthogonalisation
-        s = V[:, :j].T @ w                  # reprojection
-        h = h + s
-        w = w - V[:, :j] @ s                # second orthogonalisation
+        Vj = V[:, :j]
+        h = np.zeros(j)
+        for _ in range(2):                  # written out here, independent of _cgs2
+            c = Vj.T @ w
+            w = w - Vj @ c
+            h = h + c
         hn = _norm(w)
         H[:j, j - 1] = h
         H[j, j - 1] = hn
