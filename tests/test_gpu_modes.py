@@ -6,7 +6,7 @@ import pytest
 
 import datagen
 import oracle
-from gpu_helpers import announce, run_gpu
+from gpu_helpers import EPS32, announce, run_gpu
 from oracle.dmd import packed_modes
 from pins import _known_A, _krylov, match_eigs
 
@@ -200,4 +200,66 @@ def test_mfma_modes_match_fp64_accumulation(n, N, r_force):
              f"(bound {tol:.1e})")
     assert np.isfinite(P32).all()
     assert err.max() <= tol
+    s.close()
+
+
+@pytest.mark.parametrize("n,N,r_force", [(100037, 101, -1), (100037, 101, 37), (5000, 300, -1),
+                                         (70001, 260, 97)])
+def test_mfma_modes_match_oracle(n, N, r_force):
+    """The FP32 MFMA mode reconstruction (FP32 basis, FP32 mode matrix) against
+    the oracle's modes V_{1:m} U_r z_i (Algorithm 1, both branches), column by
+    column after matching eigenvalues, up to the unit factor an eigenvector
+    is defined with.  Ragged rows (128-row tiles), ragged 32-deep k chunks,
+    ragged 32-mode blocks and, for N = 260/300, a second 256-mode tile.
+    Gaussian snapshots: kappa_2 ~ 3, so the bound is tight: 10 eps32
+    (sqrt(k) + kappa_r gap_r) for the basis and subspace, plus the
+    first-order eigenvector change ||dT|| s_i, plus the FP32 accumulation of
+    the reconstruction, (k + 2) sqrt(k) 2^-24."""
+    import torch
+
+    import parity_bounds as PB
+    from paper_1805_05821_amd import foa as F
+
+    rng = np.random.default_rng(n + N + max(r_force, 0))
+    X = rng.standard_normal((n, N)).astype(np.float32)
+    st = oracle.foa_batch(X.astype(np.float64), tol=0.0)
+    g = run_gpu(X, "f32", tol=0.0)
+    s = g["stream"]
+    m = g["m"]
+    assert g["q"] == st.q == N
+    r = m if r_force < 0 else r_force
+    if r_force > 0:
+        assert s.truncate(r_force=r_force)[0] == r_force
+        res = oracle.dmd_truncated(st, r)
+        T = res["Ur"].T @ st.H[:m, :m] @ res["Ur"]
+    else:
+        res = oracle.dmd_untruncated(st)
+        T = st.H[:m, :m]
+    sig = PB.svals(st.beta[:m, :m])
+    kr, gr = PB.kappa_r(sig, r), PB.gap_factor(sig, r)
+    lam_c, Z, Yn, cond = PB.eig_condition(T)
+    sens = PB.eigvec_sensitivity(lam_c, Z, Yn)
+    Hn = np.linalg.norm(st.H[:m + 1, :m], 2)
+    dT = PB.C * EPS32 * kr * (1.0 + 2.0 * gr) * Hn
+    Phi_o, lam_o, kind_o = packed_modes(res, st.V)
+    cols = Phi_o.shape[1]
+    phi = torch.full((cols + 3, n), float("nan"), dtype=torch.float32, device="cuda")
+    lam_g, kind, amp, err = F.foa_modes(s.ctx, m, phi, n, cols + 3, F.FOA_F32)
+    ncols = int(np.sum(np.where(kind == 1, 2, 1)))
+    assert ncols == cols and torch.isnan(phi[ncols:]).all()
+    Pg = PB.unpack(phi[:ncols].double().cpu().numpy().T, kind)
+    Po = PB.unpack(Phi_o, kind_o)
+    ja, jb = PB.match(lam_g, lam_o)
+    io, ic = PB.match(lam_o, lam_c)
+    sens_o = np.empty(len(lam_o))
+    sens_o[io] = sens[ic]
+    k = m
+    worst, worst_err = 0.0, 0.0
+    for a, b in zip(ja, jb):
+        e = PB.phase_aligned_error(Pg[a], Po[b])
+        tol = PB.C * EPS32 * (np.sqrt(k) + kr * gr) + dT * sens_o[b] + (k + 2) * np.sqrt(k) * 2.0 ** -24
+        worst, worst_err = max(worst, e / tol), max(worst_err, e)
+    announce(f"n={n} N={N} r={r}: {len(ja)} entries / {ncols} columns, kappa_r={kr:.2e}, "
+             f"max phase-aligned column error {worst_err:.2e}, max err/bound {worst:.2e}")
+    assert worst <= 1.0
     s.close()
