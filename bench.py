@@ -38,7 +38,7 @@ def log(*a):
     sys.stderr.flush()
 
 
-def run_form(prec, X, n, N, warmup, steps, options):
+def run_form(prec, X, n, N, warmup, steps, options, r_force=0):
     import torch
 
     from paper_1805_05821_amd import foa as F
@@ -74,10 +74,13 @@ def run_form(prec, X, n, N, warmup, steps, options):
     launches, kms, kbytes = F.foa_profile(s.ctx)
     s.set_option("profile", 0)
     H, B, q, m = s.state()
+    # truncated DMD of the last run: the storage precision's rank rule, or r_force
+    r_tr, _ = s.truncate(r_force=r_force)
+    lam_tr, ind_tr = s.indicators()
     log(f"[{prec}] {steps} steps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), q={q}, "
-        f"row passes {launches} launches {kms:.1f} ms {kbytes / kms / 1e6:.1f} GB/s")
+        f"row passes {launches} launches {kms:.1f} ms {kbytes / kms / 1e6:.1f} GB/s, truncated rank {r_tr}")
     res = dict(ms_per_step=ms / steps, wall_s=wall, q=q, status=st, H=H, beta=B, m=m,
-               pass_launches=launches, pass_ms=kms, pass_bytes=kbytes)
+               pass_launches=launches, pass_ms=kms, pass_bytes=kbytes, r_trunc=r_tr, lam_trunc=lam_tr)
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -117,9 +120,33 @@ def run_blocked(prec, X, n, N, warmup, steps):
     return dict(ms_per_step=ms / steps, q=q, H=H, m=m)
 
 
-def run_batched(bw, warmup, steps, streams=None):
+def _stream_gate(H32, lam32, r, H64, B64, m):
+    """One stream's truncated FP32-vs-FP64 gate (see truncated_gate)."""
+    import numpy as np
+    from scipy.optimize import linear_sum_assignment
+
+    U, sig, _ = np.linalg.svd(B64[:m, :m])
+    kap_r = float(sig[0] / sig[r - 1])
+    T = U[:, :r].T @ H64[:m, :m] @ U[:, :r]
+    lam, Z = np.linalg.eig(T)
+    Z = Z / np.linalg.norm(Z, axis=0)
+    Y = np.linalg.inv(Z).conj().T
+    Y = Y / np.linalg.norm(Y, axis=0)
+    cond = 1.0 / np.abs(np.sum(Y.conj() * Z, axis=0))
+    la = np.concatenate([lam32, lam32[lam32.imag > 0].conj()])
+    C = np.abs(la[:, None] - lam[None, :])
+    ia, ib = linear_sum_assignment(C)
+    ratio = C[ia, ib] / (10 * EPS32 * kap_r * np.maximum(1.0, cond[ib]))
+    return float(ratio.max()), kap_r
+
+
+def run_batched(bw, warmup, runs, streams=None):
     """The batched form on a batched workload: every stream from q = 0 to its
-    N_s snapshots; one run = max N_s graph launches."""
+    N_s snapshots; one run = max N_s graph launches.  The median of ``runs``
+    timed runs is reported.  After timing, every stream is checked: basis
+    orthogonality ||I - V^T V||_2 against 10 sqrt(q) eps32, and its truncated
+    DMD (FP32 rank rule) against an FP64-basis batch of the same streams
+    (untimed) by the eigenvalue gate 10 eps32 kappa_r cond_i."""
     import numpy as np
     import torch
 
@@ -149,35 +176,65 @@ def run_batched(bw, warmup, steps, streams=None):
         j = np.arange(N[s], dtype=np.float64)
         alg += n[s] * (3.0 * 4.0 * j.sum() + 8.0 * N[s])
 
-    def one_run():
-        bt.reset()
+    def one_run(b):
+        b.reset()
         for k in range(T):
-            bt.push_ptrs(dptr[k], F.FOA_F32)
+            b.push_ptrs(dptr[k], F.FOA_F32)
 
     for _ in range(warmup):
-        one_run()
+        one_run(bt)
         bt.sync()
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(steps):
-        one_run()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    times = []
+    for _ in range(runs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        one_run(bt)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
     q, st = bt.sync()
     ok = bool(np.all(q == np.array(N)) and np.all(st == 0))
+    # per-stream checks (untimed)
+    b64 = FOABatch(n, N, prec="f64")
+    one_run(b64)
+    q64, st64 = b64.sync()
+    worst_orth, worst_eig, worst_kr = 0.0, 0.0, 0.0
+    for s in range(S):
+        v32, v64 = bt.view(s), b64.view(s)
+        qs = int(q[s])
+        V = torch.empty((qs, n[s]), dtype=torch.float64, device="cuda")
+        F.foa_copy_basis(v32, V, n[s], F.FOA_F64, qs)
+        G = (V @ V.T).cpu().numpy()
+        orth = float(np.abs(np.linalg.eigvalsh(np.eye(qs) - G)).max()) / (10 * np.sqrt(qs) * EPS32)
+        r, _ = F.foa_truncate(v32)
+        lam32, _ = F.foa_indicators(v32, qs)
+        H64, B64, _, m = F.foa_get_state(v64)
+        ratio, kr = _stream_gate(None, lam32, r, H64, B64, m)
+        worst_orth, worst_eig, worst_kr = max(worst_orth, orth), max(worst_eig, ratio), max(worst_kr, kr)
+        del V
+    b64.close()
     bt.close()
     del Xs
     torch.cuda.empty_cache()
     gbs = alg / (ms / 1e3) / 1e9
-    log(f"[batched] {ms:.1f} ms per run of {T} steps, {sum(N) / (ms / 1e3):.0f} snapshots/s, {gbs:.0f} GB/s")
+    log(f"[batched] median {ms:.1f} ms per run of {T} steps (runs {[round(t, 1) for t in times]}), "
+        f"{sum(N) / (ms / 1e3):.0f} snapshots/s, {gbs:.0f} GB/s; worst stream: orth/bound {worst_orth:.2e}, "
+        f"truncated eig err/bound {worst_eig:.2e}")
     return {"workload": bw.name, "streams": S, "form": "fp32-basis-cgs2, one graph launch per step",
             "snapshots_per_run": int(sum(N)), "steps_per_run": int(T), "ms_per_run": round(ms, 3),
+            "runs_ms": [round(t, 3) for t in times], "timing": f"median of {runs} runs after {warmup} warm-up",
             "value": round(sum(N) / (ms / 1e3), 1), "unit": "snapshots/s",
             "achieved_gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
-            "alg_bytes_per_run": alg, "all_streams_complete": ok}
+            "alg_bytes_per_run": alg, "all_streams_complete": ok and bool(np.all(q64 == np.array(N))),
+            "per_stream_error": {
+                "max_orthogonality_over_bound": worst_orth,
+                "max_truncated_eig_err_over_bound": worst_eig,
+                "max_kappa_r": worst_kr,
+                "reference": "FP64-basis batch of the same streams; bounds 10 sqrt(q) eps32 and "
+                             "10 eps32 kappa_r cond_i at the FP32 rank rule's r"}}
 
 
 FP32_MFMA_PEAK_TFLOPS = 157.3
@@ -241,28 +298,128 @@ def run_large(w, gemm_reps=3):
             "dominant_eig_max_distance": dist}
 
 
-def cpu_baseline(w, rows):
-    import numpy as np
-
-    import datagen
-    import oracle
-
+def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
 
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
-        threads = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def _time_oracle(X64, threads=None):
+    import oracle
+
+    if threads is None:
+        t0 = time.perf_counter()
+        st = oracle.foa_batch(X64)
+        return time.perf_counter() - t0, st
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        st = oracle.foa_batch(X64)
+        return time.perf_counter() - t0, st
+
+
+def cpu_baseline(w, rows, rows_1t):
+    """The oracle (plain NumPy FP64, as it stands) on the host: all BLAS
+    threads on ``rows`` rows, one thread on ``rows_1t`` rows, all N
+    snapshots; the time per snapshot scales linearly in n (every stage of an
+    iteration is a sweep over the rows), so it is scaled to the workload's n."""
+    import numpy as np
+
+    import datagen
+
+    threads = _blas_threads()
     X, _, _ = datagen.snapshots_numpy(w, n=rows, dtype="float32")
     X64 = np.asfortranarray(X.astype(np.float64))
-    t0 = time.perf_counter()
-    st = oracle.foa_batch(X64)
-    t = time.perf_counter() - t0
+    t, st = _time_oracle(X64)
     scale = w.n / rows
+    X1 = np.asfortranarray(X64[:rows_1t])
+    t1, _ = _time_oracle(X1, threads=1)
+    scale1 = w.n / rows_1t
     return dict(value=w.N / (t * scale), unit="snapshots/s", cores=int(threads), kind="oracle",
                 sample=f"oracle FOA over all N={w.N} snapshots of the same workload at n={rows} rows "
                        f"(1/{scale:g} of the rows), {t:.1f} s; time scaled linearly in n to n={w.n}",
-                seconds=t, q=st.q)
+                seconds=t, q=st.q,
+                single_thread={"value": w.N / (t1 * scale1), "unit": "snapshots/s", "cores": 1,
+                               "sample": f"same, n={rows_1t} rows (1/{scale1:g}), one BLAS thread, {t1:.1f} s"})
+
+
+def oracle_full_timings():
+    """The oracle at the full size of the workloads that fit host memory:
+    exact_rank_4096x64, noisy_2p20x200 (all threads and one thread) and the
+    256 streams of batched_256 one after another (all threads)."""
+    import numpy as np
+
+    import datagen
+
+    threads = _blas_threads()
+    out = {"cpu_threads": int(threads), "cpu_model": _cpu_model()}
+    for name in ("exact_rank_4096x64", "noisy_2p20x200"):
+        w = datagen.get_workload(name)
+        X, _, _ = datagen.snapshots_numpy(w, dtype="float64")
+        X = np.asfortranarray(X)
+        t, st = _time_oracle(X)
+        t1, _ = _time_oracle(X, threads=1)
+        out[name] = {"n": w.n, "N": w.N, "q": st.q, "seconds_all_threads": t, "seconds_1_thread": t1,
+                     "snapshots_per_s_all_threads": st.pushes / t, "snapshots_per_s_1_thread": st.pushes / t1}
+        log(f"[oracle] {name}: {t:.2f} s ({threads} threads), {t1:.2f} s (1 thread)")
+    bw = datagen.get_workload("batched_256")
+    total, snaps = 0.0, 0
+    for w in datagen.batched_streams(bw):
+        X, _, _ = datagen.snapshots_numpy(w, dtype="float32")
+        X = np.asfortranarray(X.astype(np.float64))
+        t, st = _time_oracle(X)
+        total += t
+        snaps += st.pushes
+    out["batched_256"] = {"streams": bw.streams, "snapshots": snaps, "seconds_all_threads": total,
+                          "snapshots_per_s_all_threads": snaps / total}
+    log(f"[oracle] batched_256: {total:.1f} s for {snaps} snapshots ({threads} threads)")
+    return out
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def truncated_gate(a, b):
+    """Truncated DMD of the FP32-basis run (rank rule of its storage
+    precision) against the FP64-basis run truncated to the same rank: per
+    matched eigenvalue |d lambda_i| <= 10 eps32 kappa_r cond_i, with
+    kappa_r = sigma_1 / sigma_r of the FP64 run's beta_m and cond_i the
+    eigenvalue condition number of its U_r^T H_m U_r (host FP64 NumPy on the
+    library's outputs).  10 eps32 kappa_r < 1 whenever the rank rule chose r,
+    so the gate binds."""
+    import numpy as np
+    from scipy.optimize import linear_sum_assignment
+
+    r, m = a["r_trunc"], b["m"]
+    U, sig, _ = np.linalg.svd(b["beta"][:m, :m])
+    kap_r = float(sig[0] / sig[r - 1])
+    T = U[:, :r].T @ b["H"][:m, :m] @ U[:, :r]
+    lam, Z = np.linalg.eig(T)
+    Z = Z / np.linalg.norm(Z, axis=0)
+    Y = np.linalg.inv(Z).conj().T
+    Y = Y / np.linalg.norm(Y, axis=0)
+    cond = 1.0 / np.abs(np.sum(Y.conj() * Z, axis=0))
+    la = np.asarray(a["lam_trunc"])
+    la = np.concatenate([la, la[la.imag > 0].conj()])
+    C = np.abs(la[:, None] - lam[None, :])
+    ia, ib = linear_sum_assignment(C)
+    err = C[ia, ib]
+    bound = 10 * EPS32 * kap_r * np.maximum(1.0, cond[ib])
+    return {"rank": int(r), "rank_f64_run": int(b["r_trunc"]), "kappa_r": kap_r,
+            "bound_10_eps32_kappa_r": 10 * EPS32 * kap_r,
+            "max_abs_eig_err": float(err.max()), "max_err_over_bound": float((err / bound).max()),
+            "within_bound": bool(np.all(err <= bound)), "eigenvalues": int(len(la))}
 
 
 def traffic_from_profiles(kind):
@@ -294,11 +451,18 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the n = 1e8 run and its mode reconstruction")
     ap.add_argument("--cpu-rows", type=int, default=1 << 20)
+    ap.add_argument("--cpu-rows-1t", type=int, default=1 << 15)
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="only time the CPU oracle at full size on the workloads that fit host memory")
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--prefetch", type=int, default=-1)
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
+
+    if args.oracle_full:
+        print(json.dumps(oracle_full_timings()), flush=True)
+        return
 
     if args.copy_calibration > 0:
         import torch
@@ -339,7 +503,8 @@ def main():
     if args.prefetch >= 0:
         options["prefetch"] = args.prefetch
     r32 = run_form("f32", X, n, N, args.warmup, args.steps, options)
-    r64 = None if args.no_f64 else run_form("f64", X, n, N, args.warmup, args.steps, options)
+    r64 = None if args.no_f64 else run_form("f64", X, n, N, args.warmup, args.steps, options,
+                                            r_force=r32["r_trunc"])
 
     snaps = N / (r32["ms_per_step"] / 1e3)
     achieved = r32["pass_bytes"] / (r32["pass_ms"] / 1e3) / 1e9
@@ -392,6 +557,7 @@ def main():
         out["speedup_f32_vs_f64"] = round(snaps / snaps64, 3)
         out["error_f32_vs_f64"] = {"rel_H_2norm": eH, "kappa2": kap, "bound_10_eps32_kappa": 10 * EPS32 * kap,
                                    "within_bound": bool(eH <= 10 * EPS32 * kap)}
+        out["error_f32_vs_f64_truncated"] = truncated_gate(r32, r64)
     if not args.no_blocked:
         try:
             rb = run_blocked("f32", X, n, N, args.warmup, args.steps)
@@ -413,7 +579,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         try:
-            out["batched_form"] = run_batched(datagen.get_workload("batched_256"), 1, 1)
+            out["batched_form"] = run_batched(datagen.get_workload("batched_256"), 1, 3)
         except Exception as e:  # reported, never silently dropped
             out["batched_form"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_large:
@@ -423,7 +589,7 @@ def main():
             out["large_form"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu:
         log(f"cpu baseline: oracle on {args.cpu_rows} rows ...")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows, args.cpu_rows_1t)
     print(json.dumps(out), flush=True)
 
 
