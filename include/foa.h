@@ -21,8 +21,9 @@
  *  - Device memory: the caller owns every device buffer.  The library keeps
  *    its whole device state in one caller-provided workspace (at least
  *    foa_workspace_bytes() bytes, 256-byte aligned) and never allocates or
- *    frees device memory.  Host scratch is library-owned and released by
- *    foa_destroy().
+ *    frees device memory; the one device memory it holds itself is the static
+ *    block workspace of foa_push_blocked_static (a fixed-size array per
+ *    device).  Host scratch is library-owned and released by foa_destroy().
  *  - Streams: all device work is enqueued on the hipStream_t given to
  *    foa_init (passed as void*); calls that return device results are
  *    stream-ordered, calls that return host results synchronise the stream.
@@ -122,6 +123,27 @@ foa_status foa_block_workspace_bytes(int64_t n, int32_t n_max, foa_prec prec, si
  * view or a stream that is not active; FOA_E_NOMEM for a small workspace. */
 foa_status foa_push_blocked(foa_ctx ctx, const void *d_X, int64_t ld, int32_t p, foa_dtype x_dtype,
                             void *d_bws, size_t bws_bytes);
+
+/* Size of the library's static block workspace (foa_push_blocked_static):
+ * 64 MiB per device, enough for foa_block_workspace_bytes(n, n_max, prec)
+ * up to about n = 1.5 million rows at n_max = 512 (about 2 million at
+ * n_max = 64). */
+#define FOA_BLOCK_STATIC_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): foa_push_blocked
+ * with its block workspace taken from a static device array of
+ * FOA_BLOCK_STATIC_BYTES that the library holds on each device it runs on
+ * (until the process ends) instead of a caller buffer.  Same arguments,
+ * results and errors as foa_push_blocked; allocates nothing.  FOA_E_NOMEM
+ * (nothing enqueued) when foa_block_workspace_bytes(n, n_max, prec) exceeds
+ * FOA_BLOCK_STATIC_BYTES; FOA_E_DEVICE if the array's device address could
+ * not be looked up.  Every call on one device shares that device's array:
+ * calls that overlap on one device (several contexts used from several host
+ * threads, or on several streams at once) race and give wrong results; the
+ * array keeps the last call's contents, and every call writes each value
+ * before it reads it (the block-rejection flag is cleared by a kernel). */
+foa_status foa_push_blocked_static(foa_ctx ctx, const void *d_X, int64_t ld, int32_t p, foa_dtype x_dtype);
 
 /* In-place fill target for the next snapshot (the memory note of Appendix
  * A.1: a new snapshot may occupy storage the method already holds): *d_col receives a device buffer of n FP64 entries inside the

@@ -358,6 +358,12 @@ foa_status foa_init(foa_ctx *out, int64_t n, int32_t n_max, foa_prec prec, void 
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->L = L;
   c->device = dev;
+  {
+    // set-up of foa_push_blocked_static on this device (once per device); an
+    // error is kept and reported by that entry point, not here
+    char *scratch_addr = nullptr;
+    (void)block_static_scratch(dev, &scratch_addr);
+  }
   c->cus = cus;
   c->grid_auto = 2 * cus;
   c->prefetch = true;  // register double buffering wherever the tile fits

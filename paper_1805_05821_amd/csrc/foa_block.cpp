@@ -90,6 +90,9 @@ hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const vo
   return launch_nextb(sa, s);
 }
 
+foa_status push_blocked_impl(foa_ctx_s *c, const void *d_X, int64_t ld, int32_t p, foa_dtype x_dtype,
+                             char *bws, const BlockLayout &L);
+
 }  // namespace
 
 extern "C" {
@@ -111,6 +114,33 @@ foa_status foa_push_blocked(foa_ctx c, const void *d_X, int64_t ld, int32_t p, f
   const BlockLayout L = block_layout(c->n, c->n_max, c->L.ldg);
   if (bws_bytes < L.total || reinterpret_cast<uintptr_t>(d_bws) % kAlign)
     return set_err(c, FOA_E_NOMEM, "block workspace of %zu bytes needed", L.total);
+  return push_blocked_impl(c, d_X, ld, p, x_dtype, static_cast<char *>(d_bws), L);
+}
+
+foa_status foa_push_blocked_static(foa_ctx c, const void *d_X, int64_t ld, int32_t p, foa_dtype x_dtype) {
+  if (!c) return FOA_E_ARG;
+  if (!d_X || (x_dtype != FOA_F32 && x_dtype != FOA_F64) || p < 0 || (p > 0 && ld < c->n))
+    return set_err(c, FOA_E_ARG, "bad blocked-push arguments");
+  if (c->is_view) return set_err(c, FOA_E_STATE, "blocked pushes go to a single stream, not a batch view");
+  const BlockLayout L = block_layout(c->n, c->n_max, c->L.ldg);
+  if (L.total > FOA_BLOCK_STATIC_BYTES)
+    return set_err(c, FOA_E_NOMEM,
+                   "the static block workspace holds %zu bytes; this stream needs %zu (n or n_max too large)",
+                   (size_t)FOA_BLOCK_STATIC_BYTES, L.total);
+  char *bws = nullptr;
+  const hipError_t e = block_static_scratch(c->device, &bws);
+  if (e != hipSuccess || !bws) return hip_err(c, e != hipSuccess ? e : hipErrorUnknown, "static block workspace");
+  return push_blocked_impl(c, d_X, ld, p, x_dtype, bws, L);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Everything of a blocked push after argument checks; bws is the block
+// workspace (the caller's, or the static one).
+foa_status push_blocked_impl(foa_ctx_s *c, const void *d_X, int64_t ld, int32_t p, foa_dtype x_dtype,
+                             char *bws, const BlockLayout &L) {
   foa_status r = sync_state(c);
   if (r != FOA_OK) return r;
   if (c->dev_status != ST_ACTIVE) return set_err(c, FOA_E_STATE, "stream is not active");
@@ -118,7 +148,6 @@ foa_status foa_push_blocked(foa_ctx c, const void *d_X, int64_t ld, int32_t p, f
   const bool x64 = x_dtype == FOA_F64;
   const size_t es = x64 ? 8 : 4;
   const char *X = static_cast<const char *>(d_X);
-  char *bws = static_cast<char *>(d_bws);
   int *flag = reinterpret_cast<int *>(bws + L.flag);
   // the block passes address a block through one 32-bit buffer range
   const bool range_ok = (double)(BPK * ld + PANEL) * es < 4294967295.0;
@@ -177,4 +206,6 @@ foa_status foa_push_blocked(foa_ctx c, const void *d_X, int64_t ld, int32_t p, f
   return sync_state(c);
 }
 
-}  // extern "C"
+
+}  // namespace
+

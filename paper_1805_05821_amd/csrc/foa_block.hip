@@ -23,9 +23,49 @@
 //               the next pass's coefficients;
 //   k_bchol   : Gram reduction, (shifted) Cholesky and triangular inverse;
 //   k_bcommit : breakdown test, beta, H_bar, sigma and the scalar state.
+#include <mutex>
+
+#include "foa.h"
 #include "foa_device.h"
 
+// Block workspace of foa_push_blocked_static, for callers that cannot
+// allocate device memory: one copy per device the library runs on, held
+// until the process ends.  Host code never uses this name as an address:
+// block_static_scratch() looks the device address up once per device and
+// every launch takes that address.
+static __device__ __align__(256) char scratch[FOA_BLOCK_STATIC_BYTES];
+
 namespace foa {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_addr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+}  // namespace
+
+hipError_t block_static_scratch(int device, char **ptr) {
+  *ptr = nullptr;
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+    void *addr = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+    if (cur >= 0 && cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    g_scratch_addr[device] = e == hipSuccess ? static_cast<char *>(addr) : nullptr;
+    g_scratch_err[device] = e;
+    g_scratch_done[device] = true;
+  }
+  *ptr = g_scratch_addr[device];
+  return g_scratch_err[device];
+}
 
 enum { BP_R1 = 0, BP_Z1 = 1, BP_Z2 = 2 };
 bool block_supported(bool tv_f64, int qw);

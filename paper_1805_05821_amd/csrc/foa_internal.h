@@ -187,6 +187,9 @@ hipError_t launch_breduce(int mode, const BlockArgs &a, hipStream_t s);
 hipError_t launch_bchol(int round, const BlockArgs &a, hipStream_t s);
 hipError_t launch_bcommit(const BlockArgs &a, hipStream_t s);
 hipError_t launch_bflag_clear(int *flag, hipStream_t s);
+// Device address of this device's static block workspace (looked up once per
+// device with that device current; the result, or the lookup's error, is kept).
+hipError_t block_static_scratch(int device, char **ptr);
 // wavefronts per row-pass workgroup at basis size j (nw_opt 0: automatic)
 int pass_nw(bool tv_f64, int nw_opt, int j);
 // resident workgroups per CU of the row-pass kernel used at tile width qw

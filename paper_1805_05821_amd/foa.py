@@ -36,6 +36,7 @@ EXPORTED = [
     "foa_get_state", "foa_copy_basis", "foa_copy_basis_rows", "foa_truncate", "foa_modes", "foa_indicators",
     "foa_reset", "foa_destroy", "foa_status_str", "foa_last_error", "foa_set_option", "foa_profile",
     "foa_profile_modes", "foa_next_column", "foa_block_workspace_bytes", "foa_push_blocked",
+    "foa_push_blocked_static",
     "foa_batch_workspace_bytes", "foa_batch_init", "foa_batch_push", "foa_batch_sync",
     "foa_batch_view", "foa_batch_reset", "foa_batch_destroy",
 ]
@@ -83,6 +84,7 @@ def _load():
         "foa_next_column": [P, P],
         "foa_block_workspace_bytes": [ctypes.c_int64, ctypes.c_int32, ctypes.c_int, P],
         "foa_push_blocked": [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, P, ctypes.c_size_t],
+        "foa_push_blocked_static": [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int],
         "foa_batch_workspace_bytes": [i32, P, P, c.c_int, c.POINTER(sz)],
         "foa_batch_init": [c.POINTER(P), i32, P, P, c.c_int, P, sz, P, f64, c.c_char_p],
         "foa_batch_push": [P, P, c.c_int],
@@ -264,6 +266,13 @@ def foa_block_workspace_bytes(n, n_max, prec):
 def foa_push_blocked(ctx, X, ld, p, x_dtype, bws, bws_bytes):
     return _check(lib.foa_push_blocked(ctx, _addr(X), int(ld), int(p), int(x_dtype), _addr(bws),
                                        int(bws_bytes)), ctx)
+
+
+def foa_push_blocked_static(ctx, X, ld, p, x_dtype):
+    return _check(lib.foa_push_blocked_static(ctx, _addr(X), int(ld), int(p), int(x_dtype)), ctx)
+
+
+FOA_BLOCK_STATIC_BYTES = 64 << 20
 
 
 def foa_next_column(ctx):

@@ -41,6 +41,12 @@ class FOAStream:
         dt = F.FOA_F64 if str(X.dtype) == "torch.float64" else F.FOA_F32
         return F.foa_push_blocked(self.ctx, X, X.stride(0), X.shape[0], dt, self.bws, self.bws.numel())
 
+    def push_blocked_static(self, X):
+        """As push_blocked, with the library's static block workspace
+        (foa_push_blocked_static: nothing is allocated)."""
+        dt = F.FOA_F64 if str(X.dtype) == "torch.float64" else F.FOA_F32
+        return F.foa_push_blocked_static(self.ctx, X, X.stride(0), X.shape[0], dt)
+
     def push_block(self, X):
         dt = F.FOA_F64 if str(X.dtype) == "torch.float64" else F.FOA_F32
         return F.foa_push_block(self.ctx, X, X.stride(0), X.shape[0], dt)
