@@ -8,7 +8,10 @@ package never imports the product path.
 Everything here is plain NumPy in float64, written from the paper:
 Algorithm 1 (batch FOA-based DMD), Algorithm 2 (Rayleigh-Ritz with Arnoldi,
 used only as a known-A test reference), Algorithms 3/4 (streaming form), the
-error indicators of Section 3.2.3 and the coefficients of Section 3.2.4.
+error indicators of Section 3.2.3 and the coefficients of Section 3.2.4;
+``lowsync`` is the one-reduction form of the FOA step (the QR view of
+Section 3.1 with the two Gram-Schmidt projections of consecutive snapshots
+sharing one sweep and one reduction).
 """
 
 from .foa import (
@@ -31,7 +34,7 @@ from .dmd import (
     packed_modes,
     packed_coefficients,
 )
-from . import foa, dmd
+from . import foa, dmd, lowsync
 
 __all__ = [
     "EPS64",
@@ -52,4 +55,5 @@ __all__ = [
     "packed_coefficients",
     "foa",
     "dmd",
+    "lowsync",
 ]
