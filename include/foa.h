@@ -97,6 +97,38 @@ foa_status foa_init(foa_ctx *ctx, int64_t n, int32_t n_max, foa_prec prec, void 
  * breakdown are ignored on the device). */
 foa_status foa_push_snapshot(foa_ctx ctx, const void *d_x, foa_dtype x_dtype);
 
+/* ---- one-reduction form ---------------------------------------------------- */
+
+typedef enum {
+  FOA_FORM_CGS2 = 0,           /* Algorithm 1's order: CGS2 of w = A v_j, three sweeps per push */
+  FOA_FORM_ONE_REDUCTION = 1   /* QR view with delayed reorthogonalisation: one sweep per push */
+} foa_form;
+
+/* Choose how pushes orthogonalise (before the first push: after foa_init or
+ * foa_reset; FOA_E_STATE otherwise, and on a batch view).
+ * FOA_FORM_ONE_REDUCTION factorises the snapshots X = V beta directly (the QR
+ * view of Section 3.1) and takes H_bar from beta through eq.
+ * betacolumnupdate, with the two classical Gram-Schmidt projections of
+ * consecutive snapshots sharing one sweep over the basis and one global
+ * reduction (delayed reorthogonalisation, Bielich et al., Parallel Computing
+ * 2022) instead of the three of Algorithm 1 (the message count of Section
+ * 3.2.5).  Same factors in exact arithmetic, rounding of the same
+ * O(eps kappa_2) order.  A column becomes final two pushes after its
+ * snapshot: every synchronising call (foa_sync and the calls returning host
+ * data) first finishes the pending columns (up to two sweeps; foa_flush does
+ * this stream-ordered), and a dependent snapshot is found when its column
+ * finishes (the stream then becomes invariant with the columns before it,
+ * as in the three-sweep form).  The snapshot is copied into the basis, so the
+ * caller may reuse its buffer once the stream has passed the push.  The
+ * blocked form and foa_next_column are not available (FOA_E_STATE).
+ * FOA_E_ARG for an FP64 basis with n_max > 257 (the sweep's register tile). */
+foa_status foa_set_form(foa_ctx ctx, foa_form form);
+
+/* One-reduction form: finish the pending columns (stream-ordered, no host
+ * synchronisation); afterwards foa_copy_basis sees every snapshot taken.
+ * No effect for the three-sweep form. */
+foa_status foa_flush(foa_ctx ctx);
+
 /* ---- blocked form (p snapshots per basis sweep) ---------------------------- */
 
 /* Caller workspace of foa_push_blocked for a stream of n rows and capacity

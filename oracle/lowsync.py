@@ -122,8 +122,8 @@ def _sweep(st, x):
         if st.has_u and rho_hat > 0.0:
             r_t = (st.gamma - float(st.w @ st.z)) / rho_hat
         u = st.V[:, iu] - Q @ st.z
-        if st.has_u:
-            u = u - (ut / rho_hat if rho_hat > 0.0 else 0.0) * r_t
+        if st.has_u and rho_hat > 0.0:
+            u = u - ut * (r_t / rho_hat)    # q_hat R_tilde with q_hat = ut / rho_hat
         u = _store(st, u)
         st.V[:, iu] = u
     # 3. the new snapshot, copied into the next column

@@ -63,6 +63,11 @@ Layout make_layout(int64_t n, int n_max, foa_prec prec, int ldg) {
   L.st = take(sizeof(DevState));
   // mode coefficients: FP64 k x r, or the padded FP32 layout of the MFMA path
   L.mcoef = take(std::max((size_t)n_max * n_max * 8, (size_t)modes_kpad(n_max) * modes_rpad(n_max) * 4));
+  // one-reduction form: second partial-sum array (with the scalar rows), the
+  // reduced sums and the prefix sums of the snapshot norms
+  L.ls_part1 = take((size_t)(n_max + LS_NSC) * L.ldg * 8);
+  L.ls_red = take((size_t)(2 * n_max + LS_NSC) * 8);
+  L.ls_xpre = take((size_t)(n_max + 1) * 8);
   L.total = off;
   return L;
 }
@@ -204,6 +209,7 @@ void release_events(foa_ctx_s *c) {
 // Enqueue one push of snapshot x (Algorithm 1: the first-snapshot
 // normalisation for q = 0, else one iteration of its snapshot loop).
 foa_status enqueue_push(foa_ctx_s *c, const void *x, bool x_f64) {
+  if (c->form == 1) return enqueue_ls_push(c, x, x_f64);
   const bool v64 = c->prec == FOA_PREC_F64;
   const int j = c->q_host;
   const int G = pass_grid(c, j, x_f64);
@@ -251,8 +257,13 @@ foa_status enqueue_push(foa_ctx_s *c, const void *x, bool x_f64) {
   return FOA_OK;
 }
 
-// Synchronise and read the device scalar state.
+// Synchronise and read the device scalar state (the one-reduction form first
+// finishes its pending columns).
 foa_status sync_state(foa_ctx_s *c) {
+  if (c->form == 1 && (c->ls_hu || c->ls_hx)) {
+    foa_status r = enqueue_ls_flush(c);
+    if (r != FOA_OK) return r;
+  }
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_err(c, e, "hipStreamSynchronize");
   DevState st;
@@ -296,6 +307,7 @@ foa_status reset_device_state(foa_ctx_s *c) {
   c->q_host = 0;
   c->dev_status = ST_ACTIVE;
   c->pushes = 0;
+  c->ls_hu = c->ls_hx = 0;
   c->mirror_valid = false;
   c->trunc_r = 0;
   c->trunc_m = 0;
@@ -501,8 +513,28 @@ foa_status foa_profile(foa_ctx c, double out[3]) {
 
 foa_status foa_next_column(foa_ctx c, void **d_col) {
   if (!c || !d_col) return FOA_E_ARG;
+  if (c->form == 1) return set_err(c, FOA_E_STATE, "the one-reduction form has no in-place snapshot buffer");
   *d_col = c->w;
   return FOA_OK;
+}
+
+foa_status foa_set_form(foa_ctx c, foa_form form) {
+  if (!c) return FOA_E_ARG;
+  if (form != FOA_FORM_CGS2 && form != FOA_FORM_ONE_REDUCTION) return set_err(c, FOA_E_ARG, "unknown form");
+  if (c->is_view) return set_err(c, FOA_E_STATE, "batch streams use the three-sweep form");
+  if (c->q_host != 0 || c->pushes != 0 || c->ls_hu || c->ls_hx)
+    return set_err(c, FOA_E_STATE, "the form is chosen before the first push (after foa_init or foa_reset)");
+  if (form == FOA_FORM_ONE_REDUCTION && !ls_supported(c->prec == FOA_PREC_F64, c->n_max - 1))
+    return set_err(c, FOA_E_ARG, "the one-reduction form holds at most %d snapshots with this basis precision",
+                   c->prec == FOA_PREC_F64 ? 257 : 513);
+  c->form = form == FOA_FORM_ONE_REDUCTION ? 1 : 0;
+  return FOA_OK;
+}
+
+foa_status foa_flush(foa_ctx c) {
+  if (!c) return FOA_E_ARG;
+  if (c->form != 1 || (!c->ls_hu && !c->ls_hx)) return FOA_OK;
+  return enqueue_ls_flush(c);
 }
 
 foa_status foa_profile_modes(foa_ctx c, double out[3]) {

@@ -141,6 +141,7 @@ namespace {
 // workspace (the caller's, or the static one).
 foa_status push_blocked_impl(foa_ctx_s *c, const void *d_X, int64_t ld, int32_t p, foa_dtype x_dtype,
                              char *bws, const BlockLayout &L) {
+  if (c->form == 1) return set_err(c, FOA_E_STATE, "the blocked form is not available on a one-reduction stream");
   foa_status r = sync_state(c);
   if (r != FOA_OK) return r;
   if (c->dev_status != ST_ACTIVE) return set_err(c, FOA_E_STATE, "stream is not active");

@@ -18,7 +18,9 @@ struct Layout {
   int64_t P = 0, n_pad = 0;
   int ldg = 0, ldH = 0, ldB = 0;
   size_t W = 0, w = 0, part = 0, partn = 0, H = 0, beta = 0, sigma = 0, bvec = 0, h = 0, s = 0;
-  size_t coefA = 0, coefB = 0, coefC = 0, st = 0, mcoef = 0, total = 0;
+  size_t coefA = 0, coefB = 0, coefC = 0, st = 0, mcoef = 0;
+  size_t ls_part1 = 0, ls_red = 0, ls_xpre = 0;  // one-reduction form
+  size_t total = 0;
 };
 
 // Eigen-decomposition of the projected matrix and everything derived from it
@@ -74,6 +76,12 @@ struct foa_ctx_s {
   std::vector<double> Ur;     // m x r, column-major
   std::vector<double> hsv;    // singular values of beta_m
   std::string err;
+  // one-reduction form (foa_set_form): 0 = three-sweep CGS2, 1 = one reduction;
+  // the host's model of the pending columns (exact unless the device found a
+  // dependent or non-finite snapshot, which the next synchronising call reads)
+  int form = 0;
+  int ls_hu = 0, ls_hx = 0;
+  int ls_occ[2][2][3][5] = {};  // resident sweep workgroups per CU [v64][x64][nw][log2 qw]
   // row-pass timing (foa_profile)
   bool profile = false;
   // kind 0: row pass (work = algorithmic bytes); kind 1: mode GEMM (work = flops)
@@ -94,6 +102,9 @@ foa_status sync_state(foa_ctx_s *c);
 foa_status refresh_mirror(foa_ctx_s *c);
 foa_status reset_device_state(foa_ctx_s *c);
 foa_status enqueue_push(foa_ctx_s *c, const void *x, bool x_f64);
+// one-reduction form (foa_lowsync.cpp)
+foa_status enqueue_ls_push(foa_ctx_s *c, const void *x, bool x_f64);
+foa_status enqueue_ls_flush(foa_ctx_s *c);
 int projected_order(const foa_ctx_s *c);
 int pass_grid(foa_ctx_s *c, int j, bool x_f64);
 foa_status collect_profile(foa_ctx_s *c);

@@ -641,6 +641,14 @@ __device__ inline void init_state_body(const SmallArgs &a, double tol) {
     st->tol = tol;
     st->hlast = 0.0;
     st->pers = 0;
+    st->ls_u = 0;
+    st->ls_x = 0;
+    st->ls_nx = 0;
+    st->ls_alpha = 0.0;
+    st->ls_gamma = 0.0;
+    st->ls_rhohat = 0.0;
+    st->ls_rt = 0.0;
+    st->ls_cq = 0.0;
   }
 }
 

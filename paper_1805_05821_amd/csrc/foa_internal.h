@@ -36,6 +36,16 @@ struct DevState {
   int seg0;       // batched form: first workgroup of this step's passes on the stream
   int pers;       // batched form: this step is run by the persistent step kernel
   int pad1;
+  // one-reduction form (foa_lowsync.hip): pending columns after the final q
+  int ls_u;       // column q is under its second projection (w in h, coefW in coefA)
+  int ls_x;       // column q + ls_u holds a snapshot copy (z in s, coefZ in coefB)
+  int ls_nx;      // snapshots accepted (final + pending)
+  int ls_pad;
+  double ls_alpha;  // ||u||^2 of the pending column
+  double ls_gamma;  // u^T x of the pending column and snapshot
+  double ls_rhohat; // estimated norm sqrt(alpha - ||w||^2) of the pending column
+  double ls_rt;     // first-pass coefficient of the snapshot on the pending column
+  double ls_cq;     // ls_rt / ls_rhohat (0 if the estimate is 0)
 };
 
 // Pass modes of the fused row kernel.
@@ -174,6 +184,40 @@ struct BlockArgs {
   int Gz;           // workgroups of the block Gram passes
 };
 
+// ---- one-reduction form (foa_lowsync.hip) -----------------------------------
+// One sweep over the rows per push: second projection of the pending column
+// (index q when ls_u), first projection of the pending snapshot copy (index
+// q + ls_u when ls_x), copy of the new snapshot, and the column sums of the
+// one reduction.  Partial sums per workgroup slot: part0[c * ldg + slot]
+// (stored column c against the formed column), part1[c * ldg + slot] (against
+// the new snapshot), and part1[(n_max + k) * ldg + slot] for the six scalar
+// sums LS_S*.
+enum { LS_UU = 0, LS_UF = 1, LS_UX = 2, LS_FF = 3, LS_FX = 4, LS_XX = 5, LS_NSC = 6 };
+struct LsArgs {
+  void *W;               // basis storage (panel layout), element type TV
+  const void *x;         // new snapshot (type TX), NULL for a flush sweep
+  const double *coefW;   // sigma o w (second projection of the pending column)
+  const double *coefZ;   // sigma o z (first projection of the pending snapshot)
+  const DevState *st;
+  double *part0, *part1;
+  int64_t n, P;
+  int n_max, ldg;
+  int flush;             // 1: no new snapshot
+};
+struct LsSmall {
+  DevState *st;
+  double *H, *beta, *sigma;
+  double *w, *z;         // pending coefficient vectors (FP64, unscaled)
+  double *coefW, *coefZ; // sigma-scaled copies for the next sweep
+  double *red;           // reduced sums: [0, n_max) part0 columns, [n_max, 2 n_max) part1, then LS_NSC scalars
+  double *xpre;          // prefix sums of ||x_i||^2 of the accepted snapshots
+  const double *part0, *part1;
+  int ldH, ldB, n_max, ldg;
+  int G;                 // partial slots written by the sweep
+  int nt;                // host's expectation of q (upper bound of the device's)
+  int flush;
+};
+
 // ---- launchers (defined in foa_kernels.hip) --------------------------------
 // tv_f64: V stored in FP64; tx_f64: snapshot in FP64.
 // nw: wavefronts per workgroup for an FP32 basis (8 or 16; FP64 uses 16).
@@ -216,6 +260,15 @@ hipError_t launch_modes_gemm(bool tv_f64, const void *W, int64_t n, int n_max, i
                              hipStream_t s);
 
 int pick_qw(int j, int cols_per_qw);
+
+// one-reduction form
+int ls_nw(bool tv_f64, int q);
+int ls_qw(bool tv_f64, int q);
+bool ls_supported(bool tv_f64, int q);
+int ls_occupancy(bool tv_f64, bool tx_f64, int q);
+hipError_t launch_ls_pass(bool tv_f64, bool tx_f64, int q, int grid, const LsArgs &a, hipStream_t s);
+hipError_t launch_ls_reduce(const LsSmall &a, hipStream_t s);
+hipError_t launch_ls_finalize(const LsSmall &a, hipStream_t s);
 
 // batched form (one call per kernel of a step; all captured in one graph)
 hipError_t launch_batch_plan(const BatchArgs &b, hipStream_t s);

@@ -1,0 +1,599 @@
+// One-reduction form of the FOA step (gfx950).
+//
+// The modified FOA factorises the snapshots as X = V beta (the QR view of
+// Section 3.1) with H_bar following from beta through eq. betacolumnupdate.
+// Algorithm 1 orthogonalises with classical Gram-Schmidt applied twice, so a
+// push needs three sweeps over the basis and three global reductions.  Here
+// the snapshots themselves are orthogonalised and the two projections of
+// consecutive snapshots share a sweep (delayed reorthogonalisation, Bielich et
+// al., Parallel Computing 2022): the sweep of a push
+//   * finishes the pending column: u - Q w, with w = Q^T u from the previous
+//     reduction (the second projection);
+//   * gives the pending snapshot copy its first projection: x - Q z - q_hat
+//     R_tilde, with z = Q^T x and the coefficient on the column just finished,
+//     R_tilde = (u^T x - w^T z) / rho_hat, from the previous reduction
+//     (rho_hat = sqrt(||u||^2 - ||w||^2), the estimated norm);
+//   * copies the new snapshot into the next basis column;
+// and forms every column sum the next step needs in the same pass.  One
+// fixed-order reduction then gives the exact norm of the finished column, w
+// of the new pending column, and z of the new snapshot.  Per push: one sweep
+// reading the final columns once, two pending columns read and written, the
+// new snapshot read and stored -- about a third of the three-sweep form's
+// traffic.  Columns become final two pushes after their snapshot; a flush
+// (sweeps without a snapshot) finishes the pending ones.
+//
+// Storage: column c holds the unnormalised vector, v_c = sigma_c column_c
+// with sigma_c = 1 / ||column_c|| (the exact norm of the stored values), as in
+// the three-sweep form.  Every dot product, norm and small-matrix operation is
+// FP64; stored columns are rounded to the basis precision, and every sum uses
+// the rounded values the next sweep will read.
+//
+// Kernels (all on the context stream):
+//   k_ls_pass     : the sweep (panel walk, tile layout and prefetch of the
+//                   three-sweep row pass; two coefficient vectors in phase 1,
+//                   two right-hand sides in phase 2, six scalar sums);
+//   k_ls_reduce   : fixed-order reduction of the workgroup partials;
+//   k_ls_finalize : one workgroup: the finished column's norm, scale and
+//                   breakdown test, H_bar's column from beta, beta's column of
+//                   the new pending column, the next sweep's coefficients.
+#include "foa_device.h"
+
+namespace foa {
+
+// ---------------------------------------------------------------------------
+// Sweep body.  One workgroup walks panels blockIdx.x, + gridDim.x, ...
+// Tile: the q final columns of a panel (lane layout of row_pass_body).  The
+// pending columns and the snapshot are read per update row.
+// ---------------------------------------------------------------------------
+template <typename TV, int NW, int QW>
+constexpr int ls_lds_doubles() {
+  constexpr int JCAP = QW * NW * Vec<TV>::EPL;
+  return 2 * JCAP + 2 * 2 * NW * PANEL + 2 * PANEL + NW * LS_NSC;
+}
+
+template <typename TV, typename TX, int NW, int QW, bool PREF>
+__device__ __forceinline__ void ls_pass_body(const LsArgs &a, double *lds) {
+#pragma clang fp contract(off)
+  constexpr int EPL = Vec<TV>::EPL;
+  constexpr int LPC = 64 / EPL;
+  constexpr int CPW = EPL;
+  constexpr int JCAP = QW * NW * CPW;
+  constexpr int RPW = PANEL / NW;
+  constexpr int GSTRIDE = NW * CPW;
+
+  double (*s_coef)[JCAP] = reinterpret_cast<double (*)[JCAP]>(lds);
+  double (*s_red)[2][NW][PANEL] = reinterpret_cast<double (*)[2][NW][PANEL]>(lds + 2 * JCAP);
+  double *s_u = lds + 2 * JCAP + 4 * NW * PANEL;
+  double *s_x = s_u + PANEL;
+  double (*s_sc)[LS_NSC] = reinterpret_cast<double (*)[LS_NSC]>(s_x + PANEL);
+
+  const DevState *st = a.st;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int cs = lane / LPC;
+  const int rg = lane % LPC;
+
+  // step state (uniform)
+  const int q = uniform(st->q);
+  const int hu = uniform(st->ls_u);
+  const int hf = uniform(st->ls_x);
+  const int hn = a.flush ? 0 : 1;
+  const int cc = q;            // column under its second projection
+  const int cf = q + hu;       // snapshot copy that gets its first projection
+  const int cn = cf + hf;      // column the new snapshot is copied to
+  const double cq = hu && hf ? uniform(st->ls_cq) : 0.0;
+
+  for (int k = 0; k < 2; ++k)
+    for (int c = tid; c < JCAP; c += NW * 64) s_coef[k][c] = (c < q) ? (k ? a.coefZ[c] : a.coefW[c]) : 0.0;
+  __syncthreads();
+
+  const int cbase = wave * CPW + cs;
+  const unsigned goff0 = (unsigned)((wave * CPW * PANEL + lane * EPL) * sizeof(TV));
+  constexpr unsigned GBYTES = (unsigned)(GSTRIDE * PANEL * sizeof(TV));
+  const unsigned tile_bytes = (unsigned)(q * PANEL * sizeof(TV));
+  const bool uact = lane < RPW;
+  const int urow = wave * RPW + (lane % RPW);
+  const unsigned pan_bytes = (unsigned)((size_t)a.n_max * PANEL * sizeof(TV));
+  // per-row offsets of the pending columns inside a panel (kOOR: absent)
+  const unsigned ocu = (uact && hu) ? (unsigned)((cc * PANEL + urow) * sizeof(TV)) : kOOR;
+  const unsigned ocf = (uact && hf) ? (unsigned)((cf * PANEL + urow) * sizeof(TV)) : kOOR;
+  const unsigned ocn = (uact && hn) ? (unsigned)((cn * PANEL + urow) * sizeof(TV)) : kOOR;
+
+  double acc0[QW], acc1[QW];
+#pragma unroll
+  for (int g = 0; g < QW; ++g) acc0[g] = acc1[g] = 0.0;
+  double sc[LS_NSC];
+#pragma unroll
+  for (int k = 0; k < LS_NSC; ++k) sc[k] = 0.0;
+
+  char *Wb = static_cast<char *>(a.W);
+  const size_t pbytes = (size_t)a.n_max * PANEL * sizeof(TV);
+  TV t[QW][EPL];
+  TV tn[QW][EPL];
+  auto load_tile = [&](int64_t p, TV (&dst)[QW][EPL], unsigned bytes) {
+    const __amdgpu_buffer_rsrc_t rt = make_rsrc(Wb + (size_t)p * pbytes, bytes);
+#pragma unroll
+    for (int g = 0; g < QW; ++g) {
+      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rt, (int)(goff0 + g * GBYTES), 0, 0);
+      unpack16<TV>(v, dst[g]);
+    }
+  };
+
+  const int64_t pstart = blockIdx.x, pend = a.P, pstep = gridDim.x;
+  int64_t p = pstart;
+  if (PREF && p < pend) {
+    load_tile(p, t, tile_bytes);
+#pragma unroll
+    for (int g = 0; g < QW; ++g) {
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(t[g][e]));
+    }
+  }
+  int par = 0;
+  for (; p < pend; p += pstep) {
+    // per-row inputs: pending column, snapshot copy, new snapshot
+    const __amdgpu_buffer_rsrc_t rp = make_rsrc(Wb + (size_t)p * pbytes, pan_bytes);
+    const double yu = buf_load_scalar<TV>(rp, ocu);
+    const double yf = buf_load_scalar<TV>(rp, ocf);
+    double xv;
+    {
+      const int64_t rem = a.n - p * PANEL;
+      const unsigned xb = hn ? (unsigned)((rem >= PANEL ? PANEL : (rem > 0 ? rem : 0)) * sizeof(TX)) : 0u;
+      const __amdgpu_buffer_rsrc_t rx = make_rsrc(static_cast<const TX *>(a.x) + (hn ? p * PANEL : 0), xb);
+      xv = buf_load_scalar<TX>(rx, uact ? (unsigned)(urow * sizeof(TX)) : kOOR);
+    }
+    if (PREF) {
+      const bool more = p + pstep < pend;
+      load_tile(more ? p + pstep : p, tn, more ? tile_bytes : 0u);
+    } else {
+      load_tile(p, t, tile_bytes);
+    }
+
+    // phase 1: row sums of the tile against sigma o w and sigma o z
+    double u[2][EPL];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) u[k][e] = 0.0;
+    }
+#pragma unroll
+    for (int g = 0; g < QW; ++g) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const double cf_ = s_coef[k][cbase + g * GSTRIDE];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) u[k][e] = fma((double)t[g][e], cf_, u[k][e]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if constexpr (LPC <= 16) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) u[k][e] = xor_sum<16>(u[k][e]);
+      }
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) u[k][e] = xor_sum<32>(u[k][e]);
+    }
+    if (cs == 0) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) s_red[par][k][wave][rg * EPL + e] = u[k][e];
+      }
+    }
+    __syncthreads();
+    double sw = 0.0, sz = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < NW; ++w2) {
+      sw += s_red[par][0][w2][urow];
+      sz += s_red[par][1][w2][urow];
+    }
+    // row update: finished column, formed column, snapshot copy (each rounded
+    // to the storage type; the sums below use the rounded values)
+    const TV ut_s = (TV)(yu - sw);
+    const double ut = (double)ut_s;
+    const TV uf_s = (TV)((yf - sz) - ut * cq);
+    const double uf = (double)uf_s;
+    const TV xs_s = (TV)xv;
+    const double xs = (double)xs_s;
+    buf_store_scalar<TV>(ut_s, rp, ocu);
+    buf_store_scalar<TV>(uf_s, rp, ocf);
+    buf_store_scalar<TV>(xs_s, rp, ocn);
+    if (uact) {
+      sc[LS_UU] = fma(ut, ut, sc[LS_UU]);
+      sc[LS_UF] = fma(ut, uf, sc[LS_UF]);
+      sc[LS_UX] = fma(ut, xs, sc[LS_UX]);
+      sc[LS_FF] = fma(uf, uf, sc[LS_FF]);
+      sc[LS_FX] = fma(uf, xs, sc[LS_FX]);
+      sc[LS_XX] = fma(xv, xv, sc[LS_XX]);
+      s_u[urow] = uf;
+      s_x[urow] = xs;
+    }
+    __syncthreads();
+    // phase 2: column sums of the tile against the formed column and the snapshot
+    double wu[EPL], wx[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      wu[e] = s_u[rg * EPL + e];
+      wx[e] = s_x[rg * EPL + e];
+    }
+    if constexpr (sizeof(TV) == 4) {
+#pragma unroll
+      for (int g = 0; g < QW; ++g) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(t[g][e]));
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < QW; ++g) {
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const double tv = (double)t[g][e];
+        acc0[g] = fma(tv, wu[e], acc0[g]);
+        acc1[g] = fma(tv, wx[e], acc1[g]);
+      }
+    }
+    if (PREF) {
+#pragma unroll
+      for (int g = 0; g < QW; ++g) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(tn[g][e]));
+      }
+#pragma unroll
+      for (int g = 0; g < QW; ++g) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) t[g][e] = tn[g][e];
+      }
+    }
+    par ^= 1;
+  }
+
+  const int slot = blockIdx.x;
+#pragma unroll
+  for (int g = 0; g < QW; ++g) {
+    double v0 = acc0[g], v1 = acc1[g];
+#pragma unroll
+    for (int m = 1; m < LPC; m <<= 1) {
+      v0 += xor_shfl(v0, m);
+      v1 += xor_shfl(v1, m);
+    }
+    const int c = cbase + g * GSTRIDE;
+    if (rg == 0 && c < q) {
+      a.part0[(size_t)c * a.ldg + slot] = v0;
+      a.part1[(size_t)c * a.ldg + slot] = v1;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < LS_NSC; ++k) {
+    double v = sc[k];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v += xor_shfl(v, m);
+    if (lane == 0) s_sc[wave][k] = v;
+  }
+  __syncthreads();
+  if (tid < LS_NSC) {
+    double v = 0.0;
+    for (int w2 = 0; w2 < NW; ++w2) v += s_sc[w2][tid];
+    a.part1[(size_t)(a.n_max + tid) * a.ldg + slot] = v;
+  }
+}
+
+// Sweeps run while the stream is active; flush sweeps also after a
+// non-finite snapshot stopped it (the snapshots before it are completed).
+__device__ __forceinline__ bool ls_runs(const DevState *st, int flush) {
+  const int s = st->status;
+  return s == ST_ACTIVE || (flush && s == ST_NONFINITE);
+}
+
+// Register budget as waves per SIMD: tiles of up to 4 groups fit 128 VGPRs,
+// 8 groups 168 and 16 groups 256 (two right-hand sides of FP64 accumulators
+// plus the current and the prefetched tile).
+template <typename TV, int NW, int QW>
+constexpr int ls_waves() {
+  return QW <= 4 ? 4 : (QW == 8 ? 3 : 2);
+}
+
+template <typename TV, typename TX, int NW, int QW, bool PREF>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(ls_waves<TV, NW, QW>()))) void k_ls_pass(
+    LsArgs a) {
+  if (!ls_runs(a.st, a.flush)) return;
+  if (a.flush && !a.st->ls_u && !a.st->ls_x) return;
+  __shared__ double lds[ls_lds_doubles<TV, NW, QW>()];
+  ls_pass_body<TV, TX, NW, QW, PREF>(a, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Reduction: one wavefront per value (part0 columns, part1 columns, scalars),
+// lane-strided sums over the slots, then a butterfly: a fixed association.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ls_reduce(LsSmall a) {
+  if (!ls_runs(a.st, a.flush)) return;
+  if (a.flush && !a.st->ls_u && !a.st->ls_x) return;
+  const int lane = threadIdx.x & 63;
+  const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int q = a.st->q;
+  const double *src;
+  int out;
+  if (v < a.nt) {
+    if (v >= q) return;
+    src = a.part0 + (size_t)v * a.ldg;
+    out = v;
+  } else if (v < 2 * a.nt) {
+    if (v - a.nt >= q) return;
+    src = a.part1 + (size_t)(v - a.nt) * a.ldg;
+    out = a.n_max + (v - a.nt);
+  } else if (v < 2 * a.nt + LS_NSC) {
+    src = a.part1 + (size_t)(a.n_max + v - 2 * a.nt) * a.ldg;
+    out = 2 * a.n_max + (v - 2 * a.nt);
+  } else {
+    return;
+  }
+  double t = 0.0;
+  for (int g = lane; g < a.G; g += 64) t += src[g];
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) t += xor_shfl(t, m);
+  if (lane == 0) a.red[out] = t;
+}
+
+// ---------------------------------------------------------------------------
+// Finalize (one workgroup of 512 threads, q <= 511 after the push).
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ inline double ls_block_sum(double v, double *sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// H_bar's column c-1 once beta's column c is final (eq. betacolumnupdate
+// solved for it): h = (beta_{0:c,c} - [H_bar_{0:c,0:c-1} beta_{0:c-1,c-1}; 0])
+// / beta_{c-1,c-1}; thread i takes row i.
+template <int NT>
+__device__ inline void ls_hbar_column(const LsSmall &a, int c) {
+  const double *bprev = a.beta + (size_t)(c - 1) * a.ldB;
+  const double *bcol = a.beta + (size_t)c * a.ldB;
+  const double d = bprev[c - 1];
+  for (int i = threadIdx.x; i <= c; i += NT) {
+    double b = 0.0;
+    if (i < c) {
+      for (int l = i > 0 ? i - 1 : 0; l < c - 1; ++l) b = fma(a.H[(size_t)l * a.ldH + i], bprev[l], b);
+    }
+    a.H[(size_t)(c - 1) * a.ldH + i] = (bcol[i] - b) / d;
+  }
+}
+
+template <int NT>
+__device__ inline void ls_finalize_body(const LsSmall &a) {
+  __shared__ double sh[NT];
+  __shared__ int s_flag;
+  DevState *st = a.st;
+  const int tid = threadIdx.x;
+  const bool push = !a.flush;
+  if (!ls_runs(st, a.flush) || (a.flush && !st->ls_u && !st->ls_x)) {
+    __syncthreads();
+    if (tid == 0 && push) st->pushes += 1;
+    return;
+  }
+  const int q0 = st->q;
+  const int hu = st->ls_u, hf = st->ls_x;
+  int hn = push ? 1 : 0;
+  const double *red0 = a.red, *red1 = a.red + a.n_max, *sc = a.red + 2 * a.n_max;
+  const double rhohat0 = st->ls_rhohat, rt0 = st->ls_rt;
+  // the new snapshot: non-finite -> dropped, the stream stops; zero first -> q = 0
+  if (hn) {
+    const double xn2 = sc[LS_XX];
+    if (!isfinite(xn2)) {
+      hn = 0;
+      __syncthreads();
+      if (tid == 0) st->status = ST_NONFINITE;
+    } else if (q0 == 0 && !hu && !hf && xn2 == 0.0) {
+      __syncthreads();
+      if (tid == 0) {
+        st->status = ST_ZERO;
+        st->pushes += 1;
+      }
+      return;
+    }
+  }
+  // 1. the pending column is finished: exact norm, breakdown test, H_bar
+  int q = q0;
+  double rho = 0.0;
+  if (hu) {
+    rho = sqrt(sc[LS_UU]);
+    const double xf = a.xpre[q0];
+    if (tid == 0) s_flag = !(rho > st->tol * sqrt(xf)) ? (isfinite(rho) ? 1 : 2) : 0;
+    __syncthreads();
+    const int flag = s_flag;
+    if (flag) {
+      // dependent (or non-finite) column: the stream keeps the q0 columns before it
+      if (flag == 1) {
+        if (tid == 0) a.beta[(size_t)q0 * a.ldB + q0] = 0.0;
+        __syncthreads();
+        if (q0 > 0) ls_hbar_column<NT>(a, q0);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        st->status = flag == 1 ? ST_INVARIANT : ST_NONFINITE;
+        st->ls_u = 0;
+        st->ls_x = 0;
+        if (push) st->pushes += 1;
+      }
+      return;
+    }
+    if (tid == 0) {
+      a.beta[(size_t)q0 * a.ldB + q0] = rho;
+      a.sigma[q0] = 1.0 / rho;
+    }
+    __syncthreads();
+    if (q0 > 0) ls_hbar_column<NT>(a, q0);
+    q = q0 + 1;
+  }
+  __syncthreads();
+  // 2. the snapshot copy became the pending column: its beta column is the
+  // first projection plus the second (w), both on the final columns
+  double alpha = 0.0, wn2 = 0.0;
+  if (hf) {
+    const int c = q;  // 0-based index of the new pending column
+    const double sk = hu ? a.sigma[q0] : 0.0;
+    for (int i = tid; i < c; i += NT) {
+      double wi, pi;
+      if (i < q0) {
+        wi = red0[i] * a.sigma[i];
+        pi = a.z[i];
+      } else {  // i == q0: the column finished in this sweep
+        wi = sc[LS_UF] * sk;
+        pi = rhohat0 > 0.0 ? (rho / rhohat0) * rt0 : 0.0;
+      }
+      a.beta[(size_t)c * a.ldB + i] = pi + wi;
+      a.w[i] = wi;
+      a.coefW[i] = a.sigma[i] * wi;
+    }
+    alpha = sc[LS_FF];
+  }
+  __syncthreads();
+  // 3. the new snapshot: first-projection coefficients on the final columns
+  if (hn) {
+    const double sk = hu ? a.sigma[q0] : 0.0;
+    for (int i = tid; i < q; i += NT) {
+      const double zi = i < q0 ? red1[i] * a.sigma[i] : sc[LS_UX] * sk;
+      a.z[i] = zi;
+      a.coefZ[i] = a.sigma[i] * zi;
+    }
+  }
+  __syncthreads();
+  // 4. scalars of the next sweep
+  const int nu = hf ? 1 : 0;
+  const int nx = hn ? 1 : 0;
+  double wz = 0.0;
+  if (nu) {
+    double t = 0.0, t2 = 0.0;
+    for (int i = tid; i < q; i += NT) {
+      t = fma(a.w[i], a.w[i], t);
+      if (nx) t2 = fma(a.w[i], a.z[i], t2);
+    }
+    wn2 = ls_block_sum<NT>(t, sh);
+    wz = ls_block_sum<NT>(t2, sh);
+  }
+  if (tid == 0) {
+    st->q = q;
+    st->ls_u = nu;
+    st->ls_x = nx;
+    if (nu) st->ls_alpha = alpha;
+    if (nx) {
+      const double xn2 = sc[LS_XX];
+      const int k = st->ls_nx;
+      a.xpre[k] = (k > 0 ? a.xpre[k - 1] : 0.0) + xn2;
+      st->ls_nx = k + 1;
+      st->xfro2 += xn2;
+      st->ls_gamma = nu ? sc[LS_FX] : 0.0;
+    }
+    double rh = 0.0, rt = 0.0, cq = 0.0;
+    if (nu) {
+      const double d = alpha - wn2;
+      rh = d > 0.0 ? sqrt(d) : 0.0;
+      if (nx && rh > 0.0) {
+        rt = (st->ls_gamma - wz) / rh;
+        cq = rt / rh;
+      }
+    }
+    st->ls_rhohat = rh;
+    st->ls_rt = rt;
+    st->ls_cq = cq;
+    if (push) st->pushes += 1;
+  }
+}
+
+__global__ __launch_bounds__(512) void k_ls_finalize(LsSmall a) { ls_finalize_body<512>(a); }
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+// Tile shapes: FP32 basis 4 wavefronts up to 128 final columns, then 8
+// wavefronts (8 groups up to 256 columns, 16 groups up to 512); FP64 basis 8
+// wavefronts (up to 16 groups, 256 columns).
+int ls_nw(bool tv_f64, int q) {
+  if (tv_f64) return 8;
+  return q <= 128 ? 4 : 8;
+}
+
+int ls_qw(bool tv_f64, int q) { return pick_qw(q > 0 ? q : 1, ls_nw(tv_f64, q) * (tv_f64 ? 2 : 4)); }
+
+bool ls_supported(bool tv_f64, int q) { return tv_f64 ? q <= 256 : q <= 512; }
+
+template <typename TV, typename TX, int NW>
+static hipError_t launch_ls_q(int qw, int grid, const LsArgs &a, hipStream_t s) {
+  constexpr int NT = NW * 64;
+  switch (qw) {
+    case 1: hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 1, true>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 2, true>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 4, true>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 8, true>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 16:
+      if constexpr (NW == 8) {
+        hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 16, true>), dim3(grid), dim3(NT), 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_pass(bool tv_f64, bool tx_f64, int q, int grid, const LsArgs &a, hipStream_t s) {
+  if (!ls_supported(tv_f64, q)) return hipErrorInvalidValue;
+  const int nw = ls_nw(tv_f64, q);
+  const int qw = ls_qw(tv_f64, q);
+  if (qw * nw * (tv_f64 ? 2 : 4) < q) return hipErrorInvalidValue;
+  if (tv_f64) return tx_f64 ? launch_ls_q<double, double, 8>(qw, grid, a, s) : launch_ls_q<double, float, 8>(qw, grid, a, s);
+  if (nw == 4) return tx_f64 ? launch_ls_q<float, double, 4>(qw, grid, a, s) : launch_ls_q<float, float, 4>(qw, grid, a, s);
+  return tx_f64 ? launch_ls_q<float, double, 8>(qw, grid, a, s) : launch_ls_q<float, float, 8>(qw, grid, a, s);
+}
+
+template <typename TV, typename TX, int NW, int QW>
+static int ls_occ_q() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ls_pass<TV, TX, NW, QW, true>),
+                                                   NW * 64, 0) != hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+template <typename TV, typename TX, int NW>
+static int ls_occ_m(int qw) {
+  switch (qw) {
+    case 1: return ls_occ_q<TV, TX, NW, 1>();
+    case 2: return ls_occ_q<TV, TX, NW, 2>();
+    case 4: return ls_occ_q<TV, TX, NW, 4>();
+    case 8: return ls_occ_q<TV, TX, NW, 8>();
+    default:
+      if constexpr (NW == 8) return ls_occ_q<TV, TX, NW, 16>();
+      return 1;
+  }
+}
+
+int ls_occupancy(bool tv_f64, bool tx_f64, int q) {
+  const int nw = ls_nw(tv_f64, q), qw = ls_qw(tv_f64, q);
+  if (tv_f64) return tx_f64 ? ls_occ_m<double, double, 8>(qw) : ls_occ_m<double, float, 8>(qw);
+  if (nw == 4) return tx_f64 ? ls_occ_m<float, double, 4>(qw) : ls_occ_m<float, float, 4>(qw);
+  return tx_f64 ? ls_occ_m<float, double, 8>(qw) : ls_occ_m<float, float, 8>(qw);
+}
+
+hipError_t launch_ls_reduce(const LsSmall &a, hipStream_t s) {
+  const int waves = 2 * a.nt + LS_NSC;
+  hipLaunchKernelGGL(k_ls_reduce, dim3((waves + 3) / 4), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_finalize(const LsSmall &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_ls_finalize, dim3(1), dim3(512), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace foa

@@ -30,13 +30,15 @@ FOA_PREC_F32 = 1
 FOA_F32 = 0
 FOA_F64 = 1
 FOA_MAX_CAPACITY = 512
+FOA_FORM_CGS2 = 0
+FOA_FORM_ONE_REDUCTION = 1
 
 EXPORTED = [
     "foa_workspace_bytes", "foa_init", "foa_push_snapshot", "foa_push_block", "foa_sync",
     "foa_get_state", "foa_copy_basis", "foa_copy_basis_rows", "foa_truncate", "foa_modes", "foa_indicators",
     "foa_reset", "foa_destroy", "foa_status_str", "foa_last_error", "foa_set_option", "foa_profile",
     "foa_profile_modes", "foa_next_column", "foa_block_workspace_bytes", "foa_push_blocked",
-    "foa_push_blocked_static",
+    "foa_push_blocked_static", "foa_set_form", "foa_flush",
     "foa_batch_workspace_bytes", "foa_batch_init", "foa_batch_push", "foa_batch_sync",
     "foa_batch_view", "foa_batch_reset", "foa_batch_destroy",
 ]
@@ -85,6 +87,8 @@ def _load():
         "foa_block_workspace_bytes": [ctypes.c_int64, ctypes.c_int32, ctypes.c_int, P],
         "foa_push_blocked": [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, P, ctypes.c_size_t],
         "foa_push_blocked_static": [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int],
+        "foa_set_form": [P, c.c_int],
+        "foa_flush": [P],
         "foa_batch_workspace_bytes": [i32, P, P, c.c_int, c.POINTER(sz)],
         "foa_batch_init": [c.POINTER(P), i32, P, P, c.c_int, P, sz, P, f64, c.c_char_p],
         "foa_batch_push": [P, P, c.c_int],
@@ -266,6 +270,14 @@ def foa_block_workspace_bytes(n, n_max, prec):
 def foa_push_blocked(ctx, X, ld, p, x_dtype, bws, bws_bytes):
     return _check(lib.foa_push_blocked(ctx, _addr(X), int(ld), int(p), int(x_dtype), _addr(bws),
                                        int(bws_bytes)), ctx)
+
+
+def foa_set_form(ctx, form):
+    return _check(lib.foa_set_form(ctx, int(form)), ctx)
+
+
+def foa_flush(ctx):
+    return _check(lib.foa_flush(ctx), ctx)
 
 
 def foa_push_blocked_static(ctx, X, ld, p, x_dtype):

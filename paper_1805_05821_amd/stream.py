@@ -8,7 +8,8 @@ from . import foa as F
 
 
 class FOAStream:
-    def __init__(self, n, n_max, prec="f64", device="cuda", stream=None, breakdown_tol=-1.0, ws_fill=None):
+    def __init__(self, n, n_max, prec="f64", device="cuda", stream=None, breakdown_tol=-1.0, ws_fill=None,
+                 form="cgs2"):
         import torch
 
         self.n = int(n)
@@ -20,6 +21,8 @@ class FOAStream:
             self.ws.fill_(int(ws_fill))
         self.stream = stream
         self.ctx = F.foa_init(self.n, self.n_max, self.prec, self.ws, nbytes, stream, breakdown_tol)
+        if form != "cgs2":
+            F.foa_set_form(self.ctx, F.FOA_FORM_ONE_REDUCTION if form == "one_reduction" else form)
 
     # pushes ---------------------------------------------------------------
     def push(self, x):
@@ -50,6 +53,10 @@ class FOAStream:
     def push_block(self, X):
         dt = F.FOA_F64 if str(X.dtype) == "torch.float64" else F.FOA_F32
         return F.foa_push_block(self.ctx, X, X.stride(0), X.shape[0], dt)
+
+    def flush(self):
+        """One-reduction form: finish the pending columns (stream-ordered)."""
+        return F.foa_flush(self.ctx)
 
     # queries --------------------------------------------------------------
     def sync(self):

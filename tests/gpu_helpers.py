@@ -15,7 +15,8 @@ def announce(*parts):
     sys.stderr.flush()
 
 
-def run_gpu(X, prec="f64", tol=-1.0, snap_dtype=None, options=None, n_max=None, block=False, ws_fill=0xFF):
+def run_gpu(X, prec="f64", tol=-1.0, snap_dtype=None, options=None, n_max=None, block=False, ws_fill=0xFF,
+            form="cgs2"):
     """Push the columns of X (n x N NumPy) through the library; returns dict."""
     import torch
 
@@ -25,7 +26,7 @@ def run_gpu(X, prec="f64", tol=-1.0, snap_dtype=None, options=None, n_max=None, 
     dt = snap_dtype or (torch.float64 if X.dtype == np.float64 else torch.float32)
     Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to(device="cuda", dtype=dt)
     # the workspace starts as NaN bytes: nothing may depend on its initial content
-    s = FOAStream(n, n_max or N, prec=prec, breakdown_tol=tol, ws_fill=ws_fill)
+    s = FOAStream(n, n_max or N, prec=prec, breakdown_tol=tol, ws_fill=ws_fill, form=form)
     for k, v in (options or {}).items():
         s.set_option(k, v)
     if block:

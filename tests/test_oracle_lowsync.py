@@ -235,8 +235,7 @@ def _mutant(edit):
 # rounding-size second-pass coefficients (the counterpart of the excluded
 # mutant of the sequential oracle).
 LS_MUTANTS = {
-    "first_projection_skips_last_column": ("u = u - (ut / rho_hat if rho_hat > 0.0 else 0.0) * r_t",
-                                           "u = u"),
+    "first_projection_skips_last_column": ("u = u - ut * (r_t / rho_hat)", "u = u"),
     "second_projection_sign": ("ut = _store(st, st.V[:, q] - Q @ st.w)", "ut = _store(st, st.V[:, q] + Q @ st.w)"),
     "gamma_without_w_z_term": ("(st.gamma - float(st.w @ st.z)) / rho_hat", "st.gamma / rho_hat"),
     "hbar_divides_by_new_diagonal": ("st.H[:c + 1, c - 1] = col / st.beta[c - 1, c - 1]",
