@@ -38,20 +38,21 @@ def log(*a):
     sys.stderr.flush()
 
 
-def run_form(prec, X, n, N, warmup, steps, options, r_force=0):
+def run_form(prec, X, n, N, warmup, steps, options, r_force=0, form="cgs2"):
     import torch
 
     from paper_1805_05821_amd import foa as F
     from paper_1805_05821_amd.stream import FOAStream
 
-    s = FOAStream(n, N, prec=prec)
+    s = FOAStream(n, N, prec=prec, form=form)
+    tag = prec if form == "cgs2" else f"{prec} {form}"
     for k, v in options.items():
         s.set_option(k, v)
     for w in range(warmup):
         s.reset()
         s.push_all(X)
         st, q = s.sync()
-        log(f"[{prec}] warmup {w + 1}/{warmup}: q={q} status={st}")
+        log(f"[{tag}] warmup {w + 1}/{warmup}: q={q} status={st}")
     F.foa_profile(s.ctx)  # discard
     s.set_option("profile", 1)
     stream = torch.cuda.current_stream()
@@ -63,9 +64,10 @@ def run_form(prec, X, n, N, warmup, steps, options, r_force=0):
     for k in range(steps):
         s.reset()
         s.push_all(X)
+        s.flush()  # one-reduction form: finish the pending columns inside the step
         if k + 1 < steps:
             st, q = s.sync()
-            log(f"[{prec}] step {k + 1}/{steps}: q={q}")
+            log(f"[{tag}] step {k + 1}/{steps}: q={q}")
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -77,7 +79,7 @@ def run_form(prec, X, n, N, warmup, steps, options, r_force=0):
     # truncated DMD of the last run: the storage precision's rank rule, or r_force
     r_tr, _ = s.truncate(r_force=r_force)
     lam_tr, ind_tr = s.indicators()
-    log(f"[{prec}] {steps} steps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), q={q}, "
+    log(f"[{tag}] {steps} steps: {ms:.1f} ms (wall {wall * 1e3:.1f} ms), q={q}, "
         f"row passes {launches} launches {kms:.1f} ms {kbytes / kms / 1e6:.1f} GB/s, truncated rank {r_tr}")
     res = dict(ms_per_step=ms / steps, wall_s=wall, q=q, status=st, H=H, beta=B, m=m,
                pass_launches=launches, pass_ms=kms, pass_bytes=kbytes, r_trunc=r_tr, lam_trunc=lam_tr)
@@ -448,6 +450,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-blocked", action="store_true", help="skip the blocked form")
+    ap.add_argument("--no-one-reduction", action="store_true", help="skip the one-reduction form")
+    ap.add_argument("--only-one-reduction", action="store_true",
+                    help="time only the one-reduction form (profiling runs)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the n = 1e8 run and its mode reconstruction")
     ap.add_argument("--cpu-rows", type=int, default=1 << 20)
@@ -456,6 +461,7 @@ def main():
                     help="only time the CPU oracle at full size on the workloads that fit host memory")
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--prefetch", type=int, default=-1)
+    ap.add_argument("--ls-nw", type=int, default=0, help="one-reduction sweep: wavefronts above 128 columns")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -502,6 +508,17 @@ def main():
     options = {"grid": args.grid}
     if args.prefetch >= 0:
         options["prefetch"] = args.prefetch
+    if args.ls_nw:
+        options["ls_nw"] = args.ls_nw
+    if args.only_one_reduction:
+        r1 = run_form("f32", X, n, N, args.warmup, args.steps, options, form="one_reduction")
+        gb1 = r1["pass_bytes"] / (r1["pass_ms"] / 1e3) / 1e9
+        print(json.dumps({"form": "one_reduction", "value": N / (r1["ms_per_step"] / 1e3),
+                          "ms_per_step": r1["ms_per_step"], "sweep_gbs": gb1,
+                          "sweep_avg_launch_ms": r1["pass_ms"] / max(r1["pass_launches"], 1),
+                          "sweep_alg_bytes_per_launch": r1["pass_bytes"] / max(r1["pass_launches"], 1)}),
+              flush=True)
+        return
     r32 = run_form("f32", X, n, N, args.warmup, args.steps, options)
     r64 = None if args.no_f64 else run_form("f64", X, n, N, args.warmup, args.steps, options,
                                             r_force=r32["r_trunc"])
@@ -558,6 +575,30 @@ def main():
         out["error_f32_vs_f64"] = {"rel_H_2norm": eH, "kappa2": kap, "bound_10_eps32_kappa": 10 * EPS32 * kap,
                                    "within_bound": bool(eH <= 10 * EPS32 * kap)}
         out["error_f32_vs_f64_truncated"] = truncated_gate(r32, r64)
+    if not args.no_one_reduction:
+        try:
+            r1 = run_form("f32", X, n, N, args.warmup, args.steps, options, form="one_reduction")
+            gb1 = r1["pass_bytes"] / (r1["pass_ms"] / 1e3) / 1e9
+            leg = {"form": "fp32-basis, one reduction per push (delayed reorthogonalisation, QR view)",
+                   "value": round(N / (r1["ms_per_step"] / 1e3), 3), "unit": "snapshots/s",
+                   "ms_per_step": round(r1["ms_per_step"], 3), "q": r1["q"],
+                   "sweep_launches": r1["pass_launches"],
+                   "sweep_alg_bytes_per_step": r1["pass_bytes"] / args.steps,
+                   "sweep_achieved_gbs": round(gb1, 1), "sweep_frac_of_peak": round(gb1 / HBM_PEAK_GBS, 4),
+                   "sweep_avg_launch_ms": r1["pass_ms"] / max(r1["pass_launches"], 1),
+                   "speedup_vs_cgs2_f32": round(r32["ms_per_step"] / r1["ms_per_step"], 3)}
+            if r64 is not None:
+                m = min(r1["m"], r64["m"])
+                H1, H64 = r1["H"][:m, :m], r64["H"][:m, :m]
+                kap = out["error_f32_vs_f64"]["kappa2"]
+                eH = float(np.linalg.norm(H1 - H64, 2) / np.linalg.norm(H64, 2))
+                leg["error_vs_f64_cgs2"] = {"rel_H_2norm": eH, "bound_10_eps32_kappa": 10 * EPS32 * kap,
+                                            "within_bound": bool(eH <= 10 * EPS32 * kap)}
+                leg["error_vs_f64_cgs2_truncated"] = truncated_gate(r1, r64)
+                leg["speedup_vs_cgs2_f64"] = round(r64["ms_per_step"] / r1["ms_per_step"], 3)
+            out["one_reduction_form"] = leg
+        except Exception as e:  # reported, never silently dropped
+            out["one_reduction_form"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_blocked:
         try:
             rb = run_blocked("f32", X, n, N, args.warmup, args.steps)

@@ -410,6 +410,12 @@ foa_status foa_set_option(foa_ctx c, const char *key, int64_t value) {
     std::memset(c->occ_cache, 0, sizeof c->occ_cache);
     return FOA_OK;
   }
+  if (!std::strcmp(key, "ls_nw")) {
+    if (value != 0 && value != 8 && value != 16) return set_err(c, FOA_E_ARG, "ls_nw must be 0, 8 or 16");
+    c->ls_nw_opt = (int)value;
+    std::memset(c->ls_occ, 0, sizeof c->ls_occ);
+    return FOA_OK;
+  }
   if (!std::strcmp(key, "profile")) {
     c->profile = value != 0;
     return FOA_OK;

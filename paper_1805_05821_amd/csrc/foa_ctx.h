@@ -82,6 +82,7 @@ struct foa_ctx_s {
   int form = 0;
   int ls_hu = 0, ls_hx = 0;
   int ls_occ[2][2][3][5] = {};  // resident sweep workgroups per CU [v64][x64][nw][log2 qw]
+  int ls_nw_opt = 0;            // option "ls_nw": 0 automatic, 16 = 16-wavefront sweeps above 128 columns
   // row-pass timing (foa_profile)
   bool profile = false;
   // kind 0: row pass (work = algorithmic bytes); kind 1: mode GEMM (work = flops)

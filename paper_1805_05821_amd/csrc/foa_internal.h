@@ -210,6 +210,7 @@ struct LsSmall {
   double *w, *z;         // pending coefficient vectors (FP64, unscaled)
   double *coefW, *coefZ; // sigma-scaled copies for the next sweep
   double *red;           // reduced sums: [0, n_max) part0 columns, [n_max, 2 n_max) part1, then LS_NSC scalars
+  double *bvec;          // H_bar product of the column the finalize finishes
   double *xpre;          // prefix sums of ||x_i||^2 of the accepted snapshots
   const double *part0, *part1;
   int ldH, ldB, n_max, ldg;
@@ -262,11 +263,12 @@ hipError_t launch_modes_gemm(bool tv_f64, const void *W, int64_t n, int n_max, i
 int pick_qw(int j, int cols_per_qw);
 
 // one-reduction form
-int ls_nw(bool tv_f64, int q);
-int ls_qw(bool tv_f64, int q);
+// wavefronts per sweep workgroup (nw_opt 16: sixteen above 128 columns, FP32 basis)
+int ls_nw(bool tv_f64, int q, int nw_opt);
+int ls_qw(bool tv_f64, int q, int nw_opt);
 bool ls_supported(bool tv_f64, int q);
-int ls_occupancy(bool tv_f64, bool tx_f64, int q);
-hipError_t launch_ls_pass(bool tv_f64, bool tx_f64, int q, int grid, const LsArgs &a, hipStream_t s);
+int ls_occupancy(bool tv_f64, bool tx_f64, int q, int nw_opt);
+hipError_t launch_ls_pass(bool tv_f64, bool tx_f64, int q, int nw_opt, int grid, const LsArgs &a, hipStream_t s);
 hipError_t launch_ls_reduce(const LsSmall &a, hipStream_t s);
 hipError_t launch_ls_finalize(const LsSmall &a, hipStream_t s);
 

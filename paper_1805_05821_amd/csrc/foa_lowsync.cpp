@@ -34,6 +34,7 @@ LsSmall ls_small(foa_ctx_s *c, int G, bool flush) {
   a.coefW = c->sa.coefA;
   a.coefZ = c->sa.coefB;
   a.red = reinterpret_cast<double *>(b + c->L.ls_red);
+  a.bvec = c->sa.bvec;
   a.xpre = reinterpret_cast<double *>(b + c->L.ls_xpre);
   a.part0 = c->part;
   a.part1 = reinterpret_cast<double *>(b + c->L.ls_part1);
@@ -54,12 +55,12 @@ int ls_grid(foa_ctx_s *c, int q, bool x64) {
   int g = c->grid_opt;
   if (g <= 0) {
     const bool v64 = c->prec == FOA_PREC_F64;
-    const int nw = ls_nw(v64, q), qw = ls_qw(v64, q);
+    const int nw = ls_nw(v64, q, c->ls_nw_opt), qw = ls_qw(v64, q, c->ls_nw_opt);
     int qi = 0;
     while ((1 << qi) < qw) ++qi;
     const int ni = nw == 4 ? 0 : (nw == 8 ? 1 : 2);
     int &occ = c->ls_occ[v64 ? 1 : 0][x64 ? 1 : 0][ni][qi];
-    if (occ <= 0) occ = ls_occupancy(v64, x64, q);
+    if (occ <= 0) occ = ls_occupancy(v64, x64, q, c->ls_nw_opt);
     g = std::max(c->grid_auto, occ * c->cus);
   }
   g = std::min<int64_t>({(int64_t)g, (int64_t)c->L.ldg, c->L.P});
@@ -99,7 +100,7 @@ foa_status enqueue_ls_sweep(foa_ctx_s *c, const void *x, bool x64) {
     e1 = take_event(c);
     if (e0 && e1) (void)hipEventRecord(e0, s);
   }
-  hipError_t e = launch_ls_pass(v64, x64, q, G, a, s);
+  hipError_t e = launch_ls_pass(v64, x64, q, c->ls_nw_opt, G, a, s);
   if (c->profile && e0 && e1) {
     (void)hipEventRecord(e1, s);
     c->ev_pending.push_back({e0, e1, bytes, 0});

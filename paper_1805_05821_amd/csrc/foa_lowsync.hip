@@ -132,7 +132,8 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, double *lds) {
   }
   int par = 0;
   for (; p < pend; p += pstep) {
-    // per-row inputs: pending column, snapshot copy, new snapshot
+    // per-row inputs: pending column, snapshot copy, new snapshot (loaded at
+    // the start of their own panel: prefetching them with the tile was slower)
     const __amdgpu_buffer_rsrc_t rp = make_rsrc(Wb + (size_t)p * pbytes, pan_bytes);
     const double yu = buf_load_scalar<TV>(rp, ocu);
     const double yf = buf_load_scalar<TV>(rp, ocf);
@@ -291,7 +292,7 @@ __device__ __forceinline__ bool ls_runs(const DevState *st, int flush) {
 // plus the current and the prefetched tile).
 template <typename TV, int NW, int QW>
 constexpr int ls_waves() {
-  return QW <= 4 ? 4 : (QW == 8 ? 3 : 2);
+  return (NW == 16 || QW <= 4) ? 4 : (QW == 8 ? 3 : 2);
 }
 
 template <typename TV, typename TX, int NW, int QW, bool PREF>
@@ -352,21 +353,45 @@ __device__ inline double ls_block_sum(double v, double *sh) {
   return r;
 }
 
-// H_bar's column c-1 once beta's column c is final (eq. betacolumnupdate
-// solved for it): h = (beta_{0:c,c} - [H_bar_{0:c,0:c-1} beta_{0:c-1,c-1}; 0])
-// / beta_{c-1,c-1}; thread i takes row i.
+// The part of H_bar's column c-1 that the earlier columns give, for the
+// column c = q that the coming finalize finishes (eq. betacolumnupdate):
+// b_i = sum_{l = max(0, i-1)}^{c-2} H_bar[i, l] beta[l, c-1], i < c.  64 rows
+// x 4 contiguous l-slices per 256 threads, slices summed in order.
+__global__ __launch_bounds__(256) void k_ls_hprod(LsSmall a) {
+  __shared__ double sh[4][64];
+  const DevState *st = a.st;
+  if (!ls_runs(st, a.flush) || !st->ls_u) return;
+  const int c = st->q;
+  const int r = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + r;
+  double t = 0.0;
+  if (i < c) {
+    const int lo = i > 0 ? i - 1 : 0, len = c - 1 > lo ? c - 1 - lo : 0;
+    const int a0 = lo + (len * sl) / 4, a1 = lo + (len * (sl + 1)) / 4;
+    const double *bprev = a.beta + (size_t)(c - 1) * a.ldB;
+    // four independent chains, so the loads of several columns are in flight
+    double t4[4] = {0.0, 0.0, 0.0, 0.0};
+    int l = a0;
+    for (; l + 4 <= a1; l += 4) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t4[k] = fma(a.H[(size_t)(l + k) * a.ldH + i], bprev[l + k], t4[k]);
+    }
+    for (; l < a1; ++l) t4[0] = fma(a.H[(size_t)l * a.ldH + i], bprev[l], t4[0]);
+    t = (t4[0] + t4[1]) + (t4[2] + t4[3]);
+  }
+  sh[sl][r] = t;
+  __syncthreads();
+  if (sl == 0 && i < c) a.bvec[i] = ((sh[0][r] + sh[1][r]) + sh[2][r]) + sh[3][r];
+}
+
+// H_bar's column c-1 once beta's column c is final: h = (beta_{0:c,c} -
+// [b; 0]) / beta_{c-1,c-1} with b from k_ls_hprod.
 template <int NT>
 __device__ inline void ls_hbar_column(const LsSmall &a, int c) {
-  const double *bprev = a.beta + (size_t)(c - 1) * a.ldB;
   const double *bcol = a.beta + (size_t)c * a.ldB;
-  const double d = bprev[c - 1];
-  for (int i = threadIdx.x; i <= c; i += NT) {
-    double b = 0.0;
-    if (i < c) {
-      for (int l = i > 0 ? i - 1 : 0; l < c - 1; ++l) b = fma(a.H[(size_t)l * a.ldH + i], bprev[l], b);
-    }
-    a.H[(size_t)(c - 1) * a.ldH + i] = (bcol[i] - b) / d;
-  }
+  const double d = a.beta[(size_t)(c - 1) * a.ldB + (c - 1)];
+  for (int i = threadIdx.x; i <= c; i += NT)
+    a.H[(size_t)(c - 1) * a.ldH + i] = (bcol[i] - (i < c ? a.bvec[i] : 0.0)) / d;
 }
 
 template <int NT>
@@ -518,12 +543,15 @@ __global__ __launch_bounds__(512) void k_ls_finalize(LsSmall a) { ls_finalize_bo
 // Tile shapes: FP32 basis 4 wavefronts up to 128 final columns, then 8
 // wavefronts (8 groups up to 256 columns, 16 groups up to 512); FP64 basis 8
 // wavefronts (up to 16 groups, 256 columns).
-int ls_nw(bool tv_f64, int q) {
+int ls_nw(bool tv_f64, int q, int nw_opt) {
   if (tv_f64) return 8;
-  return q <= 128 ? 4 : 8;
+  if (q <= 128) return 4;
+  return (nw_opt == 16 && q <= 256) ? 16 : 8;
 }
 
-int ls_qw(bool tv_f64, int q) { return pick_qw(q > 0 ? q : 1, ls_nw(tv_f64, q) * (tv_f64 ? 2 : 4)); }
+int ls_qw(bool tv_f64, int q, int nw_opt) {
+  return pick_qw(q > 0 ? q : 1, ls_nw(tv_f64, q, nw_opt) * (tv_f64 ? 2 : 4));
+}
 
 bool ls_supported(bool tv_f64, int q) { return tv_f64 ? q <= 256 : q <= 512; }
 
@@ -546,13 +574,15 @@ static hipError_t launch_ls_q(int qw, int grid, const LsArgs &a, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_ls_pass(bool tv_f64, bool tx_f64, int q, int grid, const LsArgs &a, hipStream_t s) {
+hipError_t launch_ls_pass(bool tv_f64, bool tx_f64, int q, int nw_opt, int grid, const LsArgs &a, hipStream_t s) {
   if (!ls_supported(tv_f64, q)) return hipErrorInvalidValue;
-  const int nw = ls_nw(tv_f64, q);
-  const int qw = ls_qw(tv_f64, q);
+  const int nw = ls_nw(tv_f64, q, nw_opt);
+  const int qw = ls_qw(tv_f64, q, nw_opt);
   if (qw * nw * (tv_f64 ? 2 : 4) < q) return hipErrorInvalidValue;
   if (tv_f64) return tx_f64 ? launch_ls_q<double, double, 8>(qw, grid, a, s) : launch_ls_q<double, float, 8>(qw, grid, a, s);
   if (nw == 4) return tx_f64 ? launch_ls_q<float, double, 4>(qw, grid, a, s) : launch_ls_q<float, float, 4>(qw, grid, a, s);
+  if (nw == 16)
+    return tx_f64 ? launch_ls_q<float, double, 16>(qw, grid, a, s) : launch_ls_q<float, float, 16>(qw, grid, a, s);
   return tx_f64 ? launch_ls_q<float, double, 8>(qw, grid, a, s) : launch_ls_q<float, float, 8>(qw, grid, a, s);
 }
 
@@ -578,10 +608,11 @@ static int ls_occ_m(int qw) {
   }
 }
 
-int ls_occupancy(bool tv_f64, bool tx_f64, int q) {
-  const int nw = ls_nw(tv_f64, q), qw = ls_qw(tv_f64, q);
+int ls_occupancy(bool tv_f64, bool tx_f64, int q, int nw_opt) {
+  const int nw = ls_nw(tv_f64, q, nw_opt), qw = ls_qw(tv_f64, q, nw_opt);
   if (tv_f64) return tx_f64 ? ls_occ_m<double, double, 8>(qw) : ls_occ_m<double, float, 8>(qw);
   if (nw == 4) return tx_f64 ? ls_occ_m<float, double, 4>(qw) : ls_occ_m<float, float, 4>(qw);
+  if (nw == 16) return tx_f64 ? ls_occ_m<float, double, 16>(qw) : ls_occ_m<float, float, 16>(qw);
   return tx_f64 ? ls_occ_m<float, double, 8>(qw) : ls_occ_m<float, float, 8>(qw);
 }
 
@@ -592,6 +623,13 @@ hipError_t launch_ls_reduce(const LsSmall &a, hipStream_t s) {
 }
 
 hipError_t launch_ls_finalize(const LsSmall &a, hipStream_t s) {
+  // the H_bar product for the column the finalize finishes (1 <= q <= nt;
+  // for q = 1 it writes the empty product 0)
+  if (a.nt >= 1) {
+    hipLaunchKernelGGL(k_ls_hprod, dim3((a.nt + 63) / 64), dim3(256), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_ls_finalize, dim3(1), dim3(512), 0, s, a);
   return hipGetLastError();
 }
