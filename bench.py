@@ -89,6 +89,44 @@ def run_form(prec, X, n, N, warmup, steps, options, r_force=0, form="cgs2"):
     return res
 
 
+def run_indicator_log(X, n, N, every):
+    """Error indicators along the stream (Section 3.2.3; the stopping criterion
+    of Algorithm 3 is the caller's): one untimed FP32-basis run of the
+    workload.  Per snapshot j, the untruncated DMD of the first j snapshots
+    has every indicator |h_{j,j-1}| |e^T z_i| <= |h_{j,j-1}| (unit z_i), read
+    from H_bar after the run.  Every `every` snapshots (and at the end) the
+    run stops for the truncated DMD at the FP32 rank rule: rank, largest and
+    median indicator of its eigenpairs (host SVD and eigensolve; untimed)."""
+    import numpy as np
+
+    from paper_1805_05821_amd.stream import FOAStream
+
+    s = FOAStream(n, N, prec="f32")
+    entries = []
+    t0 = time.perf_counter()
+    host_s = 0.0
+    for k in range(N):
+        s.push(X[k])
+        if (k + 1) % every == 0 or k == N - 1:
+            t1 = time.perf_counter()
+            r, _ = s.truncate()
+            lam, ind = s.indicators()
+            host_s += time.perf_counter() - t1
+            entries.append({"snapshots": k + 1, "rank": int(r), "entries": int(len(ind)),
+                            "max_indicator": float(ind.max()) if len(ind) else 0.0,
+                            "median_indicator": float(np.median(ind)) if len(ind) else 0.0})
+    wall = time.perf_counter() - t0
+    H, B, q, m = s.state()
+    hsub = np.abs(np.array([H[j + 1, j] for j in range(m)]))   # |h_{j+2,j+1}| after snapshot j + 2
+    s.close()
+    log(f"[indicators] {len(entries)} truncated evaluations, host {host_s:.1f} s of {wall:.1f} s; "
+        f"last: rank {entries[-1]['rank']}, max indicator {entries[-1]['max_indicator']:.2e}")
+    return {"form": "fp32-basis-cgs2", "every": every, "truncated": entries,
+            "per_snapshot_bound": {"definition": "|h_{j,j-1}| after snapshot j (>= every untruncated indicator)",
+                                   "values": [float(f"{v:.3e}") for v in hsub]},
+            "host_seconds": round(host_s, 2), "wall_seconds": round(wall, 2)}
+
+
 def run_blocked(prec, X, n, N, warmup, steps):
     """The blocked form (foa_push_blocked: 4 snapshots per sweep of the basis)
     over the same snapshots, from q = 0; one step = one run over all N."""
@@ -451,10 +489,15 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-blocked", action="store_true", help="skip the blocked form")
     ap.add_argument("--no-one-reduction", action="store_true", help="skip the one-reduction form")
+    ap.add_argument("--no-indicators", action="store_true", help="skip the indicator log of the workload")
+    ap.add_argument("--indicator-every", type=int, default=50)
     ap.add_argument("--only-one-reduction", action="store_true",
                     help="time only the one-reduction form (profiling runs)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the n = 1e8 run and its mode reconstruction")
+    ap.add_argument("--only-large", action="store_true",
+                    help="run only the n = 1e8 workload's leg (profiling runs)")
+    ap.add_argument("--large-n", type=int, default=None, help="row count of that leg (profiling runs)")
     ap.add_argument("--cpu-rows", type=int, default=1 << 20)
     ap.add_argument("--cpu-rows-1t", type=int, default=1 << 15)
     ap.add_argument("--oracle-full", action="store_true",
@@ -492,6 +535,13 @@ def main():
     import torch
 
     import datagen
+
+    if args.only_large:
+        lw = datagen.get_workload("large_1e8x300")
+        if args.large_n:
+            lw = lw.with_n(args.large_n)
+        print(json.dumps({"large_form": run_large(lw)}), flush=True)
+        return
 
     w = datagen.get_workload(args.workload)
     if args.n:
@@ -616,6 +666,11 @@ def main():
             out["blocked_form"] = blk
         except Exception as e:  # reported, never silently dropped
             out["blocked_form"] = {"error": f"{type(e).__name__}: {e}"}
+    if not args.no_indicators:
+        try:
+            out["indicator_log"] = run_indicator_log(X, n, N, args.indicator_every)
+        except Exception as e:  # reported, never silently dropped
+            out["indicator_log"] = {"error": f"{type(e).__name__}: {e}"}
     del X
     torch.cuda.empty_cache()
     if not args.no_batched:
@@ -625,7 +680,8 @@ def main():
             out["batched_form"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_large:
         try:
-            out["large_form"] = run_large(datagen.get_workload("large_1e8x300"))
+            lw = datagen.get_workload("large_1e8x300")
+            out["large_form"] = run_large(lw.with_n(args.large_n) if args.large_n else lw)
         except Exception as e:  # reported, never silently dropped
             out["large_form"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu:

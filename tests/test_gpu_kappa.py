@@ -9,12 +9,17 @@ is checked).  Both basis precisions and the blocked form (FP64) run through
 the C ABI; the oracle's error on the same snapshots is reported beside the
 device's.
 
-FP32 basis with FP64 arithmetic (a form the paper does not have): the paper's
-bound is checked with eps = eps32 (a uniform-FP32 reading of it), and the
-fitted slope is reported, not asserted: the storage rounding enters each new
-column after it has been computed and later columns are orthogonalised against
-the rounded basis, and on this map the error grows only about like
-eps32 * sqrt(kappa) (a CPU emulation of the same arithmetic shows the same).
+Checks: the paper's bound err <= N eps kappa_2 ||H|| at every point; the
+log-log slope of the error against kappa_2 in [0.8, 1.2] for the FP64 forms
+(linear in kappa, not quadratic); the device's FP64 error within a factor 10
+of the oracle's on the same snapshots (plus an eps ||H|| floor: both are the
+O(eps kappa) error of the same factorisation).  FP32 basis with FP64
+arithmetic (a form the paper does not have): the bound with eps = eps32, and
+a slope of at most 1.2 -- the storage rounding enters each new column after
+it has been computed and later columns are orthogonalised against the
+rounded basis, so on this map the error grows only about like eps32 *
+sqrt(kappa) (a CPU emulation of the same arithmetic shows the same); it must
+not grow faster than the paper's O(eps kappa).
 """
 
 import numpy as np
@@ -51,7 +56,7 @@ def _run_blocked(X, tol):
     return dict(status=status, q=q, m=m, H=H, beta=B, V=V, stream=s)
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "f64-blocked"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f64-blocked", "f64-one-reduction", "f32-one-reduction"])
 def test_projection_error_grows_like_kappa(prec):
     A = np.vander(np.linspace(0, 1, 50))
     ks, es = [], []
@@ -60,7 +65,11 @@ def test_projection_error_grows_like_kappa(prec):
         psi1 = np.random.default_rng(100 + seed).standard_normal(50)
         for N in NS:
             X = _krylov(A, psi1, N)
-            g = _run_blocked(X, 0.0) if prec == "f64-blocked" else run_gpu(X, prec, tol=0.0)
+            if prec == "f64-blocked":
+                g = _run_blocked(X, 0.0)
+            else:
+                form = "one_reduction" if prec.endswith("one-reduction") else "cgs2"
+                g = run_gpu(X, prec[:3], tol=0.0, form=form)
             assert g["q"] == N and g["status"] == 0
             m = N - 1
             V = g["V"][:, :m]
@@ -70,15 +79,19 @@ def test_projection_error_grows_like_kappa(prec):
             err_o = np.linalg.norm(ref.V[:, :m].T @ A @ ref.V[:, :m] - ref.H[:m, :m])
             kap = np.linalg.cond(X[:, :m])
             nH = np.linalg.norm(Hm)
-            eps = EPS32 if prec == "f32" else EPS64
+            eps = EPS32 if prec.startswith("f32") else EPS64
             lines.append(f"{seed:>4} {N:>3} {kap:9.2e} {err:9.2e} {err_o:10.2e} {err / (eps * kap * nH):15.2e}")
             # the paper's O(eps kappa) bound with the constant taken as N
             assert err <= N * eps * kap * nH, (seed, N, err, kap)
+            if eps == EPS64:
+                assert err <= 10 * err_o + 10 * EPS64 * nH, (seed, N, err, err_o)
             ks.append(kap)
             es.append(err)
             g["stream"].close()
     slope = np.polyfit(np.log(ks), np.log(es), 1)[0]
     announce(f"{prec}: log-log slope of the error against kappa_2: {slope:.2f} over {len(ks)} points\n"
              + "\n".join(lines))
-    if prec != "f32":
-        assert 0.6 <= slope <= 1.4
+    if prec.startswith("f64"):
+        assert 0.8 <= slope <= 1.2
+    else:
+        assert slope <= 1.2
