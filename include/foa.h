@@ -325,6 +325,17 @@ foa_status foa_batch_sync(foa_batch b, int32_t *h_q, int32_t *h_status);
  * through foa_batch_push only (FOA_E_STATE otherwise). */
 foa_status foa_batch_view(foa_batch b, int32_t s, foa_ctx *view);
 
+/* Choose the form of every stream of the batch (before the first push: after
+ * foa_batch_init or foa_batch_reset; FOA_E_STATE otherwise), as foa_set_form
+ * does for one stream.  FOA_FORM_ONE_REDUCTION: each step runs one sweep per
+ * tile bucket over the planned ranges, then every stream's reduction, H_bar
+ * product and finalize (one graph launch per step); the launch configuration
+ * is tuned again for it (table key with "/form1").  foa_batch_sync first
+ * finishes every stream's pending columns (two flush steps); views show the
+ * state as of the last foa_batch_sync.  FOA_E_ARG for an FP64 basis with a
+ * capacity above 257. */
+foa_status foa_batch_set_form(foa_batch b, foa_form form);
+
 /* Forget all snapshots of every stream (q = 0), keeping workspace, tuning and
  * graphs.  Stream-ordered. */
 foa_status foa_batch_reset(foa_batch b);

@@ -111,6 +111,11 @@ struct foa_batch_s {
   // one captured step per snapshot dtype and widest bucket that can be in use
   hipGraph_t graph[2][NBUCKET] = {};
   hipGraphExec_t exec[2][NBUCKET] = {};
+  // one-reduction form (foa_batch_set_form): flush steps, one graph per widest bucket
+  int form = 0;
+  hipGraph_t graph_flush[NBUCKET] = {};
+  hipGraphExec_t exec_flush[NBUCKET] = {};
+  bool ls_pending = false;  // pushes since the last flush
   int pushes = 0;  // foa_batch_push calls since the last reset
   std::string tune_path, tune_key;
   std::vector<DevState> hstates;
@@ -137,6 +142,9 @@ foa_status upload_config(foa_batch_s *b, int unit_panels) {
     d.coefA = v->sa.coefA;
     d.coefB = v->sa.coefB;
     d.coefC = v->sa.coefC;
+    d.part1 = reinterpret_cast<double *>(static_cast<char *>(v->ws) + v->L.ls_part1);
+    d.red = reinterpret_cast<double *>(static_cast<char *>(v->ws) + v->L.ls_red);
+    d.xpre = reinterpret_cast<double *>(static_cast<char *>(v->ws) + v->L.ls_xpre);
     d.n = v->n;
     d.P = v->L.P;
     d.n_max = v->n_max;
@@ -152,7 +160,9 @@ foa_status upload_config(foa_batch_s *b, int unit_panels) {
   // every bucket gets at least the tuned grid, and at least one workgroup
   // per resident slot of its kernel
   for (int k = 0; k < NBUCKET; ++k) {
-    if (b->occ[k] <= 0) b->occ[k] = batch_pass_occupancy(b->prec == FOA_PREC_F64, k);
+    if (b->occ[k] <= 0)
+      b->occ[k] = b->form == 1 ? ls_batch_occupancy(b->prec == FOA_PREC_F64, k)
+                               : batch_pass_occupancy(b->prec == FOA_PREC_F64, k);
     b->args.gridb[k] = std::min(kMaxBatchGrid, std::max(b->grid, b->occ[k] * b->cus));
   }
   return FOA_OK;
@@ -163,7 +173,19 @@ foa_status upload_config(foa_batch_s *b, int unit_panels) {
 // the reductions, finalize and next b.  Persistent mode (FP32 basis): the
 // streams of up to kPersistCols columns run in one persistent launch; first
 // pushes and wider bases take the bucket launches, which skip the others.
+hipError_t enqueue_ls_step(foa_batch_s *b, bool x_f64, hipStream_t s, int kmax) {
+  const bool v64 = b->prec == FOA_PREC_F64;
+  const BatchArgs &a = b->args;
+  hipError_t e;
+  if ((e = launch_batch_plan(a, s)) != hipSuccess) return e;
+  for (int k = 0; k <= kmax && k < NBUCKET; ++k)
+    if (ls_batch_supported(v64, k) && (e = launch_ls_batch_pass(v64, x_f64, k, a.gridb[k], a, s)) != hipSuccess)
+      return e;
+  return launch_ls_batch_small(a, s);
+}
+
 hipError_t enqueue_step(foa_batch_s *b, bool x_f64, hipStream_t s, int kmax) {
+  if (b->form == 1) return enqueue_ls_step(b, x_f64, s, kmax);
   const bool v64 = b->prec == FOA_PREC_F64;
   const int cols = batch_cols_per_qw(v64);
   const int qmax = pick_qw(std::max(b->B.max_nmax - 1, 1), cols);
@@ -198,6 +220,12 @@ void drop_graphs(foa_batch_s *b) {
       b->exec[x][k] = nullptr;
       b->graph[x][k] = nullptr;
     }
+  for (int k = 0; k < NBUCKET; ++k) {
+    if (b->exec_flush[k]) (void)hipGraphExecDestroy(b->exec_flush[k]);
+    if (b->graph_flush[k]) (void)hipGraphDestroy(b->graph_flush[k]);
+    b->exec_flush[k] = nullptr;
+    b->graph_flush[k] = nullptr;
+  }
 }
 
 // Widest bucket any stream can be in at the next push: a stream's basis
@@ -214,11 +242,14 @@ int widest_bucket(const foa_batch_s *b) {
   return k;
 }
 
-foa_status ensure_graph(foa_batch_s *b, bool x_f64, int kmax) {
-  hipGraphExec_t &slot = b->exec[x_f64 ? 1 : 0][kmax];
+foa_status ensure_graph(foa_batch_s *b, bool x_f64, int kmax, bool flush = false) {
+  hipGraphExec_t &slot = flush ? b->exec_flush[kmax] : b->exec[x_f64 ? 1 : 0][kmax];
+  hipGraph_t &gslot = flush ? b->graph_flush[kmax] : b->graph[x_f64 ? 1 : 0][kmax];
   if (slot) return FOA_OK;
   if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return FOA_E_DEVICE;
+  if (flush) b->args.ls_mode = 2;  // captured by value into the step's kernels
   hipError_t e = enqueue_step(b, x_f64, b->cap, kmax);
+  if (flush) b->args.ls_mode = 1;
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->cap, &g);
   if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -230,8 +261,26 @@ foa_status ensure_graph(foa_batch_s *b, bool x_f64, int kmax) {
     (void)hipGraphDestroy(g);
     return FOA_E_DEVICE;
   }
-  b->graph[x_f64 ? 1 : 0][kmax] = g;
+  gslot = g;
   slot = x;
+  return FOA_OK;
+}
+
+// One-reduction form: finish the pending columns of every stream (two flush
+// steps cover the deepest pipeline; a stream with nothing pending is left
+// alone).
+foa_status ls_flush(foa_batch_s *b) {
+  if (b->form != 1 || !b->ls_pending) return FOA_OK;
+  const int kmax = widest_bucket(b);
+  foa_status r = ensure_graph(b, false, kmax, true);
+  if (r != FOA_OK) return r;
+  for (int i = 0; i < 2; ++i)
+    if (hipGraphLaunch(b->exec_flush[kmax], b->stream) != hipSuccess) return FOA_E_DEVICE;
+  b->ls_pending = false;
+  for (foa_ctx_s *v : b->views) {
+    v->mirror_valid = false;
+    v->dmd.valid = false;
+  }
   return FOA_OK;
 }
 
@@ -414,7 +463,7 @@ foa_status tune(foa_batch_s *b) {
   for (int unit : kUnitCandidates)
     for (int gm : {1, 2, 4})
       if ((r = consider(unit, gm * b->cus, false)) != FOA_OK) return r;
-  if (b->prec == FOA_PREC_F32 && b->args.p_groups > 0)
+  if (b->prec == FOA_PREC_F32 && b->args.p_groups > 0 && b->form == 0)
     for (int unit : kUnitCandidates)
       if ((r = consider(unit, 2 * b->cus, true)) != FOA_OK) return r;
   b->tuned_ms = best;
@@ -560,6 +609,7 @@ foa_status foa_batch_push(foa_batch b, const void *const *d_x_ptrs, foa_dtype x_
     return FOA_E_DEVICE;
   if (hipGraphLaunch(b->exec[x_dtype == FOA_F64 ? 1 : 0][kmax], b->stream) != hipSuccess) return FOA_E_DEVICE;
   ++b->pushes;
+  if (b->form == 1) b->ls_pending = true;
   for (foa_ctx_s *v : b->views) {
     v->mirror_valid = false;
     v->dmd.valid = false;
@@ -569,6 +619,8 @@ foa_status foa_batch_push(foa_batch b, const void *const *d_x_ptrs, foa_dtype x_
 
 foa_status foa_batch_sync(foa_batch b, int32_t *h_q, int32_t *h_status) {
   if (!b) return FOA_E_ARG;
+  foa_status r = ls_flush(b);
+  if (r != FOA_OK) return r;
   if (hipStreamSynchronize(b->stream) != hipSuccess) return FOA_E_DEVICE;
   b->hstates.resize(b->S);
   if (hipMemcpy(b->hstates.data(), b->ws + b->B.states, (size_t)b->S * sizeof(DevState), hipMemcpyDeviceToHost) !=
@@ -598,7 +650,30 @@ foa_status foa_batch_view(foa_batch b, int32_t s, foa_ctx *view) {
 
 foa_status foa_batch_reset(foa_batch b) {
   if (!b) return FOA_E_ARG;
+  b->ls_pending = false;
   return reset_states(b);
+}
+
+foa_status foa_batch_set_form(foa_batch b, foa_form form) {
+  if (!b) return FOA_E_ARG;
+  if (form != FOA_FORM_CGS2 && form != FOA_FORM_ONE_REDUCTION) return FOA_E_ARG;
+  if (b->pushes != 0) return FOA_E_STATE;  // before the first push (after init or reset)
+  const int f = form == FOA_FORM_ONE_REDUCTION ? 1 : 0;
+  if (f == 1 && b->prec == FOA_PREC_F64 && b->B.max_nmax > 257) return FOA_E_ARG;
+  if (f == b->form) return FOA_OK;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return FOA_E_DEVICE;
+  drop_graphs(b);
+  b->form = f;
+  b->args.ls_mode = f;
+  b->persist = false;
+  for (int k = 0; k < NBUCKET; ++k) b->occ[k] = 0;
+  const size_t cut = b->tune_key.find("/form");
+  if (cut != std::string::npos) b->tune_key.resize(cut);
+  if (f == 1) b->tune_key += "/form1";
+  foa_status r = tune(b);
+  if (r == FOA_OK) r = reset_states(b);
+  if (r == FOA_OK && hipStreamSynchronize(b->stream) != hipSuccess) r = FOA_E_DEVICE;
+  return r;
 }
 
 foa_status foa_batch_destroy(foa_batch b) {

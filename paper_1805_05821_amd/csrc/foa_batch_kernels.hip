@@ -78,10 +78,15 @@ __global__ __launch_bounds__(1024) void k_batch_plan(BatchArgs b) {
     if (s < b.S) {
       const BatchStream &d = b.streams[s];
       DevState *st = d.st;
-      const bool offered = b.xptrs[s] != nullptr;
+      const bool offered = b.ls_mode != 2 && b.xptrs[s] != nullptr;
       const int j = st->q;
-      const bool room = j < d.n_max;
-      const int act = (st->status == ST_ACTIVE && offered && room) ? 1 : 0;
+      // one-reduction form: the pending columns also hold snapshots; a flush
+      // step runs every stream that has pending columns (also after a
+      // non-finite snapshot stopped it)
+      const bool room = (b.ls_mode ? j + st->ls_u + st->ls_x : j) < d.n_max;
+      const int act = b.ls_mode == 2
+                          ? ((st->status == ST_ACTIVE || st->status == ST_NONFINITE) && (st->ls_u || st->ls_x))
+                          : ((st->status == ST_ACTIVE && offered && room) ? 1 : 0);
       st->jstep = j;
       st->act = act;
       st->nseg = 0;
@@ -274,6 +279,8 @@ __global__ __launch_bounds__(256) void k_tune_states(BatchArgs b, int t) {
     st->q = t;
     st->status = ST_ACTIVE;
     st->full = 0;
+    // one-reduction form: the steady state (a column and a snapshot pending)
+    st->ls_u = st->ls_x = (b.ls_mode && t + 2 < d.n_max) ? 1 : 0;
   }
 }
 

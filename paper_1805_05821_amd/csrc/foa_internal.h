@@ -99,6 +99,7 @@ struct BatchStream {
   double *w, *part, *partn;
   DevState *st;
   double *H, *beta, *sigma, *bvec, *h, *s, *coefA, *coefB, *coefC;
+  double *part1, *red, *xpre;  // one-reduction form
   int64_t n, P;
   int n_max, ldg, ldH, ldB;
 };
@@ -124,6 +125,7 @@ struct BatchArgs {
   int *meta;                 // NBUCKET x 2: streams in the bucket, workgroups in use
   int *spos;                 // S: bucket (high 8 bits) and list position of each active stream
   int S, n_rblocks, max_nmax;
+  int ls_mode;               // 0: three-sweep form; one-reduction form: 1 push step, 2 flush step
   int cols_per_qw;           // basis columns per unit of tile width
   int gridb[NBUCKET];        // workgroups of the row-pass launches of bucket k
   int min_seg;               // fewest panels per workgroup
@@ -271,6 +273,12 @@ int ls_occupancy(bool tv_f64, bool tx_f64, int q, int nw_opt);
 hipError_t launch_ls_pass(bool tv_f64, bool tx_f64, int q, int nw_opt, int grid, const LsArgs &a, hipStream_t s);
 hipError_t launch_ls_reduce(const LsSmall &a, hipStream_t s);
 hipError_t launch_ls_finalize(const LsSmall &a, hipStream_t s);
+// batched one-reduction form: the sweep of bucket k (0 = empty basis, 1..5 as
+// the three-sweep buckets), then the per-stream reduce, H_bar product and finalize
+bool ls_batch_supported(bool tv_f64, int k);
+int ls_batch_occupancy(bool tv_f64, int k);
+hipError_t launch_ls_batch_pass(bool tv_f64, bool tx_f64, int k, int grid, const BatchArgs &b, hipStream_t s);
+hipError_t launch_ls_batch_small(const BatchArgs &b, hipStream_t s);
 
 // batched form (one call per kernel of a step; all captured in one graph)
 hipError_t launch_batch_plan(const BatchArgs &b, hipStream_t s);

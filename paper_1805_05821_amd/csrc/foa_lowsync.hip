@@ -51,8 +51,12 @@ constexpr int ls_lds_doubles() {
   return 2 * JCAP + 2 * 2 * NW * PANEL + 2 * PANEL + NW * LS_NSC;
 }
 
+// One workgroup processes panels pstart, pstart + pstep, ... < pend of one
+// stream and writes its partial sums to slot `slot`.  Called uniformly by the
+// whole workgroup (it synchronises).
 template <typename TV, typename TX, int NW, int QW, bool PREF>
-__device__ __forceinline__ void ls_pass_body(const LsArgs &a, double *lds) {
+__device__ __forceinline__ void ls_pass_body(const LsArgs &a, int64_t pstart, int64_t pend, int64_t pstep,
+                                             int slot, double *lds) {
 #pragma clang fp contract(off)
   constexpr int EPL = Vec<TV>::EPL;
   constexpr int LPC = 64 / EPL;
@@ -84,6 +88,7 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, double *lds) {
   const int cn = cf + hf;      // column the new snapshot is copied to
   const double cq = hu && hf ? uniform(st->ls_cq) : 0.0;
 
+  __syncthreads();  // the previous call of this workgroup may still read LDS
   for (int k = 0; k < 2; ++k)
     for (int c = tid; c < JCAP; c += NW * 64) s_coef[k][c] = (c < q) ? (k ? a.coefZ[c] : a.coefW[c]) : 0.0;
   __syncthreads();
@@ -120,7 +125,6 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, double *lds) {
     }
   };
 
-  const int64_t pstart = blockIdx.x, pend = a.P, pstep = gridDim.x;
   int64_t p = pstart;
   if (PREF && p < pend) {
     load_tile(p, t, tile_bytes);
@@ -250,7 +254,6 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, double *lds) {
     par ^= 1;
   }
 
-  const int slot = blockIdx.x;
 #pragma unroll
   for (int g = 0; g < QW; ++g) {
     double v0 = acc0[g], v1 = acc1[g];
@@ -301,18 +304,17 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(ls_wave
   if (!ls_runs(a.st, a.flush)) return;
   if (a.flush && !a.st->ls_u && !a.st->ls_x) return;
   __shared__ double lds[ls_lds_doubles<TV, NW, QW>()];
-  ls_pass_body<TV, TX, NW, QW, PREF>(a, lds);
+  ls_pass_body<TV, TX, NW, QW, PREF>(a, blockIdx.x, a.P, gridDim.x, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
 // Reduction: one wavefront per value (part0 columns, part1 columns, scalars),
 // lane-strided sums over the slots, then a butterfly: a fixed association.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ls_reduce(LsSmall a) {
-  if (!ls_runs(a.st, a.flush)) return;
-  if (a.flush && !a.st->ls_u && !a.st->ls_x) return;
+// one wavefront per value; vblock selects four consecutive values
+__device__ inline void ls_reduce_body(const LsSmall &a, int vblock) {
   const int lane = threadIdx.x & 63;
-  const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int v = vblock * 4 + (threadIdx.x >> 6);
   const int q = a.st->q;
   const double *src;
   int out;
@@ -337,6 +339,12 @@ __global__ __launch_bounds__(256) void k_ls_reduce(LsSmall a) {
   if (lane == 0) a.red[out] = t;
 }
 
+__global__ __launch_bounds__(256) void k_ls_reduce(LsSmall a) {
+  if (!ls_runs(a.st, a.flush)) return;
+  if (a.flush && !a.st->ls_u && !a.st->ls_x) return;
+  ls_reduce_body(a, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Finalize (one workgroup of 512 threads, q <= 511 after the push).
 // ---------------------------------------------------------------------------
@@ -357,13 +365,12 @@ __device__ inline double ls_block_sum(double v, double *sh) {
 // column c = q that the coming finalize finishes (eq. betacolumnupdate):
 // b_i = sum_{l = max(0, i-1)}^{c-2} H_bar[i, l] beta[l, c-1], i < c.  64 rows
 // x 4 contiguous l-slices per 256 threads, slices summed in order.
-__global__ __launch_bounds__(256) void k_ls_hprod(LsSmall a) {
+__device__ inline void ls_hprod_body(const LsSmall &a, int rblock) {
   __shared__ double sh[4][64];
   const DevState *st = a.st;
-  if (!ls_runs(st, a.flush) || !st->ls_u) return;
   const int c = st->q;
   const int r = threadIdx.x & 63, sl = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + r;
+  const int i = rblock * 64 + r;
   double t = 0.0;
   if (i < c) {
     const int lo = i > 0 ? i - 1 : 0, len = c - 1 > lo ? c - 1 - lo : 0;
@@ -382,6 +389,11 @@ __global__ __launch_bounds__(256) void k_ls_hprod(LsSmall a) {
   sh[sl][r] = t;
   __syncthreads();
   if (sl == 0 && i < c) a.bvec[i] = ((sh[0][r] + sh[1][r]) + sh[2][r]) + sh[3][r];
+}
+
+__global__ __launch_bounds__(256) void k_ls_hprod(LsSmall a) {
+  if (!ls_runs(a.st, a.flush) || !a.st->ls_u) return;
+  ls_hprod_body(a, blockIdx.x);
 }
 
 // H_bar's column c-1 once beta's column c is final: h = (beta_{0:c,c} -
@@ -631,6 +643,174 @@ hipError_t launch_ls_finalize(const LsSmall &a, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_ls_finalize, dim3(1), dim3(512), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched one-reduction form.  The per-step plan of the three-sweep batched
+// form (k_batch_plan with ls_mode) buckets the streams by final columns q
+// and cuts each bucket's panels into workgroup ranges; here each bucket runs
+// one sweep over its ranges, then every active stream its reduction, H_bar
+// product and finalize.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ LsSmall ls_small_of(const BatchStream &d, int flush) {
+  LsSmall a{};
+  a.st = d.st;
+  a.H = d.H;
+  a.beta = d.beta;
+  a.sigma = d.sigma;
+  a.w = d.h;
+  a.z = d.s;
+  a.coefW = d.coefA;
+  a.coefZ = d.coefB;
+  a.red = d.red;
+  a.bvec = d.bvec;
+  a.xpre = d.xpre;
+  a.part0 = d.part;
+  a.part1 = d.part1;
+  a.ldH = d.ldH;
+  a.ldB = d.ldB;
+  a.n_max = d.n_max;
+  a.ldg = d.ldg;
+  a.G = d.st->nseg;
+  a.nt = d.st->jstep;
+  a.flush = flush;
+  return a;
+}
+
+template <typename TV, typename TX, int NW, int QW, int BK>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(ls_waves<TV, NW, QW>()))) void k_ls_pass_batch(
+    BatchArgs b) {
+  __shared__ double lds[ls_lds_doubles<TV, NW, QW>()];
+  const int G = uniform(b.meta[2 * BK + 1]);
+  if ((int)blockIdx.x >= G) return;
+  const int cnt = uniform(b.meta[2 * BK]);
+  const int64_t *pre = b.pre + (size_t)BK * (b.S + 1);
+  const int *list = b.list + (size_t)BK * b.S;
+  const int64_t T = pre[cnt];
+  int64_t lo = uniform((int64_t)blockIdx.x * T / G);
+  const int64_t hi = uniform((int64_t)(blockIdx.x + 1) * T / G);
+  int i = uniform(b.first[BK * kMaxBatchGrid + blockIdx.x]);
+  const int flush = b.ls_mode == 2 ? 1 : 0;
+  while (lo < hi) {
+    const int s = uniform(list[i]);
+    const int64_t ps = uniform(pre[i]), pe = uniform(pre[i + 1]);
+    const int64_t e = pe < hi ? pe : hi;
+    const BatchStream &d = b.streams[s];
+    const DevState *st = uniform(d.st);
+    LsArgs a{};
+    a.W = uniform(d.W);
+    a.x = flush ? nullptr : uniform(b.xptrs[s]);
+    a.coefW = uniform(d.coefA);
+    a.coefZ = uniform(d.coefB);
+    a.st = st;
+    a.part0 = uniform(d.part);
+    a.part1 = uniform(d.part1);
+    a.n = uniform(d.n);
+    a.P = uniform(d.P);
+    a.n_max = uniform(d.n_max);
+    a.ldg = uniform(d.ldg);
+    a.flush = flush;
+    ls_pass_body<TV, TX, NW, QW, true>(a, lo - ps, e - ps, 1, (int)blockIdx.x - uniform(st->seg0), lds);
+    lo = e;
+    ++i;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ls_reduce_batch(BatchArgs b) {
+  const BatchStream &d = b.streams[blockIdx.y];
+  if (!d.st->act) return;
+  const LsSmall a = ls_small_of(d, b.ls_mode == 2);
+  if ((int)blockIdx.x * 4 >= 2 * a.nt + LS_NSC) return;
+  ls_reduce_body(a, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_ls_hprod_batch(BatchArgs b) {
+  const BatchStream &d = b.streams[blockIdx.y];
+  if (!d.st->act || !d.st->ls_u) return;
+  if ((int)blockIdx.x * 64 >= d.st->q && blockIdx.x > 0) return;
+  ls_hprod_body(ls_small_of(d, b.ls_mode == 2), blockIdx.x);
+}
+
+__global__ __launch_bounds__(512) void k_ls_finalize_batch(BatchArgs b) {
+  const int s = blockIdx.x;
+  const BatchStream &d = b.streams[s];
+  DevState *st = d.st;
+  const int flush = b.ls_mode == 2 ? 1 : 0;
+  if (!flush) {
+    if (b.xptrs[s] == nullptr) return;  // idle this step
+    if (!st->act) {                     // offered to a stream that takes no snapshot
+      if (threadIdx.x == 0) st->pushes += 1;
+      return;
+    }
+  } else if (!st->act) {
+    return;
+  }
+  ls_finalize_body<512>(ls_small_of(d, flush));
+}
+
+// Kernel shape of bucket k (basis sizes up to 32, 64, 128, 256, 512 final
+// columns; k = 0 for an empty basis takes the shape of k = 1).  FP32 basis:
+// 1, 2, 4, 8, 8 wavefronts with 8, 8, 8, 8, 16 groups; FP64 basis: 8
+// wavefronts with 2, 4, 8, 16 groups (at most 256 columns).
+bool ls_batch_supported(bool tv_f64, int k) { return !tv_f64 || k <= 4; }
+
+template <typename TV, typename TX, int BK>
+static const void *ls_batch_fn(int *nt) {
+  if constexpr (sizeof(TV) == 4) {
+    constexpr int NW = BK <= 1 ? 1 : (BK == 2 ? 2 : (BK == 3 ? 4 : 8));
+    constexpr int QW = BK == 5 ? 16 : 8;
+    *nt = NW * 64;
+    return reinterpret_cast<const void *>(&k_ls_pass_batch<TV, TX, NW, QW, BK>);
+  } else {
+    constexpr int QW = BK <= 1 ? 2 : (BK == 2 ? 4 : (BK == 3 ? 8 : 16));
+    *nt = 8 * 64;
+    return reinterpret_cast<const void *>(&k_ls_pass_batch<TV, TX, 8, QW, BK>);
+  }
+}
+
+template <typename TV, typename TX>
+static const void *ls_batch_fn_k(int k, int *nt) {
+  switch (k) {
+    case 0: return ls_batch_fn<TV, TX, 0>(nt);
+    case 1: return ls_batch_fn<TV, TX, 1>(nt);
+    case 2: return ls_batch_fn<TV, TX, 2>(nt);
+    case 3: return ls_batch_fn<TV, TX, 3>(nt);
+    case 4: return ls_batch_fn<TV, TX, 4>(nt);
+    default:
+      if constexpr (sizeof(TV) == 4) return ls_batch_fn<TV, TX, 5>(nt);
+      return nullptr;
+  }
+}
+
+static const void *ls_batch_kernel(bool tv_f64, bool tx_f64, int k, int *nt) {
+  if (tv_f64) return tx_f64 ? ls_batch_fn_k<double, double>(k, nt) : ls_batch_fn_k<double, float>(k, nt);
+  return tx_f64 ? ls_batch_fn_k<float, double>(k, nt) : ls_batch_fn_k<float, float>(k, nt);
+}
+
+int ls_batch_occupancy(bool tv_f64, int k) {
+  int nt = 0, nb = 0;
+  const void *f = ls_batch_kernel(tv_f64, false, k, &nt);
+  if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, nt, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_ls_batch_pass(bool tv_f64, bool tx_f64, int k, int grid, const BatchArgs &b, hipStream_t s) {
+  int nt = 0;
+  const void *f = ls_batch_kernel(tv_f64, tx_f64, k, &nt);
+  if (!f) return hipErrorInvalidValue;
+  void *args[] = {const_cast<BatchArgs *>(&b)};
+  return hipLaunchKernel(f, dim3(grid), dim3(nt), args, 0, s);
+}
+
+hipError_t launch_ls_batch_small(const BatchArgs &b, hipStream_t s) {
+  const int vblocks = (2 * b.max_nmax + LS_NSC + 3) / 4;
+  hipLaunchKernelGGL(k_ls_reduce_batch, dim3(vblocks, b.S), dim3(256), 0, s, b);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ls_hprod_batch, dim3((b.max_nmax + 63) / 64, b.S), dim3(256), 0, s, b);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ls_finalize_batch, dim3(b.S), dim3(512), 0, s, b);
   return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ EXPORTED = [
     "foa_get_state", "foa_copy_basis", "foa_copy_basis_rows", "foa_truncate", "foa_modes", "foa_indicators",
     "foa_reset", "foa_destroy", "foa_status_str", "foa_last_error", "foa_set_option", "foa_profile",
     "foa_profile_modes", "foa_next_column", "foa_block_workspace_bytes", "foa_push_blocked",
-    "foa_push_blocked_static", "foa_set_form", "foa_flush",
+    "foa_push_blocked_static", "foa_set_form", "foa_flush", "foa_batch_set_form",
     "foa_batch_workspace_bytes", "foa_batch_init", "foa_batch_push", "foa_batch_sync",
     "foa_batch_view", "foa_batch_reset", "foa_batch_destroy",
 ]
@@ -88,6 +88,7 @@ def _load():
         "foa_push_blocked": [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, P, ctypes.c_size_t],
         "foa_push_blocked_static": [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int],
         "foa_set_form": [P, c.c_int],
+        "foa_batch_set_form": [P, c.c_int],
         "foa_flush": [P],
         "foa_batch_workspace_bytes": [i32, P, P, c.c_int, c.POINTER(sz)],
         "foa_batch_init": [c.POINTER(P), i32, P, P, c.c_int, P, sz, P, f64, c.c_char_p],
@@ -274,6 +275,10 @@ def foa_push_blocked(ctx, X, ld, p, x_dtype, bws, bws_bytes):
 
 def foa_set_form(ctx, form):
     return _check(lib.foa_set_form(ctx, int(form)), ctx)
+
+
+def foa_batch_set_form(b, form):
+    return _check(lib.foa_batch_set_form(b, int(form)))
 
 
 def foa_flush(ctx):

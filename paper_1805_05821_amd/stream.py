@@ -125,7 +125,7 @@ class FOABatch:
     (foa_batch_* of the C ABI)."""
 
     def __init__(self, n_list, nmax_list, prec="f32", device="cuda", stream=None, breakdown_tol=-1.0,
-                 tune_table=None, ws_fill=None):
+                 tune_table=None, ws_fill=None, form="cgs2"):
         import torch
 
         self.n = [int(v) for v in n_list]
@@ -138,6 +138,8 @@ class FOABatch:
             self.ws.fill_(int(ws_fill))
         self.device = device
         self.b = F.foa_batch_init(self.n, self.n_max, self.prec, self.ws, stream, breakdown_tol, tune_table)
+        if form != "cgs2":
+            F.foa_batch_set_form(self.b, F.FOA_FORM_ONE_REDUCTION if form == "one_reduction" else form)
         self._ptrs = torch.zeros(self.S, dtype=torch.int64, device=device)
 
     def push(self, xs, x_dtype=None):
