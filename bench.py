@@ -180,13 +180,37 @@ def _stream_gate(H32, lam32, r, H64, B64, m):
     return float(ratio.max()), kap_r
 
 
-def run_batched(bw, warmup, runs, streams=None):
+def ls_sweep_bytes(n, N, sV=4.0, sX=4.0):
+    """Algorithmic bytes of the one-reduction form over N snapshots of n rows
+    followed by its flush: each sweep reads the q final columns once, reads
+    and writes the pending columns, and reads and stores the new snapshot
+    (the host model of the pending columns, as the library counts them)."""
+    q = hu = hx = 0
+    total = 0.0
+    for k in range(N + 2):
+        new = 1 if k < N else 0
+        if k >= N and not (hu or hx):
+            break
+        pend = hu + hx
+        total += n * (q * sV + pend * sV + (pend + new) * sV + new * sX)
+        if hu:
+            q, hu = q + 1, 0
+        if hx:
+            hu, hx = 1, 0
+        if new:
+            hx = 1
+    return total
+
+
+def run_batched(bw, warmup, runs, streams=None, form="cgs2"):
     """The batched form on a batched workload: every stream from q = 0 to its
-    N_s snapshots; one run = max N_s graph launches.  The median of ``runs``
-    timed runs is reported.  After timing, every stream is checked: basis
-    orthogonality ||I - V^T V||_2 against 10 sqrt(q) eps32, and its truncated
-    DMD (FP32 rank rule) against an FP64-basis batch of the same streams
-    (untimed) by the eigenvalue gate 10 eps32 kappa_r cond_i."""
+    N_s snapshots; one run = max N_s graph launches (plus, in the
+    one-reduction form, the two flush steps that finish every stream).  The
+    median of ``runs`` timed runs is reported.  After timing, every stream is
+    checked: basis orthogonality ||I - V^T V||_2 against 10 sqrt(q) eps32,
+    and its truncated DMD (FP32 rank rule) against an FP64-basis batch of the
+    same streams (CGS2 form, untimed) by the eigenvalue gate 10 eps32 kappa_r
+    cond_i."""
     import numpy as np
     import torch
 
@@ -209,17 +233,22 @@ def run_batched(bw, warmup, runs, streams=None):
     dptr = torch.from_numpy(ptr).cuda()
     log(f"[batched] generated {S} streams (sum n = {sum(n)}, sum N = {sum(N)}) in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
-    bt = FOABatch(n, N, prec="f32")
-    log(f"[batched] init + autotune {time.perf_counter() - t0:.2f} s")
+    bt = FOABatch(n, N, prec="f32", form=form)
+    tag = "[batched]" if form == "cgs2" else "[batched one-reduction]"
+    log(f"{tag} init + autotune {time.perf_counter() - t0:.2f} s")
     alg = 0.0
     for s in range(S):
-        j = np.arange(N[s], dtype=np.float64)
-        alg += n[s] * (3.0 * 4.0 * j.sum() + 8.0 * N[s])
+        if form == "cgs2":
+            j = np.arange(N[s], dtype=np.float64)
+            alg += n[s] * (3.0 * 4.0 * j.sum() + 8.0 * N[s])
+        else:
+            alg += ls_sweep_bytes(n[s], N[s])
 
     def one_run(b):
         b.reset()
         for k in range(T):
             b.push_ptrs(dptr[k], F.FOA_F32)
+        b.flush()
 
     for _ in range(warmup):
         one_run(bt)
@@ -260,10 +289,12 @@ def run_batched(bw, warmup, runs, streams=None):
     del Xs
     torch.cuda.empty_cache()
     gbs = alg / (ms / 1e3) / 1e9
-    log(f"[batched] median {ms:.1f} ms per run of {T} steps (runs {[round(t, 1) for t in times]}), "
+    log(f"{tag} median {ms:.1f} ms per run of {T} steps (runs {[round(t, 1) for t in times]}), "
         f"{sum(N) / (ms / 1e3):.0f} snapshots/s, {gbs:.0f} GB/s; worst stream: orth/bound {worst_orth:.2e}, "
         f"truncated eig err/bound {worst_eig:.2e}")
-    return {"workload": bw.name, "streams": S, "form": "fp32-basis-cgs2, one graph launch per step",
+    desc = ("fp32-basis-cgs2, one graph launch per step" if form == "cgs2" else
+            "fp32-basis one-reduction, one graph launch per step, two flush steps per run")
+    return {"workload": bw.name, "streams": S, "form": desc,
             "snapshots_per_run": int(sum(N)), "steps_per_run": int(T), "ms_per_run": round(ms, 3),
             "runs_ms": [round(t, 3) for t in times], "timing": f"median of {runs} runs after {warmup} warm-up",
             "value": round(sum(N) / (ms / 1e3), 1), "unit": "snapshots/s",
@@ -498,6 +529,8 @@ def main():
     ap.add_argument("--only-large", action="store_true",
                     help="run only the n = 1e8 workload's leg (profiling runs)")
     ap.add_argument("--large-n", type=int, default=None, help="row count of that leg (profiling runs)")
+    ap.add_argument("--only-batched", choices=["cgs2", "one_reduction", "both"], default=None,
+                    help="run only the batched_256 leg in the given form(s) (profiling runs)")
     ap.add_argument("--cpu-rows", type=int, default=1 << 20)
     ap.add_argument("--cpu-rows-1t", type=int, default=1 << 15)
     ap.add_argument("--oracle-full", action="store_true",
@@ -541,6 +574,12 @@ def main():
         if args.large_n:
             lw = lw.with_n(args.large_n)
         print(json.dumps({"large_form": run_large(lw)}), flush=True)
+        return
+
+    if args.only_batched:
+        bw = datagen.get_workload("batched_256")
+        forms = ["cgs2", "one_reduction"] if args.only_batched == "both" else [args.only_batched]
+        print(json.dumps({f: run_batched(bw, args.warmup, max(args.steps, 1), form=f) for f in forms}), flush=True)
         return
 
     w = datagen.get_workload(args.workload)
@@ -678,6 +717,12 @@ def main():
             out["batched_form"] = run_batched(datagen.get_workload("batched_256"), 1, 3)
         except Exception as e:  # reported, never silently dropped
             out["batched_form"] = {"error": f"{type(e).__name__}: {e}"}
+        if not args.no_one_reduction:
+            try:
+                out["batched_one_reduction"] = run_batched(datagen.get_workload("batched_256"), 1, 3,
+                                                           form="one_reduction")
+            except Exception as e:  # reported, never silently dropped
+                out["batched_one_reduction"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_large:
         try:
             lw = datagen.get_workload("large_1e8x300")

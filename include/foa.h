@@ -336,6 +336,12 @@ foa_status foa_batch_view(foa_batch b, int32_t s, foa_ctx *view);
  * capacity above 257. */
 foa_status foa_batch_set_form(foa_batch b, foa_form form);
 
+/* One-reduction form: enqueue the two flush steps that finish every stream's
+ * pending columns (the same steps foa_batch_sync runs first), without waiting;
+ * nothing to do when no push came since the last flush, and for the CGS2
+ * form.  Stream-ordered; a later foa_batch_push continues the streams. */
+foa_status foa_batch_flush(foa_batch b);
+
 /* Forget all snapshots of every stream (q = 0), keeping workspace, tuning and
  * graphs.  Stream-ordered. */
 foa_status foa_batch_reset(foa_batch b);

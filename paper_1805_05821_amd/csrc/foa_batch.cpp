@@ -654,6 +654,11 @@ foa_status foa_batch_reset(foa_batch b) {
   return reset_states(b);
 }
 
+foa_status foa_batch_flush(foa_batch b) {
+  if (!b) return FOA_E_ARG;
+  return ls_flush(b);
+}
+
 foa_status foa_batch_set_form(foa_batch b, foa_form form) {
   if (!b) return FOA_E_ARG;
   if (form != FOA_FORM_CGS2 && form != FOA_FORM_ONE_REDUCTION) return FOA_E_ARG;

@@ -39,6 +39,7 @@ EXPORTED = [
     "foa_reset", "foa_destroy", "foa_status_str", "foa_last_error", "foa_set_option", "foa_profile",
     "foa_profile_modes", "foa_next_column", "foa_block_workspace_bytes", "foa_push_blocked",
     "foa_push_blocked_static", "foa_set_form", "foa_flush", "foa_batch_set_form",
+    "foa_batch_flush",
     "foa_batch_workspace_bytes", "foa_batch_init", "foa_batch_push", "foa_batch_sync",
     "foa_batch_view", "foa_batch_reset", "foa_batch_destroy",
 ]
@@ -90,6 +91,7 @@ def _load():
         "foa_set_form": [P, c.c_int],
         "foa_batch_set_form": [P, c.c_int],
         "foa_flush": [P],
+        "foa_batch_flush": [P],
         "foa_batch_workspace_bytes": [i32, P, P, c.c_int, c.POINTER(sz)],
         "foa_batch_init": [c.POINTER(P), i32, P, P, c.c_int, P, sz, P, f64, c.c_char_p],
         "foa_batch_push": [P, P, c.c_int],
@@ -283,6 +285,10 @@ def foa_batch_set_form(b, form):
 
 def foa_flush(ctx):
     return _check(lib.foa_flush(ctx), ctx)
+
+
+def foa_batch_flush(b):
+    return _check(lib.foa_batch_flush(b))
 
 
 def foa_push_blocked_static(ctx, X, ld, p, x_dtype):

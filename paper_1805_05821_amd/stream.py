@@ -160,6 +160,10 @@ class FOABatch:
     def reset(self):
         return F.foa_batch_reset(self.b)
 
+    def flush(self):
+        """One-reduction form: enqueue the steps that finish the pending columns."""
+        return F.foa_batch_flush(self.b)
+
     def sync(self):
         return F.foa_batch_sync(self.b, self.S)
 

@@ -219,3 +219,45 @@ def test_batched_256_full_shape_vs_oracle():
     announce(f"{len(pick)} streams checked; worst err/bound: {worst}")
     assert max(worst.values()) <= 1.0
     bt.close()
+
+
+def test_flush_midway_then_continue():
+    """foa_batch_flush after 13 steps finishes every stream's pending columns
+    without waiting; the pushes after it continue the streams: against the
+    one-reduction oracle that flushes at the same point (FP64 basis)."""
+    import torch
+
+    from paper_1805_05821_amd import foa as F
+    from paper_1805_05821_amd.stream import FOABatch
+
+    w = datagen.get_workload("noisy_2p20x200")
+    Xs = [np.asfortranarray(datagen.snapshots_numpy(w.with_n(n).with_N(N), dtype="float64")[0])
+          for n, N in ((2000, 40), (9001, 25), (70, 33))]
+    S = len(Xs)
+    Xd = [torch.from_numpy(np.ascontiguousarray(X.T)).cuda() for X in Xs]
+    T = max(X.shape[1] for X in Xs)
+    bt = FOABatch([X.shape[0] for X in Xs], [X.shape[1] for X in Xs], prec="f64", form="one_reduction")
+    ptr = np.zeros((T, S), dtype=np.int64)
+    for s in range(S):
+        for t in range(Xs[s].shape[1]):
+            ptr[t, s] = Xd[s][t].data_ptr()
+    dptr = torch.from_numpy(ptr).cuda()
+    for t in range(T):
+        if t == 13:
+            bt.flush()
+        bt.push_ptrs(dptr[t], F.FOA_F64)
+    q, st = bt.sync()
+    for s, X in enumerate(Xs):
+        ref = LS.init(X.shape[0], X.shape[1])
+        for t in range(X.shape[1]):
+            if t == 13:
+                LS.flush(ref)
+            LS.push(ref, np.ascontiguousarray(X[:, t]))
+        LS.flush(ref)
+        H, B, qv, m = F.foa_get_state(bt.view(s))
+        assert qv == ref.q == X.shape[1] and st[s] == 0
+        kap = kappa_of(ref.beta[:m, :m])
+        eH, eB = rel(H[:qv, :m], ref.H[:qv, :m]), rel(B[:qv, :qv], ref.beta[:qv, :qv])
+        announce(f"stream {s}: q={qv} kappa={kap:.1e} relH={eH:.1e} relB={eB:.1e}")
+        assert max(eH, eB) <= 10 * qv * EPS64 * kap
+    bt.close()
