@@ -133,7 +133,7 @@ __global__ __launch_bounds__(NW * 64) void k_bpass(BlockArgs a) {
     const __amdgpu_buffer_rsrc_t rt = make_rsrc(Wb + (size_t)p * pbytes, bytes);
 #pragma unroll
     for (int g = 0; g < QW; ++g) {
-      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rt, (int)(goff0 + g * GBYTES), 0, 0);
+      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rt, (int)(goff0 + g * GBYTES), 0, kTileLoad);
       unpack16<TV>(v, dst[g]);
     }
   };

@@ -267,7 +267,7 @@ __device__ __forceinline__ void row_pass_body(const PassArgs &a, int64_t pstart,
     const __amdgpu_buffer_rsrc_t rt = make_rsrc(Wb + (size_t)p * pbytes, bytes);
 #pragma unroll
     for (int g = 0; g < QW; ++g) {
-      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rt, (int)(goff0 + g * GBYTES), 0, 0);
+      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rt, (int)(goff0 + g * GBYTES), 0, kTileLoad);
       unpack16<TV>(v, dst[g]);
     }
   };

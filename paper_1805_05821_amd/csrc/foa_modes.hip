@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB <= 5 ? 3
       const int e = (tid + u * 256) * 4;  // first of 4 consecutive rows
       const int c = e / MT_ROWS, row = e % MT_ROWS;
       const unsigned off = k0 + c < kdim ? (row / PANEL) * pbytes + ((k0 + c) * PANEL + row % PANEL) * 4u : kOOR;
-      ra[u] = __builtin_bit_cast(f32x4v, __builtin_amdgcn_raw_buffer_load_b128(rw, (int)off, 0, 0));
+      ra[u] = __builtin_bit_cast(f32x4v, __builtin_amdgcn_raw_buffer_load_b128(rw, (int)off, 0, kTileLoad));
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
