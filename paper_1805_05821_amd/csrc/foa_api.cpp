@@ -133,10 +133,8 @@ int pass_grid(foa_ctx_s *c, int j, bool x_f64) {
   if (g <= 0) {
     const bool v64 = c->prec == FOA_PREC_F64;
     const int nw = pass_nw(v64, c->nw, j);
-    const int cols = v64 ? 32 : nw * 4;
-    const int qw = pick_qw(j > 0 ? j : 1, cols);
-    int qi = 0;
-    while ((1 << qi) < qw) ++qi;
+    const int qw = pass_qw(v64, nw, j);
+    const int qi = tile_slot(qw);
     const int ni = nw == 4 ? 0 : (nw == 8 ? 1 : 2);
     int &occ = c->occ_cache[x_f64 ? 1 : 0][ni][qi];
     if (occ <= 0) occ = pass_occupancy(v64, x_f64, c->prefetch, nw, qw);

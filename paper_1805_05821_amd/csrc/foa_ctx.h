@@ -58,7 +58,7 @@ struct foa_ctx_s {
   foa::SmallArgs sa{};
   // launch configuration
   int grid_auto = 0, grid_opt = 0;
-  int occ_cache[2][3][5] = {};  // resident pass-A workgroups per CU [x_f64][nw 4/8/16][log2 qw]
+  int occ_cache[2][3][7] = {};  // resident pass-A workgroups per CU [x_f64][nw 4/8/16][tile_slot]
   bool prefetch = false;
   int nw = 16;  // wavefronts per row-pass workgroup (FP32 basis: 8 or 16)
   double tol = 0.0;
@@ -81,7 +81,7 @@ struct foa_ctx_s {
   // dependent or non-finite snapshot, which the next synchronising call reads)
   int form = 0;
   int ls_hu = 0, ls_hx = 0;
-  int ls_occ[2][2][3][5] = {};  // resident sweep workgroups per CU [v64][x64][nw][log2 qw]
+  int ls_occ[2][2][3][7] = {};  // resident sweep workgroups per CU [v64][x64][nw][tile_slot]
   int ls_nw_opt = 0;            // option "ls_nw": 0 automatic, 16 = 16-wavefront sweeps above 128 columns
   // row-pass timing (foa_profile)
   bool profile = false;

@@ -107,7 +107,7 @@ __device__ __forceinline__ void unpack16<double>(const u32x4 &v, double (&o)[2])
 // loop (a reload inside it would wait for the prefetched tile).
 template <typename TV, int QW>
 constexpr int pass_waves() {
-  return sizeof(TV) == 4 ? (QW == 8 ? 4 : (QW == 4 ? 5 : 1)) : 1;
+  return sizeof(TV) == 4 ? ((QW == 8 || QW == 6) ? 4 : (QW == 4 ? 5 : 1)) : 1;
 }
 
 // Work-vector schemes of the row passes (see the fused row pass below).

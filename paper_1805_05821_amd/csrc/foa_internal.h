@@ -263,6 +263,11 @@ hipError_t launch_modes_gemm(bool tv_f64, const void *W, int64_t n, int n_max, i
                              hipStream_t s);
 
 int pick_qw(int j, int cols_per_qw);
+// groups per wavefront of the row pass at basis size j with nw wavefronts
+int pass_qw(bool tv_f64, int nw, int j);
+// index of a tile width (groups per wavefront: 1, 2, 4, 8, 16, 6, 12) in
+// per-width caches, 0..6
+int tile_slot(int qw);
 
 // one-reduction form
 // wavefronts per sweep workgroup (nw_opt 16: sixteen above 128 columns, FP32 basis)

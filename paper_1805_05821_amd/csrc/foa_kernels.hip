@@ -79,6 +79,27 @@ int pick_qw(int j, int cols_per_qw) {
   return qw;
 }
 
+int tile_slot(int qw) {
+  switch (qw) {
+    case 1: return 0;
+    case 2: return 1;
+    case 4: return 2;
+    case 8: return 3;
+    case 16: return 4;
+    case 6: return 5;
+    default: return 6;
+  }
+}
+
+// The FP32 pass has 6-group tiles where the power-of-two tile would be a
+// third to a half empty and a 6-group one measured faster at n = 2^24:
+// 8 x 6 for 129-192 columns (about 2%) and 16 x 6 for 321-384 (about 5%;
+// 16 x 6 for 257-320 was 6% slower than 8 x 16).
+int pass_qw(bool tv_f64, int nw, int j) {
+  if (!tv_f64 && ((nw == 8 && j > 128 && j <= 192) || (nw == 16 && j > 320 && j <= 384))) return 6;
+  return pick_qw(j > 0 ? j : 1, tv_f64 ? 32 : nw * 4);
+}
+
 template <typename TV, typename TX, int NW, int MODE, bool PREF>
 static hipError_t launch_pass_q(int qw, int grid, const PassArgs &a, hipStream_t s) {
   constexpr int NT = NW * 64;
@@ -87,6 +108,12 @@ static hipError_t launch_pass_q(int qw, int grid, const PassArgs &a, hipStream_t
     case 2: hipLaunchKernelGGL((k_pass<TV, TX, NW, 2, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
     case 4: hipLaunchKernelGGL((k_pass<TV, TX, NW, 4, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
     case 8: hipLaunchKernelGGL((k_pass<TV, TX, NW, 8, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 6:
+      if constexpr (sizeof(TV) == 4 && NW >= 8) {
+        hipLaunchKernelGGL((k_pass<TV, TX, NW, 6, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
     default:
       if constexpr (NW * 16 * Vec<TV>::EPL <= 512)
         hipLaunchKernelGGL((k_pass<TV, TX, NW, 16, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a);
@@ -106,7 +133,7 @@ static bool prefetch_fits(int qw) {
 
 template <typename TV, typename TX, int NW>
 static hipError_t launch_pass_m(int mode, bool pref, int grid, const PassArgs &a, hipStream_t s) {
-  const int qw = pick_qw(a.j, NW * Vec<TV>::EPL);
+  const int qw = pass_qw(sizeof(TV) == 8, NW, a.j);
   if (qw * NW * Vec<TV>::EPL < a.j) return hipErrorInvalidValue;  // tile narrower than the basis
   pref = pref && prefetch_fits<TV, NW>(qw);
   switch (mode) {
@@ -173,6 +200,9 @@ static int occ_m(int qw, bool pref) {
     case 2: return occ_q<TV, TX, NW, 2>(pref);
     case 4: return occ_q<TV, TX, NW, 4>(pref);
     case 8: return occ_q<TV, TX, NW, 8>(pref);
+    case 6:
+      if constexpr (sizeof(TV) == 4 && NW >= 8) return occ_q<TV, TX, NW, 6>(pref);
+      return 1;
     default:
       if constexpr (NW * 16 * Vec<TV>::EPL <= 512) return occ_q<TV, TX, NW, 16>(pref);
       return 1;

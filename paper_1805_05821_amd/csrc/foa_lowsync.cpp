@@ -56,8 +56,7 @@ int ls_grid(foa_ctx_s *c, int q, bool x64) {
   if (g <= 0) {
     const bool v64 = c->prec == FOA_PREC_F64;
     const int nw = ls_nw(v64, q, c->ls_nw_opt), qw = ls_qw(v64, q, c->ls_nw_opt);
-    int qi = 0;
-    while ((1 << qi) < qw) ++qi;
+    const int qi = tile_slot(qw);
     const int ni = nw == 4 ? 0 : (nw == 8 ? 1 : 2);
     int &occ = c->ls_occ[v64 ? 1 : 0][x64 ? 1 : 0][ni][qi];
     if (occ <= 0) occ = ls_occupancy(v64, x64, q, c->ls_nw_opt);

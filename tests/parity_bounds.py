@@ -14,6 +14,31 @@ import numpy as np
 from scipy.optimize import linear_sum_assignment
 
 C = 10.0
+EPS64 = 2.0 ** -52
+
+
+def column_gate_f64(g, st, c=C):
+    """Element-wise FP64 gate, column by column: column j of H_bar and of
+    beta against c (j+2) eps64 kappa_2 of the leading (j+2) x (j+2) block of
+    the oracle's beta (the snapshots column j depends on), relative to the
+    largest entry of the leading block.  Returns the largest error / bound
+    (columns whose leading block is singular, after a breakdown, are
+    skipped)."""
+    m, q = g["m"], g["q"]
+    worst = 0.0
+    for j in range(m):
+        k = min(j + 2, q)
+        s = np.linalg.svd(st.beta[:k, :k], compute_uv=False)
+        if not s[-1] > 0.0:
+            continue
+        kap = s[0] / s[-1]
+        scale = np.abs(st.H[:k, :j + 1]).max()
+        eH = np.abs(g["H"][:k, j] - st.H[:k, j]).max() / scale
+        sb = np.abs(st.beta[:k, :k]).max()
+        eB = np.abs(g["beta"][:k, j + 1] - st.beta[:k, j + 1]).max() / sb if j + 1 < q else 0.0
+        tol = c * k * EPS64 * kap
+        worst = max(worst, eH / tol, eB / tol)
+    return worst
 
 
 def svals(beta_m):

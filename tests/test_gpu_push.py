@@ -5,6 +5,7 @@ import pytest
 
 import datagen
 import oracle
+import parity_bounds as PB
 from gpu_helpers import EPS32, EPS64, announce, kappa_of, rel, run_gpu
 from pins import match_eigs
 
@@ -39,8 +40,11 @@ def _compare_f64(g, st, c=100.0):
     bc = q + 1 if st.status == "invariant" else q
     eB = rel(g["beta"][:q, :bc], st.beta[:q, :bc])
     eV = np.abs(g["V"] - st.V[:, :q]).max()
-    announce(f"q={q} kappa={kap:.2e} relH={eH:.2e} relB={eB:.2e} maxV={eV:.2e} tol={tol:.2e}")
+    col = PB.column_gate_f64(g, st)
+    announce(f"q={q} kappa={kap:.2e} relH={eH:.2e} relB={eB:.2e} maxV={eV:.2e} tol={tol:.2e} "
+             f"column err/bound {col:.2e}")
     assert eH <= tol and eB <= tol and eV <= tol
+    assert col <= 1.0
     return kap
 
 

@@ -54,25 +54,6 @@ def _gram_gpu(s, q):
     return G
 
 
-def _column_gate_f64(g, st, c=10.0):
-    """Column j of H_bar and of beta against c (j+2) eps64 kappa_2 of the
-    leading (j+2) x (j+2) block of beta (the snapshots column j depends on),
-    relative to the largest entry of the leading block."""
-    m, q = g["m"], g["q"]
-    worst = 0.0
-    for j in range(m):
-        k = min(j + 2, q)
-        s = np.linalg.svd(st.beta[:k, :k], compute_uv=False)
-        kap = s[0] / s[-1]
-        scale = np.abs(st.H[:k, :j + 1]).max()
-        eH = np.abs(g["H"][:k, j] - st.H[:k, j]).max() / scale
-        sb = np.abs(st.beta[:k, :k]).max()
-        eB = np.abs(g["beta"][:k, j + 1] - st.beta[:k, j + 1]).max() / sb if j + 1 < q else 0.0
-        tol = c * k * EPS64 * kap
-        worst = max(worst, eH / tol, eB / tol)
-    return worst
-
-
 def _truncated_checks(g, st, r, eps, tag, modes_phi=None, binding=True):
     """Truncated eigenvalues, projection and indicators (and, with a mode
     matrix, the modes) of the HIP path against the oracle at rank r."""
@@ -165,7 +146,7 @@ def test_headline_recipe_reduced_n(prec):
     H_o = st.H[:m, :m]
     eH = np.linalg.norm(g["H"][:m, :m] - H_o, 2) / np.linalg.norm(H_o, 2)
     if prec == "f64":
-        worst = _column_gate_f64(g, st)
+        worst = PB.column_gate_f64(g, st)
         lam_o, Z, Yn, cond = PB.eig_condition(H_o)
         ratio, err, _ = PB.eig_gate(np.linalg.eigvals(g["H"][:m, :m]), lam_o, cond, EPS64, kap)
         announce(f"f64: kappa_2={kap:.2e} relH2={eH:.2e} column gate max err/bound {worst:.2e} "
