@@ -19,9 +19,22 @@
       the SHA-256 of the kernel source it describes.
   python -m paper_1805_05821_amd.rocprof_summary batched FETCH_DIR WRITE_DIR \
          FETCH_SCALE WRITE_SCALE STEPS
-      HBM bytes of the batched form's last run: FETCH_SIZE and WRITE_SIZE of
-      every batched kernel dispatched from the STEPS-th last plan dispatch on,
-      scaled by the calibration factors (bytes per counter unit), per kernel.
+      HBM bytes of the batched form's last timed run: FETCH_SIZE and
+      WRITE_SIZE of every batched kernel dispatched from the STEPS-th last plan
+      dispatch before the FP64-basis reference batch on, scaled by the
+      calibration factors (bytes per counter unit), per kernel.
+  python -m paper_1805_05821_amd.rocprof_summary kernel_traffic FETCH_DIR WRITE_DIR \
+         FETCH_COPY_DIR WRITE_COPY_DIR COPY_BYTES NAME_PREFIX BENCH_LOG KEY
+      the same per-launch HBM bytes for the kernels whose name starts with
+      NAME_PREFIX, against the algorithmic bytes per launch that the
+      benchmark's JSON line in BENCH_LOG holds under KEY.
+  python -m paper_1805_05821_amd.rocprof_summary batched_run DIR OCCURRENCE STEPS
+      per-kernel time of one batched run in a kernel trace: the STEPS plan
+      dispatches (k_batch_plan) that precede the OCCURRENCE-th FP64-basis
+      batch (the untimed reference batch bench.py builds after each timed
+      batched leg, 1-based), with every dispatch from the first of them to
+      the run's last finalize; also the span from the first dispatch's start
+      to the last one's end.
 """
 
 import csv
@@ -125,6 +138,33 @@ def _row_pass_avg(d, counter):
     return v / max(n, 1), n
 
 
+def _prefix_avg(d, counter, prefix):
+    per = counter_per_dispatch(d, counter)
+    v = sum(x for name, (x, n) in per.items() if name.startswith(prefix))
+    n = sum(n for name, (x, n) in per.items() if name.startswith(prefix))
+    return v / max(n, 1), n
+
+
+def kernel_traffic(fetch_dir, write_dir, fetch_copy, write_copy, copy_bytes, prefix, bench_log, key):
+    import json
+
+    copy_bytes = float(copy_bytes)
+    f_scale = copy_bytes / _copy_value(fetch_copy, "FETCH_SIZE")
+    w_scale = copy_bytes / _copy_value(write_copy, "WRITE_SIZE")
+    f_avg, nf = _prefix_avg(fetch_dir, "FETCH_SIZE", prefix)
+    w_avg, nw = _prefix_avg(write_dir, "WRITE_SIZE", prefix)
+    alg = None
+    for line in open(bench_log):
+        line = line.strip()
+        if line.startswith("{") and f'"{key}"' in line:
+            alg = json.loads(line)[key]
+    fetch_b, write_b = f_avg * f_scale, w_avg * w_scale
+    return {"kernels": prefix, "dispatches": [nf, nw], "fetch_bytes_per_launch": fetch_b,
+            "write_bytes_per_launch": write_b, "traffic_bytes_per_launch": fetch_b + write_b,
+            "alg_bytes_per_launch": alg, "traffic_over_alg": (fetch_b + write_b) / alg if alg else None,
+            "fetch_scale": f_scale, "write_scale": w_scale}
+
+
 ROW_PASS_SOURCES = ("foa_buffer.h", "foa_device.h", "foa_kernels.hip")
 
 
@@ -192,6 +232,43 @@ def window(d, prefix, start, count):
             f"{len(sel)} dispatches, total {sum(ms):.2f} ms, average {sum(ms) / max(len(ms), 1):.4f} ms")
 
 
+def batched_run(d, occurrence, steps):
+    """Per-kernel time of one batched run (see the module docstring)."""
+    rows = []
+    for path in _find(d, "kernel_trace.csv"):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]),
+                             _col(r, "Kernel_Name", "Kernel-Name")))
+    rows.sort()
+    # an FP64-basis batch starts at its first row pass after FP32-basis
+    # batched row passes or sweeps
+    starts, last = [], None
+    for i, (_, _, n) in enumerate(rows):
+        if "k_pass_batch<double" in n:
+            if last != "f64":
+                starts.append(i)
+            last = "f64"
+        elif "k_pass_batch<float" in n or "k_ls_pass_batch<float" in n:
+            last = "f32"
+    end = starts[int(occurrence) - 1]
+    plans = [i for i in range(end) if rows[i][2].startswith("foa::k_batch_plan")]
+    first = plans[-int(steps)]
+    # the run ends with its last step's finalize (the next batch's set-up follows)
+    last = max(i for i in range(first, end) if "finalize_batch" in rows[i][2])
+    per = defaultdict(lambda: [0, 0.0])
+    for a, b, n in rows[first:last + 1]:
+        k = n.split("(")[0]
+        per[k][0] += 1
+        per[k][1] += (b - a) / 1e6
+    busy = sum(v[1] for v in per.values())
+    span = (rows[last][1] - rows[first][0]) / 1e6
+    lines = [f"dispatches {first}..{last} in time order: span {span:.2f} ms, kernel time {busy:.2f} ms"]
+    for k, (c, ms) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"{c:6d} {ms:9.2f} ms {1e3 * ms / c:9.1f} us  {k}")
+    return "\n".join(lines)
+
+
 def batched_traffic(fetch_dir, write_dir, fetch_scale, write_scale, steps):
     """Per-kernel HBM bytes of the batched form's last run of STEPS steps."""
     lines, total = [], 0.0
@@ -205,12 +282,25 @@ def batched_traffic(fetch_dir, write_dir, fetch_scale, write_scale, steps):
                 di = int(_col(r, "Dispatch_Id"))
                 per[di] += float(_col(r, "Counter_Value"))
                 name[di] = _col(r, "Kernel_Name")
-        plans = sorted(di for di, n in name.items() if n.startswith("foa::k_batch_plan"))
+        # the timed FP32-basis run ends where the FP64-basis reference batch
+        # that bench.py builds after it starts
+        end, last = None, None
+        for di in sorted(name):
+            n = name[di]
+            if "k_pass_batch<double" in n:
+                if last == "f32":
+                    end = di
+                    break
+                last = "f64"
+            elif "k_pass_batch<float" in n or "k_ls_pass_batch<float" in n or "k_step_persist<float" in n:
+                last = "f32"
+        end = end if end is not None else max(name) + 1
+        plans = sorted(di for di, n in name.items() if n.startswith("foa::k_batch_plan") and di < end)
         first = plans[-int(steps)]
         tot = defaultdict(float)
         for di, v in per.items():
             n = name[di]
-            if di >= first and ("batch" in n.lower() or "persist" in n):
+            if first <= di < end and ("batch" in n.lower() or "persist" in n):
                 tot[n.split("(")[0]] += v * scale
         sub = sum(tot.values())
         total += sub
@@ -229,6 +319,12 @@ def main(argv):
         print(window(argv[1], argv[2], argv[3], argv[4]))
     elif len(argv) >= 3 and argv[0] == "counter":
         print(summarize_counter(argv[1], argv[2]))
+    elif len(argv) >= 9 and argv[0] == "kernel_traffic":
+        import json
+
+        print(json.dumps(kernel_traffic(*argv[1:9]), indent=1))
+    elif len(argv) >= 4 and argv[0] == "batched_run":
+        print(batched_run(argv[1], argv[2], argv[3]))
     elif len(argv) >= 6 and argv[0] == "batched":
         print(batched_traffic(*argv[1:6]))
     elif len(argv) >= 8 and argv[0] == "traffic":
