@@ -89,6 +89,64 @@ def run_form(prec, X, n, N, warmup, steps, options, r_force=0, form="cgs2"):
     return res
 
 
+def copy_bandwidth(gib=4.0, reps=3):
+    """Device-to-device copy rate (bytes read + written per second) of a plain
+    torch copy: the practical streaming reference the roofline fraction is
+    also reported against."""
+    import torch
+
+    nbytes = int(gib * (1 << 30)) // 4 * 4
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def run_latency_small(runs=5):
+    """The latency-bound exact-rank workload (n = 4096, N = 64, FP64 basis;
+    the basis fits the caches): microseconds per push over whole runs of all
+    64 pushes (the stream becomes invariant at snapshot 21; later pushes are
+    ignored on the device), median of `runs` after a warm-up."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_1805_05821_amd.stream import FOAStream
+
+    w = datagen.get_workload("exact_rank_4096x64")
+    X, _, _ = datagen.snapshots_torch(w, "cuda")
+    s = FOAStream(w.n, w.N, prec="f64")
+    s.push_all(X)
+    st, q = s.sync()
+    times = []
+    for _ in range(runs):
+        s.reset()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.push_all(X)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    st, q = s.sync()
+    s.close()
+    ms = float(np.median(times))
+    log(f"[latency] exact_rank_4096x64: {1e3 * ms / w.N:.1f} us per push (q={q}, status={st})")
+    return {"workload": w.name, "bound": "latency (the basis fits the caches)", "pushes": w.N, "q": q,
+            "status": st, "us_per_push": round(1e3 * ms / w.N, 2), "runs_ms": [round(t, 4) for t in times],
+            "timing": f"median of {runs} runs after a warm-up"}
+
+
 def run_indicator_log(X, n, N, every):
     """Error indicators along the stream (Section 3.2.3; the stopping criterion
     of Algorithm 3 is the caller's): one untimed FP32-basis run of the
@@ -647,6 +705,13 @@ def main():
         },
         "hbm_gbs_step": round(r32["pass_bytes"] / args.steps / (r32["ms_per_step"] / 1e3) / 1e9, 1),
     }
+    try:
+        cgbs = copy_bandwidth()
+        out["roofline"]["copy_gbs"] = round(cgbs, 1)
+        out["roofline"]["frac_of_copy"] = round(achieved / cgbs, 4)
+        log(f"device copy {cgbs:.0f} GB/s (read + write); row passes at {achieved / cgbs:.3f} of it")
+    except Exception as e:  # reported, never silently dropped
+        out["roofline"]["copy_gbs"] = f"error: {type(e).__name__}: {e}"
     if r64 is not None:
         m = min(r32["m"], r64["m"])
         H32, H64 = r32["H"][:m, :m], r64["H"][:m, :m]
@@ -723,6 +788,10 @@ def main():
                                                            form="one_reduction")
             except Exception as e:  # reported, never silently dropped
                 out["batched_one_reduction"] = {"error": f"{type(e).__name__}: {e}"}
+    try:
+        out["latency_form"] = run_latency_small()
+    except Exception as e:  # reported, never silently dropped
+        out["latency_form"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_large:
         try:
             lw = datagen.get_workload("large_1e8x300")
