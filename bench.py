@@ -579,6 +579,7 @@ def main():
     ap.add_argument("--no-blocked", action="store_true", help="skip the blocked form")
     ap.add_argument("--no-one-reduction", action="store_true", help="skip the one-reduction form")
     ap.add_argument("--no-indicators", action="store_true", help="skip the indicator log of the workload")
+    ap.add_argument("--no-latency", action="store_true", help="skip the latency-bound exact-rank workload")
     ap.add_argument("--indicator-every", type=int, default=50)
     ap.add_argument("--only-one-reduction", action="store_true",
                     help="time only the one-reduction form (profiling runs)")
@@ -788,10 +789,11 @@ def main():
                                                            form="one_reduction")
             except Exception as e:  # reported, never silently dropped
                 out["batched_one_reduction"] = {"error": f"{type(e).__name__}: {e}"}
-    try:
-        out["latency_form"] = run_latency_small()
-    except Exception as e:  # reported, never silently dropped
-        out["latency_form"] = {"error": f"{type(e).__name__}: {e}"}
+    if not args.no_latency:
+        try:
+            out["latency_form"] = run_latency_small()
+        except Exception as e:  # reported, never silently dropped
+            out["latency_form"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_large:
         try:
             lw = datagen.get_workload("large_1e8x300")

@@ -91,12 +91,14 @@ int tile_slot(int qw) {
   }
 }
 
-// The FP32 pass has 6-group tiles where the power-of-two tile would be a
-// third to a half empty and a 6-group one measured faster at n = 2^24:
-// 8 x 6 for 129-192 columns (about 2%) and 16 x 6 for 321-384 (about 5%;
-// 16 x 6 for 257-320 was 6% slower than 8 x 16).
+// The FP32 pass has 6- and 12-group tiles where the power-of-two tile would
+// be a third to a half empty and the narrower one measured faster at
+// n = 2^24: 8 x 6 for 129-192 columns (about 2%), 8 x 12 for 257-320 (about
+// 2%) and 16 x 6 for 321-384 (about 5%; 16 x 6 for 257-320 was 6% slower
+// than 8 x 16, and 8 x 12 for 321-384 no faster than 16 x 6).
 int pass_qw(bool tv_f64, int nw, int j) {
   if (!tv_f64 && ((nw == 8 && j > 128 && j <= 192) || (nw == 16 && j > 320 && j <= 384))) return 6;
+  if (!tv_f64 && nw == 8 && j > 256 && j <= 320) return 12;
   return pick_qw(j > 0 ? j : 1, tv_f64 ? 32 : nw * 4);
 }
 
@@ -111,6 +113,12 @@ static hipError_t launch_pass_q(int qw, int grid, const PassArgs &a, hipStream_t
     case 6:
       if constexpr (sizeof(TV) == 4 && NW >= 8) {
         hipLaunchKernelGGL((k_pass<TV, TX, NW, 6, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
+    case 12:
+      if constexpr (sizeof(TV) == 4 && NW == 8) {
+        hipLaunchKernelGGL((k_pass<TV, TX, NW, 12, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a);
         break;
       }
       return hipErrorInvalidValue;
@@ -202,6 +210,9 @@ static int occ_m(int qw, bool pref) {
     case 8: return occ_q<TV, TX, NW, 8>(pref);
     case 6:
       if constexpr (sizeof(TV) == 4 && NW >= 8) return occ_q<TV, TX, NW, 6>(pref);
+      return 1;
+    case 12:
+      if constexpr (sizeof(TV) == 4 && NW == 8) return occ_q<TV, TX, NW, 12>(pref);
       return 1;
     default:
       if constexpr (NW * 16 * Vec<TV>::EPL <= 512) return occ_q<TV, TX, NW, 16>(pref);

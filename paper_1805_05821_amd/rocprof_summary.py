@@ -132,10 +132,10 @@ def _copy_value(d, counter):
 
 
 def _row_pass_avg(d, counter):
+    """Average per launch of the FP32-basis row passes (the form the record describes)."""
     per = counter_per_dispatch(d, counter)
-    v = sum(x for name, (x, n) in per.items() if is_row_pass(name))
-    n = sum(n for name, (x, n) in per.items() if is_row_pass(name))
-    return v / max(n, 1), n
+    sel = [(x, n) for name, (x, n) in per.items() if is_row_pass(name) and "k_pass<float" in name]
+    return sum(x for x, _ in sel) / max(sum(n for _, n in sel), 1), sum(n for _, n in sel)
 
 
 def _prefix_avg(d, counter, prefix):
