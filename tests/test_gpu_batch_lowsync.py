@@ -261,3 +261,56 @@ def test_flush_midway_then_continue():
         announce(f"stream {s}: q={qv} kappa={kap:.1e} relH={eH:.1e} relB={eB:.1e}")
         assert max(eH, eB) <= 10 * qv * EPS64 * kap
     bt.close()
+
+
+def test_shared_table_bitwise_and_reset_replay(tmp_path):
+    """Two one-reduction batches with the same launch configuration (the second
+    reads the first's entry in the tuning table, key with "/form1") give
+    bitwise-equal H_bar, beta and basis; a reset followed by the same pushes
+    replays the captured step graphs and reproduces the first run bitwise."""
+    import torch
+
+    from paper_1805_05821_amd import foa as F
+    from paper_1805_05821_amd.stream import FOABatch
+
+    Xs = [X.astype(np.float32) for X in _mixed()[1:5]]
+    S = len(Xs)
+    n = [X.shape[0] for X in Xs]
+    N = [X.shape[1] for X in Xs]
+    Xd = [torch.from_numpy(np.ascontiguousarray(X.T)).cuda() for X in Xs]
+    T = max(N)
+    ptr = np.zeros((T, S), dtype=np.int64)
+    for s in range(S):
+        for t in range(N[s]):
+            ptr[t, s] = Xd[s][t].data_ptr()
+    dptr = torch.from_numpy(ptr).cuda()
+    table = str(tmp_path / "tune.json")
+
+    def run(bt):
+        for t in range(T):
+            bt.push_ptrs(dptr[t], F.FOA_F32)
+        q, st = bt.sync()
+        out = []
+        for s in range(S):
+            v = bt.view(s)
+            H, B, qv, m = F.foa_get_state(v)
+            V = torch.empty((qv, n[s]), dtype=torch.float64, device="cuda")
+            F.foa_copy_basis(v, V, n[s], F.FOA_F64, qv)
+            out.append((qv, H, B, V.cpu().numpy()))
+        return q, st, out
+
+    a = FOABatch(n, N, prec="f32", form="one_reduction", tune_table=table)
+    qa, sa, ra = run(a)
+    b = FOABatch(n, N, prec="f32", form="one_reduction", tune_table=table)
+    qb, sb, rb = run(b)
+    a.reset()
+    qc, sc, rc = run(a)
+    assert np.array_equal(qa, np.array(N)) and np.all(sa == 0)
+    for s in range(S):
+        for other in (rb[s], rc[s]):
+            assert other[0] == ra[s][0]
+            for x, y in zip(ra[s][1:], other[1:]):
+                assert np.array_equal(x, y), s
+    announce(f"{S} streams: shared table and reset replay bitwise equal")
+    a.close()
+    b.close()
