@@ -35,6 +35,21 @@ sigma_c = 1 / ||column_c||.  With storage="f32" every stored column is
 rounded to float32 (all arithmetic stays float64), the precision form of the
 library's FP32 basis.
 
+Non-orthogonality of the stored basis.  A stored column is rounded after it
+is orthogonalised, so the final columns are orthonormal only up to
+E = Q^T Q - I (entries of order eps32 / sqrt(n) with an FP32 basis).  Two
+projections that treat Q as orthonormal leave components of order ||E|| ||x||
+along Q; once that reaches the residual of a new snapshot (snapshots near the
+noise floor of the data, small n) the error compounds from column to column.
+The second projection (the reorthogonalisation) therefore uses the
+coefficients (I - E) w in place of w: the projector Q (I - E) Q^T differs from
+the orthogonal projector onto span(Q) by O(||E||^2), so the column it leaves
+is orthogonal to the stored basis to O(||E||^2) whatever the first projection
+left.  E gains a column when a column becomes final: its inner products with
+the earlier final columns, from the same sweep's column sums.  With an FP64
+basis E is of order eps64 and the correction changes results at rounding
+level only.
+
 Breakdown (the reading of the exact-arithmetic condition h_{j+1,j} = 0 used
 for the sequential form): column c is dependent when its exact norm
 beta_{c,c} <= tol ||X_1^c||_F.  The stream then becomes invariant with the c-1
@@ -82,13 +97,15 @@ class LowSyncState:
     gamma: float = 0.0
     pushes: int = 0
     sweeps: int = 0
+    E: np.ndarray = None          # Q^T Q - I of the final columns (cap x cap)
+    w_hat: np.ndarray = None      # (I - E) w, the second-projection coefficients used
 
 
 def init(n, capacity, tol=None, storage="f64") -> LowSyncState:
     tol = default_breakdown_tol(capacity) if tol is None or tol < 0 else float(tol)
     return LowSyncState(V=np.zeros((n, capacity + 2), order="F"), H=np.zeros((capacity, capacity), order="F"),
                         beta=np.zeros((capacity, capacity), order="F"), sigma=np.zeros(capacity + 2),
-                        storage=storage, tol=tol)
+                        storage=storage, tol=tol, E=np.zeros((capacity, capacity)))
 
 
 def _store(st, v):
@@ -110,17 +127,18 @@ def _sweep(st, x):
     q = st.q
     Q = st.V[:, :q] * st.sigma[:q]              # final columns, normalised
     st.sweeps += 1
-    rho_hat = np.sqrt(max(st.alpha - float(st.w @ st.w), 0.0)) if st.has_u else 0.0
+    # ||u - Q w_hat||^2 = ||u||^2 - w^T w_hat + O(||E||^2)
+    rho_hat = np.sqrt(max(st.alpha - float(st.w @ st.w_hat), 0.0)) if st.has_u else 0.0
     # 1. second projection of the pending column (index q)
     if st.has_u:
-        ut = _store(st, st.V[:, q] - Q @ st.w)
+        ut = _store(st, st.V[:, q] - Q @ st.w_hat)
         st.V[:, q] = ut
     # 2. first projection of the pending snapshot copy
     iu = q + (1 if st.has_u else 0)           # where the snapshot copy sits
     if st.has_x:
         r_t = 0.0
         if st.has_u and rho_hat > 0.0:
-            r_t = (st.gamma - float(st.w @ st.z)) / rho_hat
+            r_t = (st.gamma - float(st.w_hat @ st.z)) / rho_hat
         u = st.V[:, iu] - Q @ st.z
         if st.has_u and rho_hat > 0.0:
             u = u - ut * (r_t / rho_hat)    # q_hat R_tilde with q_hat = ut / rho_hat
@@ -135,6 +153,7 @@ def _sweep(st, x):
     # ---- the one reduction: column sums against Q and the pending vectors ----
     if st.has_u:
         nu2 = float(ut @ ut)
+        gq = Q.T @ ut                    # the finished (stored) column against Q
     if st.has_x:
         wq, alpha = Q.T @ u, float(u @ u)
         wu = float(ut @ u) if st.has_u else None
@@ -162,6 +181,7 @@ def _sweep(st, x):
             return
         st.beta[c, c] = rho
         st.sigma[c] = 1.0 / rho
+        st.E[:c, c] = st.E[c, :c] = gq / rho     # E gains the new final column
         if c > 0:
             _hbar_column(st, c)
         st.q = q = c + 1
@@ -176,8 +196,9 @@ def _sweep(st, x):
             wfull = np.append(wfull, wu * st.sigma[k])
             p = np.append(p, (rho / rho_hat) * r_t if rho_hat > 0.0 else 0.0)
         c = st.q                         # 0-based index of this column
-        st.beta[:c, c] = p + wfull
-        st.has_u, st.w, st.alpha = True, wfull, alpha
+        w_hat = wfull - st.E[:c, :c] @ wfull
+        st.beta[:c, c] = p + w_hat       # the coefficients actually subtracted
+        st.has_u, st.w, st.w_hat, st.alpha = True, wfull, w_hat, alpha
         st.has_x = False
     if x is not None:
         zfull = zq.copy()

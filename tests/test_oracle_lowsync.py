@@ -85,6 +85,29 @@ def pin_ls_orthogonality(L):
     return ok, "; ".join(msgs)
 
 
+def pin_ls_noise_floor_f32(L):
+    """FP32 storage where new snapshots lie at the noise floor of the data and
+    the stored basis is far from orthonormal at working precision (the
+    noisy_2p24x500 recipe at n = 5000, N = 384: 240 signal directions, then
+    residuals of ~1e-8 ||x||, against an ||I - Q^T Q|| of a few 1e-8 from the
+    rounding of the stored columns): orthogonality and factorisation stay at
+    10 sqrt(q) eps32 (eqs. qrfactorth, errorinfact), and beta is the
+    factorisation of the snapshots.  Without the Gram correction of the
+    second projection the basis loses orthogonality entirely here."""
+    w = datagen.get_workload("noisy_2p24x500").with_n(5000).with_N(384)
+    X, _, _ = datagen.snapshots_numpy(w, dtype="float64")
+    st = L.run(X, storage="f32")
+    q = st.q
+    V = L.basis(st)
+    if not (np.all(np.isfinite(V)) and np.all(np.isfinite(st.beta[:q, :q]))):
+        return False, f"q={q}: non-finite basis or beta"
+    e = np.linalg.norm(np.eye(q) - V.T @ V, 2)
+    r = np.linalg.norm(X[:, :q] - V @ st.beta[:q, :q]) / np.linalg.norm(X[:, :q])
+    b = 10 * np.sqrt(q) * EPS32
+    return (q == X.shape[1] and e <= b and r <= b,
+            f"q={q} ||I-V^TV||={e:.1e}, factorisation {r:.1e} (bound {b:.1e})")
+
+
 def pin_ls_factorisation(L):
     """||X - V beta||_F / ||X||_F <= 10 sqrt(q) eps of the storage precision
     (eq. errorinfact's leading term) at kappa_2 ~ 1e9."""
@@ -191,8 +214,8 @@ def pin_ls_one_sweep(L):
 
 
 LS_PINS = [pin_ls_householder_qr, pin_ls_vs_sequential, pin_ls_orthogonality, pin_ls_factorisation,
-           pin_ls_shift_relation, pin_ls_exact_rank, pin_ls_nonfinite_and_zero, pin_ls_flush_midway,
-           pin_ls_one_sweep]
+           pin_ls_noise_floor_f32, pin_ls_shift_relation, pin_ls_exact_rank, pin_ls_nonfinite_and_zero,
+           pin_ls_flush_midway, pin_ls_one_sweep]
 
 
 def run_all(L):
@@ -236,8 +259,12 @@ def _mutant(edit):
 # mutant of the sequential oracle).
 LS_MUTANTS = {
     "first_projection_skips_last_column": ("u = u - ut * (r_t / rho_hat)", "u = u"),
-    "second_projection_sign": ("ut = _store(st, st.V[:, q] - Q @ st.w)", "ut = _store(st, st.V[:, q] + Q @ st.w)"),
-    "gamma_without_w_z_term": ("(st.gamma - float(st.w @ st.z)) / rho_hat", "st.gamma / rho_hat"),
+    "second_projection_sign": ("ut = _store(st, st.V[:, q] - Q @ st.w_hat)",
+                               "ut = _store(st, st.V[:, q] + Q @ st.w_hat)"),
+    "gamma_without_w_z_term": ("(st.gamma - float(st.w_hat @ st.z)) / rho_hat", "st.gamma / rho_hat"),
+    "second_projection_ignores_gram": ("w_hat = wfull - st.E[:c, :c] @ wfull", "w_hat = wfull"),
+    "gram_column_unscaled": ("st.E[:c, c] = st.E[c, :c] = gq / rho", "st.E[:c, c] = st.E[c, :c] = gq"),
+    "gram_column_sign": ("st.E[:c, c] = st.E[c, :c] = gq / rho", "st.E[:c, c] = st.E[c, :c] = -gq / rho"),
     "hbar_divides_by_new_diagonal": ("st.H[:c + 1, c - 1] = col / st.beta[c - 1, c - 1]",
                                      "st.H[:c + 1, c - 1] = col / st.beta[c, c]"),
     "w_last_entry_unscaled": ("wfull = np.append(wfull, wu * st.sigma[k])", "wfull = np.append(wfull, wu)"),
