@@ -568,6 +568,12 @@ static hipError_t launch_bpass_q(int qw, int grid, const BlockArgs &a, hipStream
     case 2: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 2, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
     case 4: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 4, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
     case 8: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 8, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 12:
+      if constexpr (sizeof(TV) == 4 && NW == 8) {
+        hipLaunchKernelGGL((k_bpass<TV, TX, NW, 12, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
     default:
       if constexpr (NW * 16 * Vec<TV>::EPL <= 512)
         hipLaunchKernelGGL((k_bpass<TV, TX, NW, 16, MODE, false>), dim3(grid), dim3(NT), 0, s, a);
@@ -578,10 +584,11 @@ static hipError_t launch_bpass_q(int qw, int grid, const BlockArgs &a, hipStream
   return hipGetLastError();
 }
 
-// Prefetch only where the doubled tile fits beside the BPK accumulators.
+// Prefetch only where the doubled tile fits beside the BPK accumulators (the
+// 12-group tile: not in BP_Z1, whose phase-1 values spill with it).
 template <typename TV, typename TX, int NW>
 static hipError_t launch_bpass_m(int mode, int qw, int grid, const BlockArgs &a, hipStream_t s) {
-  const bool pref = sizeof(TV) == 4 ? qw <= 8 : qw <= 4;
+  const bool pref = sizeof(TV) == 4 ? (qw <= 8 || (qw == 12 && mode != BP_Z1)) : qw <= 4;
   if (!block_supported(sizeof(TV) == 8, qw)) return hipErrorInvalidValue;
   switch (mode) {
     case BP_R1:

@@ -89,7 +89,7 @@ def test_blocked_f64_matches_blocked_oracle(n, N):
 @pytest.mark.parametrize("N", [61, 300])
 def test_blocked_f32_within_bound(N):
     """FP32 basis: ||H32 - H64|| <= 10 eps32 kappa and orthogonality; N = 300
-    reaches the widest column tile."""
+    reaches the 12-group column tile (257-384 columns)."""
     X = _noisy(5000, N, "noisy_2p24x500")
     g = _run_blocked(X, "f32")
     seq = oracle.foa_batch(X)
