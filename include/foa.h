@@ -113,7 +113,10 @@ typedef enum {
  * reduction (delayed reorthogonalisation, Bielich et al., Parallel Computing
  * 2022) instead of the three of Algorithm 1 (the message count of Section
  * 3.2.5).  Same factors in exact arithmetic, rounding of the same
- * O(eps kappa_2) order.  A column becomes final two pushes after its
+ * O(eps kappa_2) order.  With an FP32 basis the second projection is taken
+ * against the stored basis's own Gram matrix (V^T V = I + E, E kept from the
+ * rounding error of each finished column), which keeps the basis orthogonal
+ * when a snapshot's new direction is as small as that rounding.  A column becomes final two pushes after its
  * snapshot: every synchronising call (foa_sync and the calls returning host
  * data) first finishes the pending columns (up to two sweeps; foa_flush does
  * this stream-ordered), and a dependent snapshot is found when its column

@@ -64,10 +64,17 @@ Layout make_layout(int64_t n, int n_max, foa_prec prec, int ldg) {
   // mode coefficients: FP64 k x r, or the padded FP32 layout of the MFMA path
   L.mcoef = take(std::max((size_t)n_max * n_max * 8, (size_t)modes_kpad(n_max) * modes_rpad(n_max) * 4));
   // one-reduction form: second partial-sum array (with the scalar rows), the
-  // reduced sums and the prefix sums of the snapshot norms
+  // reduced sums and the prefix sums of the snapshot norms; with an FP32
+  // basis also the partial sums of the finished column's rounding error, the
+  // Gram deviation E of the final columns and the corrected coefficients
   L.ls_part1 = take((size_t)(n_max + LS_NSC) * L.ldg * 8);
-  L.ls_red = take((size_t)(2 * n_max + LS_NSC) * 8);
+  L.ls_red = take((size_t)(3 * n_max + LS_NSC) * 8);
   L.ls_xpre = take((size_t)(n_max + 1) * 8);
+  L.ls_what = take((size_t)(n_max + 1) * 8);
+  if (prec == FOA_PREC_F32) {
+    L.ls_part2 = take((size_t)n_max * L.ldg * 8);
+    L.ls_E = take((size_t)n_max * n_max * 8);
+  }
   L.total = off;
   return L;
 }

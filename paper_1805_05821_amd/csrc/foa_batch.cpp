@@ -145,6 +145,14 @@ foa_status upload_config(foa_batch_s *b, int unit_panels) {
     d.part1 = reinterpret_cast<double *>(static_cast<char *>(v->ws) + v->L.ls_part1);
     d.red = reinterpret_cast<double *>(static_cast<char *>(v->ws) + v->L.ls_red);
     d.xpre = reinterpret_cast<double *>(static_cast<char *>(v->ws) + v->L.ls_xpre);
+    d.what = reinterpret_cast<double *>(static_cast<char *>(v->ws) + v->L.ls_what);
+    if (v->prec == FOA_PREC_F32) {
+      d.part2 = reinterpret_cast<double *>(static_cast<char *>(v->ws) + v->L.ls_part2);
+      d.E = reinterpret_cast<double *>(static_cast<char *>(v->ws) + v->L.ls_E);
+    } else {
+      d.part2 = nullptr;
+      d.E = nullptr;
+    }
     d.n = v->n;
     d.P = v->L.P;
     d.n_max = v->n_max;

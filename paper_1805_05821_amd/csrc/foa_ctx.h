@@ -20,6 +20,7 @@ struct Layout {
   size_t W = 0, w = 0, part = 0, partn = 0, H = 0, beta = 0, sigma = 0, bvec = 0, h = 0, s = 0;
   size_t coefA = 0, coefB = 0, coefC = 0, st = 0, mcoef = 0;
   size_t ls_part1 = 0, ls_red = 0, ls_xpre = 0;  // one-reduction form
+  size_t ls_part2 = 0, ls_E = 0, ls_what = 0;     // one-reduction form, FP32 basis
   size_t total = 0;
 };
 

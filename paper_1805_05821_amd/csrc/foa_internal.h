@@ -100,6 +100,7 @@ struct BatchStream {
   DevState *st;
   double *H, *beta, *sigma, *bvec, *h, *s, *coefA, *coefB, *coefC;
   double *part1, *red, *xpre;  // one-reduction form
+  double *part2, *E, *what;    // one-reduction form, FP32 basis: the Gram correction
   int64_t n, P;
   int n_max, ldg, ldH, ldB;
 };
@@ -202,6 +203,7 @@ struct LsArgs {
   const double *coefZ;   // sigma o z (first projection of the pending snapshot)
   const DevState *st;
   double *part0, *part1;
+  double *part2;         // FP32 basis: the finished column's rounding error against each column
   int64_t n, P;
   int n_max, ldg;
   int flush;             // 1: no new snapshot
@@ -211,14 +213,18 @@ struct LsSmall {
   double *H, *beta, *sigma;
   double *w, *z;         // pending coefficient vectors (FP64, unscaled)
   double *coefW, *coefZ; // sigma-scaled copies for the next sweep
-  double *red;           // reduced sums: [0, n_max) part0 columns, [n_max, 2 n_max) part1, then LS_NSC scalars
+  double *red;           // reduced sums: [0, n_max) part0 columns, [n_max, 2 n_max) part1, then LS_NSC
+                         // scalars, then (FP32 basis) [2 n_max + LS_NSC, 3 n_max + LS_NSC) part2 columns
   double *bvec;          // H_bar product of the column the finalize finishes
   double *xpre;          // prefix sums of ||x_i||^2 of the accepted snapshots
-  const double *part0, *part1;
+  double *E;             // FP32 basis: Q^T Q - I of the final columns (n_max x n_max, column-major)
+  double *what;          // E w for the new pending column (from k_ls_hprod), then (I - E) w
+  const double *part0, *part1, *part2;
   int ldH, ldB, n_max, ldg;
   int G;                 // partial slots written by the sweep
   int nt;                // host's expectation of q (upper bound of the device's)
   int flush;
+  int gram;              // 1: FP32 basis, the second projection uses (I - E) w
 };
 
 // ---- launchers (defined in foa_kernels.hip) --------------------------------

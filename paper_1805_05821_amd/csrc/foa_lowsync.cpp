@@ -38,6 +38,12 @@ LsSmall ls_small(foa_ctx_s *c, int G, bool flush) {
   a.xpre = reinterpret_cast<double *>(b + c->L.ls_xpre);
   a.part0 = c->part;
   a.part1 = reinterpret_cast<double *>(b + c->L.ls_part1);
+  a.what = reinterpret_cast<double *>(b + c->L.ls_what);
+  if (c->prec == FOA_PREC_F32) {
+    a.gram = 1;
+    a.part2 = reinterpret_cast<double *>(b + c->L.ls_part2);
+    a.E = reinterpret_cast<double *>(b + c->L.ls_E);
+  }
   a.ldH = c->L.ldH;
   a.ldB = c->L.ldB;
   a.n_max = c->n_max;
@@ -81,6 +87,7 @@ foa_status enqueue_ls_sweep(foa_ctx_s *c, const void *x, bool x64) {
   a.st = c->sa.st;
   a.part0 = c->part;
   a.part1 = reinterpret_cast<double *>(static_cast<char *>(c->ws) + c->L.ls_part1);
+  if (c->prec == FOA_PREC_F32) a.part2 = reinterpret_cast<double *>(static_cast<char *>(c->ws) + c->L.ls_part2);
   a.n = c->n;
   a.P = c->L.P;
   a.n_max = c->n_max;

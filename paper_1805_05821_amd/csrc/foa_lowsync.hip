@@ -45,16 +45,43 @@ namespace foa {
 // Tile: the q final columns of a panel (lane layout of row_pass_body).  The
 // pending columns and the snapshot are read per update row.
 // ---------------------------------------------------------------------------
+#ifndef LS_PF16
+#define LS_PF16 8
+#endif
+#ifndef LS_PF8
+#define LS_PF8 4
+#endif
+
 template <typename TV, int NW, int QW>
 constexpr int ls_lds_doubles() {
   constexpr int JCAP = QW * NW * Vec<TV>::EPL;
-  return 2 * JCAP + 2 * 2 * NW * PANEL + 2 * PANEL + NW * LS_NSC;
+  return 2 * JCAP + 2 * 2 * NW * PANEL + 3 * PANEL + NW * LS_NSC;
+}
+
+// Groups of the next panel's tile loaded ahead (the prefetch): all of them,
+// except for the FP32 16-group tile, where the Gram sums leave room for 8 (a
+// full prefetch spills).  The other groups load at the start of their panel.
+template <typename TV, int NW, int QW>
+constexpr int ls_pf() {
+  return sizeof(TV) == 4 && QW == 16 ? LS_PF16 : (sizeof(TV) == 4 && QW == 8 && NW < 8 ? LS_PF8 : QW);
+}
+
+// Groups [G0, G1) of a tile (16-byte loads, one per group and lane) into
+// dst[D0 + g - G0].
+template <typename TV, int G0, int G1, int D0, int D>
+__device__ __forceinline__ void ls_load_groups(__amdgpu_buffer_rsrc_t rt, unsigned goff0, unsigned gbytes,
+                                               TV (&dst)[D][Vec<TV>::EPL]) {
+#pragma unroll
+  for (int g = G0; g < G1; ++g) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rt, (int)(goff0 + g * gbytes), 0, kTileLoad);
+    unpack16<TV>(v, dst[D0 + g - G0]);
+  }
 }
 
 // One workgroup processes panels pstart, pstart + pstep, ... < pend of one
 // stream and writes its partial sums to slot `slot`.  Called uniformly by the
 // whole workgroup (it synchronises).
-template <typename TV, typename TX, int NW, int QW, bool PREF>
+template <typename TV, typename TX, int NW, int QW, int PF>
 __device__ __forceinline__ void ls_pass_body(const LsArgs &a, int64_t pstart, int64_t pend, int64_t pstep,
                                              int slot, double *lds) {
 #pragma clang fp contract(off)
@@ -69,7 +96,13 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, int64_t pstart, in
   double (*s_red)[2][NW][PANEL] = reinterpret_cast<double (*)[2][NW][PANEL]>(lds + 2 * JCAP);
   double *s_u = lds + 2 * JCAP + 4 * NW * PANEL;
   double *s_x = s_u + PANEL;
-  double (*s_sc)[LS_NSC] = reinterpret_cast<double (*)[LS_NSC]>(s_x + PANEL);
+  float *s_d = reinterpret_cast<float *>(s_x + PANEL);  // rounding error of the finished column
+  double (*s_sc)[LS_NSC] = reinterpret_cast<double (*)[LS_NSC]>(s_x + 2 * PANEL);
+  // FP32 basis: the finished column's inner products with the final columns
+  // (the Gram correction of the second projection) need the sums of its
+  // rounding error against the tile; FP32 accumulation of those tiny values
+  // suffices for a correction.  An FP64 basis needs none.
+  constexpr bool GRAM = sizeof(TV) == 4;
 
   const DevState *st = a.st;
   const int tid = threadIdx.x;
@@ -106,8 +139,11 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, int64_t pstart, in
   const unsigned ocn = (uact && hn) ? (unsigned)((cn * PANEL + urow) * sizeof(TV)) : kOOR;
 
   double acc0[QW], acc1[QW];
+  float acc2[GRAM ? QW : 1];
 #pragma unroll
   for (int g = 0; g < QW; ++g) acc0[g] = acc1[g] = 0.0;
+#pragma unroll
+  for (int g = 0; g < (GRAM ? QW : 1); ++g) acc2[g] = 0.f;
   double sc[LS_NSC];
 #pragma unroll
   for (int k = 0; k < LS_NSC; ++k) sc[k] = 0.0;
@@ -115,21 +151,13 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, int64_t pstart, in
   char *Wb = static_cast<char *>(a.W);
   const size_t pbytes = (size_t)a.n_max * PANEL * sizeof(TV);
   TV t[QW][EPL];
-  TV tn[QW][EPL];
-  auto load_tile = [&](int64_t p, TV (&dst)[QW][EPL], unsigned bytes) {
-    const __amdgpu_buffer_rsrc_t rt = make_rsrc(Wb + (size_t)p * pbytes, bytes);
-#pragma unroll
-    for (int g = 0; g < QW; ++g) {
-      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rt, (int)(goff0 + g * GBYTES), 0, kTileLoad);
-      unpack16<TV>(v, dst[g]);
-    }
-  };
+  TV tn[PF > 0 ? PF : 1][EPL];
 
   int64_t p = pstart;
-  if (PREF && p < pend) {
-    load_tile(p, t, tile_bytes);
+  if (PF > 0 && p < pend) {
+    ls_load_groups<TV, 0, PF, 0>(make_rsrc(Wb + (size_t)p * pbytes, tile_bytes), goff0, GBYTES, t);
 #pragma unroll
-    for (int g = 0; g < QW; ++g) {
+    for (int g = 0; g < PF; ++g) {
 #pragma unroll
       for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(t[g][e]));
     }
@@ -148,11 +176,14 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, int64_t pstart, in
       const __amdgpu_buffer_rsrc_t rx = make_rsrc(static_cast<const TX *>(a.x) + (hn ? p * PANEL : 0), xb);
       xv = buf_load_scalar<TX>(rx, uact ? (unsigned)(urow * sizeof(TX)) : kOOR);
     }
-    if (PREF) {
+    if constexpr (PF < QW) {
+      // the groups not prefetched, straight into their place
+      ls_load_groups<TV, PF, QW, PF>(make_rsrc(Wb + (size_t)p * pbytes, tile_bytes), goff0, GBYTES, t);
+    }
+    if constexpr (PF > 0) {
       const bool more = p + pstep < pend;
-      load_tile(more ? p + pstep : p, tn, more ? tile_bytes : 0u);
-    } else {
-      load_tile(p, t, tile_bytes);
+      ls_load_groups<TV, 0, PF, 0>(make_rsrc(Wb + (size_t)(more ? p + pstep : p) * pbytes, more ? tile_bytes : 0u),
+                                   goff0, GBYTES, tn);
     }
 
     // phase 1: row sums of the tile against sigma o w and sigma o z
@@ -214,14 +245,17 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, int64_t pstart, in
       sc[LS_XX] = fma(xv, xv, sc[LS_XX]);
       s_u[urow] = uf;
       s_x[urow] = xs;
+      if constexpr (GRAM) s_d[urow] = (float)(ut - (yu - sw));
     }
     __syncthreads();
     // phase 2: column sums of the tile against the formed column and the snapshot
     double wu[EPL], wx[EPL];
+    float wd[EPL];
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
       wu[e] = s_u[rg * EPL + e];
       wx[e] = s_x[rg * EPL + e];
+      wd[e] = GRAM ? s_d[rg * EPL + e] : 0.f;
     }
     if constexpr (sizeof(TV) == 4) {
 #pragma unroll
@@ -239,14 +273,20 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, int64_t pstart, in
         acc1[g] = fma(tv, wx[e], acc1[g]);
       }
     }
-    if (PREF) {
+    if constexpr (GRAM) {
 #pragma unroll
-      for (int g = 0; g < QW; ++g) {
+      for (int g = 0; g < QW; ++g)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) acc2[g] = fmaf((float)t[g][e], wd[e], acc2[g]);
+    }
+    if constexpr (PF > 0) {
+#pragma unroll
+      for (int g = 0; g < PF; ++g) {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(tn[g][e]));
       }
 #pragma unroll
-      for (int g = 0; g < QW; ++g) {
+      for (int g = 0; g < PF; ++g) {
 #pragma unroll
         for (int e = 0; e < EPL; ++e) t[g][e] = tn[g][e];
       }
@@ -266,6 +306,12 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, int64_t pstart, in
     if (rg == 0 && c < q) {
       a.part0[(size_t)c * a.ldg + slot] = v0;
       a.part1[(size_t)c * a.ldg + slot] = v1;
+    }
+    if constexpr (GRAM) {
+      float v2 = acc2[g];
+#pragma unroll
+      for (int m = 1; m < LPC; m <<= 1) v2 += __shfl_xor(v2, m);
+      if (rg == 0 && c < q) a.part2[(size_t)c * a.ldg + slot] = (double)v2;
     }
   }
 #pragma unroll
@@ -292,19 +338,23 @@ __device__ __forceinline__ bool ls_runs(const DevState *st, int flush) {
 
 // Register budget as waves per SIMD: tiles of up to 4 groups fit 128 VGPRs,
 // 6 and 8 groups 168, 12 and 16 groups 256 (two right-hand sides of FP64
-// accumulators plus the current and the prefetched tile).
+// accumulators, the FP32 basis's Gram sums, the current and the prefetched
+// tile; the FP32 16-group tile prefetches half of its groups).
 template <typename TV, int NW, int QW>
 constexpr int ls_waves() {
-  return (NW == 16 || QW <= 4) ? 4 : (QW <= 8 ? 3 : 2);
+  // an 8-wavefront workgroup keeps one workgroup per CU at 2 or 3 waves per
+  // SIMD, so 8-wavefront tiles of 8 groups take the larger budget (no spill of
+  // the FP32 basis's Gram sums)
+  return (NW == 16 || QW <= 4) ? 4 : ((QW <= 8 && NW < 8) || QW == 6 ? 3 : 2);
 }
 
-template <typename TV, typename TX, int NW, int QW, bool PREF>
+template <typename TV, typename TX, int NW, int QW>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(ls_waves<TV, NW, QW>()))) void k_ls_pass(
     LsArgs a) {
   if (!ls_runs(a.st, a.flush)) return;
   if (a.flush && !a.st->ls_u && !a.st->ls_x) return;
   __shared__ double lds[ls_lds_doubles<TV, NW, QW>()];
-  ls_pass_body<TV, TX, NW, QW, PREF>(a, blockIdx.x, a.P, gridDim.x, blockIdx.x, lds);
+  ls_pass_body<TV, TX, NW, QW, ls_pf<TV, NW, QW>()>(a, blockIdx.x, a.P, gridDim.x, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -329,6 +379,11 @@ __device__ inline void ls_reduce_body(const LsSmall &a, int vblock) {
   } else if (v < 2 * a.nt + LS_NSC) {
     src = a.part1 + (size_t)(a.n_max + v - 2 * a.nt) * a.ldg;
     out = 2 * a.n_max + (v - 2 * a.nt);
+  } else if (a.gram && v < 3 * a.nt + LS_NSC) {
+    const int c = v - 2 * a.nt - LS_NSC;
+    if (c >= q || !a.st->ls_u) return;
+    src = a.part2 + (size_t)c * a.ldg;
+    out = 2 * a.n_max + LS_NSC + c;
   } else {
     return;
   }
@@ -391,9 +446,41 @@ __device__ inline void ls_hprod_body(const LsSmall &a, int rblock) {
   if (sl == 0 && i < c) a.bvec[i] = ((sh[0][r] + sh[1][r]) + sh[2][r]) + sh[3][r];
 }
 
+// FP32 basis: E w over the earlier final columns for the column that the
+// coming finalize makes pending (w_l = sigma_l * its reduced sum l, l < q):
+// the same 64 rows x 4 slices, E symmetric with a zero diagonal.  The terms of
+// the column finished in the same sweep are added by the finalize.
+__device__ inline void ls_ew_body(const LsSmall &a, int rblock) {
+  __shared__ double sh[4][64];
+  const DevState *st = a.st;
+  const int c = st->q;
+  const int r = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int i = rblock * 64 + r;
+  double t = 0.0;
+  if (i < c) {
+    const int a0 = (c * sl) / 4, a1 = (c * (sl + 1)) / 4;
+    const double *Ei = a.E + i;  // row i (= column i)
+    double t4[4] = {0.0, 0.0, 0.0, 0.0};
+    int l = a0;
+    for (; l + 4 <= a1; l += 4) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t4[k] = fma(Ei[(size_t)(l + k) * a.n_max], a.red[l + k] * a.sigma[l + k], t4[k]);
+    }
+    for (; l < a1; ++l) t4[0] = fma(Ei[(size_t)l * a.n_max], a.red[l] * a.sigma[l], t4[0]);
+    t = (t4[0] + t4[1]) + (t4[2] + t4[3]);
+  }
+  sh[sl][r] = t;
+  __syncthreads();
+  if (sl == 0 && i < c) a.what[i] = ((sh[0][r] + sh[1][r]) + sh[2][r]) + sh[3][r];
+}
+
 __global__ __launch_bounds__(256) void k_ls_hprod(LsSmall a) {
-  if (!ls_runs(a.st, a.flush) || !a.st->ls_u) return;
-  ls_hprod_body(a, blockIdx.x);
+  if (!ls_runs(a.st, a.flush)) return;
+  if (a.st->ls_u) ls_hprod_body(a, blockIdx.x);
+  if (a.gram && a.st->ls_x) {
+    __syncthreads();
+    ls_ew_body(a, blockIdx.x);
+  }
 }
 
 // H_bar's column c-1 once beta's column c is final: h = (beta_{0:c,c} -
@@ -468,6 +555,17 @@ __device__ inline void ls_finalize_body(const LsSmall &a) {
       a.beta[(size_t)q0 * a.ldB + q0] = rho;
       a.sigma[q0] = 1.0 / rho;
     }
+    if (a.gram) {
+      // E's new column: q_i^T q_q0 = sigma_i (stored_i^T delta) / rho, delta the
+      // rounding error of the stored column (the rest is O(||E||^2))
+      const double *red2 = a.red + 2 * a.n_max + LS_NSC;
+      for (int i = tid; i < q0; i += NT) {
+        const double g = a.sigma[i] * red2[i] / rho;
+        a.E[(size_t)q0 * a.n_max + i] = g;
+        a.E[(size_t)i * a.n_max + q0] = g;
+      }
+      if (tid == 0) a.E[(size_t)q0 * a.n_max + q0] = 0.0;
+    }
     __syncthreads();
     if (q0 > 0) ls_hbar_column<NT>(a, q0);
     q = q0 + 1;
@@ -479,18 +577,31 @@ __device__ inline void ls_finalize_body(const LsSmall &a) {
   if (hf) {
     const int c = q;  // 0-based index of the new pending column
     const double sk = hu ? a.sigma[q0] : 0.0;
+    // FP32 basis: E w.  k_ls_hprod left the part over the earlier final
+    // columns in what[0, q0); the finished column q0 adds w_q0 E[i, q0] to
+    // rows i < q0 and the whole row q0, sum_l E[q0, l] w_l.
+    double eq0 = 0.0;
+    if (a.gram && hu) {
+      double t = 0.0;
+      for (int l = tid; l < q0; l += NT) t = fma(a.E[(size_t)q0 * a.n_max + l], red0[l] * a.sigma[l], t);
+      eq0 = ls_block_sum<NT>(t, sh);
+    }
     for (int i = tid; i < c; i += NT) {
-      double wi, pi;
+      double wi, pi, ewi = 0.0;
       if (i < q0) {
         wi = red0[i] * a.sigma[i];
         pi = a.z[i];
+        if (a.gram) ewi = a.what[i] + (hu ? a.E[(size_t)q0 * a.n_max + i] * (sc[LS_UF] * sk) : 0.0);
       } else {  // i == q0: the column finished in this sweep
         wi = sc[LS_UF] * sk;
         pi = rhohat0 > 0.0 ? (rho / rhohat0) * rt0 : 0.0;
+        ewi = eq0;
       }
-      a.beta[(size_t)c * a.ldB + i] = pi + wi;
+      const double wh = wi - ewi;  // the second-projection coefficient used
+      a.beta[(size_t)c * a.ldB + i] = pi + wh;
       a.w[i] = wi;
-      a.coefW[i] = a.sigma[i] * wi;
+      a.what[i] = wh;
+      a.coefW[i] = a.sigma[i] * wh;
     }
     alpha = sc[LS_FF];
   }
@@ -510,10 +621,12 @@ __device__ inline void ls_finalize_body(const LsSmall &a) {
   const int nx = hn ? 1 : 0;
   double wz = 0.0;
   if (nu) {
+    // ||u - Q w_hat||^2 = ||u||^2 - w^T w_hat and the R_tilde identity with
+    // w_hat (w_hat = w with an FP64 basis)
     double t = 0.0, t2 = 0.0;
     for (int i = tid; i < q; i += NT) {
-      t = fma(a.w[i], a.w[i], t);
-      if (nx) t2 = fma(a.w[i], a.z[i], t2);
+      t = fma(a.w[i], a.what[i], t);
+      if (nx) t2 = fma(a.what[i], a.z[i], t2);
     }
     wn2 = ls_block_sum<NT>(t, sh);
     wz = ls_block_sum<NT>(t2, sh);
@@ -580,25 +693,30 @@ template <typename TV, typename TX, int NW>
 static hipError_t launch_ls_q(int qw, int grid, const LsArgs &a, hipStream_t s) {
   constexpr int NT = NW * 64;
   switch (qw) {
-    case 1: hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 1, true>), dim3(grid), dim3(NT), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 2, true>), dim3(grid), dim3(NT), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 4, true>), dim3(grid), dim3(NT), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 8, true>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 1>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 2>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 4>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 8:
+      if constexpr (NW < 16) {  // the 16-wavefront tile covers at most 256 columns with 4 groups
+        hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 8>), dim3(grid), dim3(NT), 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
     case 16:
       if constexpr (NW == 8) {
-        hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 16, true>), dim3(grid), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 16>), dim3(grid), dim3(NT), 0, s, a);
         break;
       }
       return hipErrorInvalidValue;
     case 6:
       if constexpr (NW == 8 && sizeof(TV) == 4) {
-        hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 6, true>), dim3(grid), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 6>), dim3(grid), dim3(NT), 0, s, a);
         break;
       }
       return hipErrorInvalidValue;
     case 12:
       if constexpr (NW == 8 && sizeof(TV) == 4) {
-        hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 12, true>), dim3(grid), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_ls_pass<TV, TX, NW, 12>), dim3(grid), dim3(NT), 0, s, a);
         break;
       }
       return hipErrorInvalidValue;
@@ -622,7 +740,7 @@ hipError_t launch_ls_pass(bool tv_f64, bool tx_f64, int q, int nw_opt, int grid,
 template <typename TV, typename TX, int NW, int QW>
 static int ls_occ_q() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ls_pass<TV, TX, NW, QW, true>),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ls_pass<TV, TX, NW, QW>),
                                                    NW * 64, 0) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
@@ -634,7 +752,9 @@ static int ls_occ_m(int qw) {
     case 1: return ls_occ_q<TV, TX, NW, 1>();
     case 2: return ls_occ_q<TV, TX, NW, 2>();
     case 4: return ls_occ_q<TV, TX, NW, 4>();
-    case 8: return ls_occ_q<TV, TX, NW, 8>();
+    case 8:
+      if constexpr (NW < 16) return ls_occ_q<TV, TX, NW, 8>();
+      return 1;
     case 6:
       if constexpr (NW == 8 && sizeof(TV) == 4) return ls_occ_q<TV, TX, NW, 6>();
       return 1;
@@ -656,7 +776,7 @@ int ls_occupancy(bool tv_f64, bool tx_f64, int q, int nw_opt) {
 }
 
 hipError_t launch_ls_reduce(const LsSmall &a, hipStream_t s) {
-  const int waves = 2 * a.nt + LS_NSC;
+  const int waves = (a.gram ? 3 : 2) * a.nt + LS_NSC;
   hipLaunchKernelGGL(k_ls_reduce, dim3((waves + 3) / 4), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -695,6 +815,10 @@ __device__ __forceinline__ LsSmall ls_small_of(const BatchStream &d, int flush) 
   a.xpre = d.xpre;
   a.part0 = d.part;
   a.part1 = d.part1;
+  a.part2 = d.part2;
+  a.E = d.E;
+  a.what = d.what;
+  a.gram = d.E != nullptr ? 1 : 0;
   a.ldH = d.ldH;
   a.ldB = d.ldB;
   a.n_max = d.n_max;
@@ -733,12 +857,13 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(ls_wave
     a.st = st;
     a.part0 = uniform(d.part);
     a.part1 = uniform(d.part1);
+    a.part2 = uniform(d.part2);
     a.n = uniform(d.n);
     a.P = uniform(d.P);
     a.n_max = uniform(d.n_max);
     a.ldg = uniform(d.ldg);
     a.flush = flush;
-    ls_pass_body<TV, TX, NW, QW, true>(a, lo - ps, e - ps, 1, (int)blockIdx.x - uniform(st->seg0), lds);
+    ls_pass_body<TV, TX, NW, QW, ls_pf<TV, NW, QW>()>(a, lo - ps, e - ps, 1, (int)blockIdx.x - uniform(st->seg0), lds);
     lo = e;
     ++i;
   }
@@ -748,15 +873,20 @@ __global__ __launch_bounds__(256) void k_ls_reduce_batch(BatchArgs b) {
   const BatchStream &d = b.streams[blockIdx.y];
   if (!d.st->act) return;
   const LsSmall a = ls_small_of(d, b.ls_mode == 2);
-  if ((int)blockIdx.x * 4 >= 2 * a.nt + LS_NSC) return;
+  if ((int)blockIdx.x * 4 >= (a.gram ? 3 : 2) * a.nt + LS_NSC) return;
   ls_reduce_body(a, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_ls_hprod_batch(BatchArgs b) {
   const BatchStream &d = b.streams[blockIdx.y];
-  if (!d.st->act || !d.st->ls_u) return;
+  const LsSmall a = ls_small_of(d, b.ls_mode == 2);
+  if (!d.st->act || !(d.st->ls_u || (a.gram && d.st->ls_x))) return;
   if ((int)blockIdx.x * 64 >= d.st->q && blockIdx.x > 0) return;
-  ls_hprod_body(ls_small_of(d, b.ls_mode == 2), blockIdx.x);
+  if (d.st->ls_u) ls_hprod_body(a, blockIdx.x);
+  if (a.gram && d.st->ls_x) {
+    __syncthreads();
+    ls_ew_body(a, blockIdx.x);
+  }
 }
 
 __global__ __launch_bounds__(512) void k_ls_finalize_batch(BatchArgs b) {
@@ -831,7 +961,7 @@ hipError_t launch_ls_batch_pass(bool tv_f64, bool tx_f64, int k, int grid, const
 }
 
 hipError_t launch_ls_batch_small(const BatchArgs &b, hipStream_t s) {
-  const int vblocks = (2 * b.max_nmax + LS_NSC + 3) / 4;
+  const int vblocks = (3 * b.max_nmax + LS_NSC + 3) / 4;
   hipLaunchKernelGGL(k_ls_reduce_batch, dim3(vblocks, b.S), dim3(256), 0, s, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

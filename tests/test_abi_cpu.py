@@ -42,10 +42,15 @@ def test_workspace_bytes(F):
     a = F.foa_workspace_bytes(1000, 50, F.FOA_PREC_F64)
     b = F.foa_workspace_bytes(1000, 50, F.FOA_PREC_F32)
     c = F.foa_workspace_bytes(100000, 50, F.FOA_PREC_F32)
-    assert a > b > 0 and c > b
-    # V alone: ceil(n/64)*64 rows x n_max columns
+    d = F.foa_workspace_bytes(100000, 50, F.FOA_PREC_F64)
+    assert a > 0 and b > 0
+    # V alone: ceil(n/64)*64 rows x n_max columns; only V and the FP64 row
+    # vector grow with n
     assert c >= 100032 * 50 * 4
-    assert a % 256 == 0
+    assert c - b >= (100032 - 1024) * (50 * 4 + 8)
+    assert d - c >= (100032 * 50 * 4) - (b - a) - 1024 * 50 * 4
+    assert d > c
+    assert a % 256 == 0 and b % 256 == 0
 
 
 @pytest.mark.parametrize("args", [(0, 10, 0), (10, 0, 0), (10, 513, 0), (10, 10, 7), (-5, 10, 1)])

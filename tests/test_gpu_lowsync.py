@@ -270,3 +270,50 @@ def test_form_rules():
     with pytest.raises(F.FOAError) as e:
         FOAStream(1000, 300, prec="f64", form="one_reduction")
     assert e.value.code == F.FOA_E_ARG
+
+
+@pytest.mark.parametrize("n,N", [(5000, 384), (5000, 500), (20000, 500)])
+def test_f32_noise_floor_gram_correction(n, N):
+    """FP32 basis where new snapshots sit at the data's noise floor and the
+    stored basis is orthonormal only to E = Q^T Q - I of a few 1e-8 (the
+    noisy_2p24x500 recipe at small n): with the Gram-corrected second
+    projection, orthogonality and factorisation stay within 10 sqrt(q) eps32
+    and H_bar within 10 eps32 kappa_2 of the sequential oracle; the single
+    stream and a batch of the same stream agree to that bound."""
+    import torch
+
+    from paper_1805_05821_amd import foa as F
+    from paper_1805_05821_amd.stream import FOABatch
+
+    w = datagen.get_workload("noisy_2p24x500").with_n(n).with_N(N)
+    X, _, _ = datagen.snapshots_numpy(w, dtype="float64")
+    st = oracle.foa_batch(X)
+    g = run_gpu(X, "f32", form="one_reduction")
+    q, m = g["q"], g["m"]
+    assert q == st.q == N
+    V = g["V"]
+    orth = np.linalg.norm(np.eye(q) - V.T @ V, 2)
+    fact = np.linalg.norm(X - V @ g["beta"][:q, :q]) / np.linalg.norm(X)
+    sig = PB.svals(st.beta[:m, :m])
+    kap = sig[0] / sig[-1]
+    eH = np.linalg.norm(g["H"][:m, :m] - st.H[:m, :m], 2) / np.linalg.norm(st.H[:m, :m], 2)
+    b = 10 * np.sqrt(q) * EPS32
+    announce(f"n={n} N={N}: ||I-V^TV||={orth:.2e} factorisation {fact:.2e} (bound {b:.1e}) "
+             f"relH2={eH:.2e} (bound {10 * EPS32 * kap:.1e})")
+    assert orth <= b and fact <= b
+    assert eH <= 10 * EPS32 * kap
+    g["stream"].close()
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+    bt = FOABatch([n], [N], prec="f32", form="one_reduction")
+    for k in range(N):
+        bt.push_ptrs(torch.tensor([Xd[k].data_ptr()], dtype=torch.int64, device="cuda"), F.FOA_F64)
+        torch.cuda.synchronize()
+    qb, sb = bt.sync()
+    view = bt.view(0)
+    Vb = torch.empty((N, n), dtype=torch.float64, device="cuda")
+    F.foa_copy_basis(view, Vb, n, F.FOA_F64, N)
+    Vb = Vb.cpu().numpy().T
+    orth_b = np.linalg.norm(np.eye(N) - Vb.T @ Vb, 2)
+    announce(f"  batched: q={qb[0]} status={sb[0]} ||I-V^TV||={orth_b:.2e}")
+    assert qb[0] == N and sb[0] == 0 and orth_b <= b
+    bt.close()
