@@ -11,13 +11,16 @@ The blocked form reaches the same factors in exact arithmetic, taking the
 snapshots Y = [psi_{q+1} .. psi_{q+p}] of a block together:
 
 1. classical Gram-Schmidt of the whole block against V, twice:
-   R1 = V^T Y, Z = Y - V R1, R2 = V^T Z, Z = Z - V R2;
+   R1 = V^T Y, Z = Y - V R1, R2 = V^T Z, Z = Z - V R2; and a third time,
+   R3 = V^T Z, Z = Z - V R3, when the part of Z still along V after two
+   passes may exceed a tenth of the basis's unit roundoff u_V relative to
+   ||Z_k|| (see third_projection_needed; R = R1 + R2 (+ R3));
 2. the block's own QR, Z = Q S, by one shifted Cholesky QR step followed by
    two plain Cholesky QR steps ("shifted CholeskyQR3": Fukaya, Kannan,
    Nakatsukasa, Yamamoto and Yanagisawa, SIAM J. Sci. Comput. 42 (2020)),
    with the published shift s = 11 (n p + p (p + 1)) u ||Z||_2^2, u = 2^-53,
    and trace(Z^T Z) >= ||Z||_2^2 in its place;
-3. beta's new columns [R1 + R2; S] and V's new columns Q;
+3. beta's new columns [R; S] and V's new columns Q;
 4. H_bar's columns c = q .. q+p-1 (1-based) from the recurrence above solved
    for H_bar_{:,c}: H_bar_{:,c} beta_{c,c} = beta_{:,c+1} - H_bar_{:,1:c-1} beta_{1:c-1,c}.
 
@@ -27,6 +30,16 @@ and the three Cholesky factorisations succeed; otherwise its snapshots are
 taken one at a time by the sequential oracle (foa.py), which applies the
 paper's breakdown and non-finite rules.  The first snapshot (its
 normalisation in Algorithm 1) is always taken by the sequential oracle.
+
+With storage="f32" every stored column of V is rounded to FP32 once it is
+final (the FP32 basis of the device form); all arithmetic stays FP64.  Two
+projections are then not always enough: V^T V = I + E with E of order
+u_32 sqrt(q / n), the part of Z left along V after the passes is about
+E^2 R1, and where the block's new directions are as small as ||E|| ||Y||
+(noise-floor snapshots, small n) that part is of the size of Z itself and
+the basis loses orthogonality block after block.  A third pass multiplies it
+by E once more.  ||E|| is estimated by ||R2||_F / ||R1||_F (R2 = -E R1 up to
+rounding), so the test costs no extra pass over V.
 
 Parity status: pinned against the sequential oracle (the same exact-arithmetic
 factors: tests compare H_bar and beta with foa.foa_batch within O(eps kappa))
@@ -39,6 +52,7 @@ from . import foa
 
 PB = 4          # snapshots per block
 UNIT = 2.0 ** -53
+THIRD_ETA = 0.1  # third projection when the estimated remainder exceeds THIRD_ETA * u_V * ||Z_k||
 
 
 def _chol_upper(G):
@@ -80,10 +94,25 @@ def block_qr(Z):
     return Q, S2 @ S1 @ S0
 
 
-def block_step(st, Y):
-    """One block of p snapshots (columns of Y) on a state with q >= 1.
-    Returns True when the block was committed, False when it was not (the
-    state is then unchanged)."""
+def third_projection_needed(R1, R2, Z, unit):
+    """True when some column of Z (after two projections) may keep a part
+    along V larger than THIRD_ETA * unit * ||Z_k||: that part is about E R2_k,
+    with ||E|| estimated by ||R2||_F / ||R1||_F."""
+    r1 = np.linalg.norm(R1)
+    if not r1 > 0.0:
+        return False
+    e = np.linalg.norm(R2) / r1
+    return bool(np.any(e * np.linalg.norm(R2, axis=0) > THIRD_ETA * unit * np.linalg.norm(Z, axis=0)))
+
+
+def storage_unit(storage):
+    return 2.0 ** -24 if storage == "f32" else UNIT
+
+
+def block_step(st, Y, unit=UNIT):
+    """One block of p snapshots (columns of Y) on a state with q >= 1; unit:
+    the unit roundoff of V's storage.  Returns True when the block was
+    committed, False when it was not (the state is then unchanged)."""
     n, p = Y.shape
     j = st.q
     V = st.V[:, :j]
@@ -94,6 +123,12 @@ def block_step(st, Y):
     Z = Y - V @ R1
     R2 = V.T @ Z
     Z = Z - V @ R2
+    R = R1 + R2
+    third = third_projection_needed(R1, R2, Z, unit)
+    if third:
+        R3 = V.T @ Z
+        Z = Z - V @ R3
+        R = R + R3
     res = block_qr(Z)
     if res is None:
         return False
@@ -102,7 +137,7 @@ def block_step(st, Y):
     if np.any(np.diag(S) <= st.tol * np.sqrt(xf)):
         return False
     beta, H = st.beta, st.H
-    beta[:j, j:j + p] = R1 + R2
+    beta[:j, j:j + p] = R
     beta[j:j + p, j:j + p] = S
     st.V[:, j:j + p] = Q
     for c in range(j - 1, j + p - 1):      # 0-based column of H_bar
@@ -111,23 +146,37 @@ def block_step(st, Y):
     st.xfro2 = float(xf[-1])
     st.q = j + p
     st.pushes += p
+    st.third_projections = getattr(st, "third_projections", 0) + int(third)
     return True
 
 
-def foa_blocked(X, p=PB, tol=None, capacity=None):
-    """The blocked form over X = [psi_1 .. psi_N] (n x N)."""
+def round_new_columns(st, q0, storage):
+    """FP32 storage: round V's columns q0 .. q-1 (final from now on)."""
+    if storage == "f32" and st.q > q0:
+        st.V[:, q0:st.q] = st.V[:, q0:st.q].astype(np.float32).astype(np.float64)
+
+
+def foa_blocked(X, p=PB, tol=None, capacity=None, storage="f64"):
+    """The blocked form over X = [psi_1 .. psi_N] (n x N); storage "f64" or
+    "f32" (V's final columns rounded to FP32)."""
     X = np.asarray(X, dtype=np.float64)
     n, N = X.shape
     cap = N if capacity is None else int(capacity)
+    unit = storage_unit(storage)
     st = foa.foa_stream_init(n, cap, tol)
+    st.third_projections = 0
     foa.foa_stream_update(st, X[:, :1])
+    round_new_columns(st, 0, storage)
     k = 1
     while k < N:
+        q0 = st.q
         if (st.status == foa.ACTIVE and k + p <= N and st.q + p <= cap
-                and block_step(st, np.ascontiguousarray(X[:, k:k + p]))):
+                and block_step(st, np.ascontiguousarray(X[:, k:k + p]), unit)):
+            round_new_columns(st, q0, storage)
             k += p
             continue
         m = min(p, N - k)
         foa.foa_stream_update(st, X[:, k:k + m])
+        round_new_columns(st, q0, storage)
         k += m
     return st

@@ -13,6 +13,7 @@ import oracle.foa as ofoa
 from pins import _krylov, match_eigs
 
 EPS64 = 2.0 ** -52
+EPS32 = 2.0 ** -23
 
 
 def _noisy(n=3000, N=61, name="noisy_2p20x200"):
@@ -106,8 +107,48 @@ def pin_block_qr(B):
             and np.abs(np.tril(S, -1)).max() == 0.0 and np.all(np.diag(S) > 0))
 
 
+def pin_noise_floor_f32(B):
+    """FP32-rounded basis, snapshots whose new directions sit at the data's
+    noise floor (about 1e-8 of their norm) at small n (5000 rows, 500
+    snapshots): the basis stays orthogonal and X = V beta holds, both to
+    10 sqrt(q) eps32 -- where two projections that take V as orthonormal lose
+    orthogonality completely (||I - V^T V|| about 47)."""
+    X = _noisy(5000, 500, "noisy_2p24x500")
+    b = B.foa_blocked(X, storage="f32")
+    q = b.q
+    V = b.V[:, :q]
+    if q != 500 or not (np.all(np.isfinite(V)) and np.all(np.isfinite(b.beta[:q, :q]))):
+        return False
+    orth = np.linalg.norm(np.eye(q) - V.T @ V, 2)
+    fact = np.linalg.norm(X[:, :q] - V @ b.beta[:q, :q]) / np.linalg.norm(X[:, :q])
+    return orth <= 10 * np.sqrt(q) * EPS32 and fact <= 10 * np.sqrt(q) * EPS32
+
+
+def pin_third_projection_rule(B):
+    """The test for a third projection: never on an exactly orthonormal basis
+    (R2 = 0), never when R1 = 0, and on a basis whose Gram deviation E is known
+    exactly it fires precisely when ||E R1||_F / ||R1||_F * ||R2_k|| exceeds a
+    tenth of the unit roundoff times ||Z_k||."""
+    rng = np.random.default_rng(11)
+    n, j, p = 400, 30, 4
+    V, _ = np.linalg.qr(rng.standard_normal((n, j)))
+    Y = rng.standard_normal((n, p))
+    R1 = V.T @ Y
+    Z = Y - V @ R1
+    ok = not B.third_projection_needed(R1, np.zeros_like(R1), Z, 2.0 ** -24)
+    ok = ok and not B.third_projection_needed(np.zeros_like(R1), np.zeros_like(R1), Z, 2.0 ** -24)
+    E = 1e-6 * rng.standard_normal((j, j))
+    R2 = -E @ R1
+    e = np.linalg.norm(R2) / np.linalg.norm(R1)
+    rem = e * np.linalg.norm(R2, axis=0)
+    for scale in (0.5, 2.0):       # Z's columns just above / below the threshold
+        Zs = Z / np.linalg.norm(Z, axis=0) * (rem.max() / (0.1 * 2.0 ** -24)) * scale
+        ok = ok and B.third_projection_needed(R1, R2, Zs, 2.0 ** -24) == (scale < 1.0)
+    return ok
+
+
 PINS = [pin_matches_sequential, pin_orthogonal_factorisation, pin_householder, pin_exact_rank,
-        pin_kappa_slope, pin_block_qr]
+        pin_kappa_slope, pin_block_qr, pin_noise_floor_f32, pin_third_projection_rule]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=lambda f: f.__name__)
@@ -121,32 +162,39 @@ class _Mutant:
     """oracle.blocked with one function replaced."""
 
     def __init__(self, **repl):
-        self.__dict__.update({k: getattr(ob, k) for k in ("PB", "UNIT", "block_qr", "_chol_upper",
-                                                          "_right_solve_upper")})
+        self.__dict__.update({k: getattr(ob, k) for k in ("PB", "UNIT", "THIRD_ETA", "block_qr", "_chol_upper",
+                                                          "_right_solve_upper", "third_projection_needed",
+                                                          "storage_unit", "round_new_columns")})
         self.__dict__.update(repl)
-        self.block_step = lambda st, Y: self.step_impl(self, st, Y)
-        self.foa_blocked = lambda X, p=ob.PB, tol=None, capacity=None: _foa_blocked(self, X, p, tol, capacity)
+        self.block_step = lambda st, Y, unit=ob.UNIT: self.step_impl(self, st, Y, unit)
+        self.foa_blocked = (lambda X, p=ob.PB, tol=None, capacity=None, storage="f64":
+                            _foa_blocked(self, X, p, tol, capacity, storage))
 
 
-def _foa_blocked(M, X, p, tol, capacity):
+def _foa_blocked(M, X, p, tol, capacity, storage):
     X = np.asarray(X, dtype=np.float64)
     n, N = X.shape
     cap = N if capacity is None else int(capacity)
+    unit = M.storage_unit(storage)
     st = ofoa.foa_stream_init(n, cap, tol)
     ofoa.foa_stream_update(st, X[:, :1])
+    M.round_new_columns(st, 0, storage)
     k = 1
     while k < N:
+        q0 = st.q
         if (st.status == ofoa.ACTIVE and k + p <= N and st.q + p <= cap
-                and M.block_step(st, np.ascontiguousarray(X[:, k:k + p]))):
+                and M.block_step(st, np.ascontiguousarray(X[:, k:k + p]), unit)):
+            M.round_new_columns(st, q0, storage)
             k += p
             continue
         m = min(p, N - k)
         ofoa.foa_stream_update(st, X[:, k:k + m])
+        M.round_new_columns(st, q0, storage)
         k += m
     return st
 
 
-def _step(M, st, Y, passes=2, h_col_shift=0, drop_S=False, transpose_R=False):
+def _step(M, st, Y, unit, passes=2, h_col_shift=0, drop_S=False, transpose_R=False, third=True):
     n, p = Y.shape
     j = st.q
     V = st.V[:, :j]
@@ -158,6 +206,10 @@ def _step(M, st, Y, passes=2, h_col_shift=0, drop_S=False, transpose_R=False):
         R2 = V.T @ Z
         Z = Z - V @ R2
         R = R1 + R2
+        if third and M.third_projection_needed(R1, R2, Z, unit):
+            R3 = V.T @ Z
+            Z = Z - V @ R3
+            R = R + R3
     res = M.block_qr(Z)
     if res is None:
         return False
@@ -186,14 +238,22 @@ MUTANTS = {
     "h_recurrence_index": dict(h_col_shift=-1),
     "block_R_offdiagonal_dropped": dict(drop_S=True),
     "R_columns_reversed": dict(transpose_R=True),
+    "no_third_projection": dict(third=False),
+    # the rule itself: the remainder measured against ||R1_k|| instead of ||Z_k||;
+    # the threshold on ||R2_k|| alone
+    "third_rule_against_R1": dict(repl=dict(third_projection_needed=lambda R1, R2, Z, unit: bool(
+        np.linalg.norm(R1) > 0 and np.any(np.linalg.norm(R2) / np.linalg.norm(R1) * np.linalg.norm(R2, axis=0)
+                                          > ob.THIRD_ETA * unit * np.linalg.norm(R1, axis=0))))),
+    "third_rule_without_E_estimate": dict(repl=dict(third_projection_needed=lambda R1, R2, Z, unit: bool(
+        np.any(np.linalg.norm(R2, axis=0) > ob.THIRD_ETA * unit * np.linalg.norm(Z, axis=0))))),
 }
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_blocked_mutant_is_caught(name):
-    kw = MUTANTS[name]
-    M = _Mutant()
-    M.step_impl = lambda M_, st, Y: _step(M_, st, Y, **kw)
+    kw = dict(MUTANTS[name])
+    M = _Mutant(**kw.pop("repl", {}))
+    M.step_impl = lambda M_, st, Y, unit: _step(M_, st, Y, unit, **kw)
     failed = []
     for pin in PINS:
         try:
