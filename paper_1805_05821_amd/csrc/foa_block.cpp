@@ -19,7 +19,7 @@ constexpr int kGramGrid = 1024;  // workgroups of the block Gram passes (partial
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct BlockLayout {
-  size_t Z = 0, coef = 0, partb = 0, partg = 0, sm = 0, flag = 0, total = 0;
+  size_t Z = 0, coef = 0, partb = 0, partg = 0, sm = 0, flag = 0, gate = 0, total = 0;
 };
 
 BlockLayout block_layout(int64_t n, int n_max, int ldg) {
@@ -37,6 +37,7 @@ BlockLayout block_layout(int64_t n, int n_max, int ldg) {
   B.partg = take((size_t)kGramGrid * BPK * BPK * 8);
   B.sm = take((size_t)SM_TOTAL * 8);
   B.flag = take(sizeof(int));
+  B.gate = take(sizeof(int));
   B.total = o;
   return B;
 }
@@ -80,6 +81,16 @@ hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const vo
   if ((e = launch_breduce(2, a, s)) != hipSuccess) return e;                         // R2, R += R2, coef
   if ((e = launch_bpass(2, v64, true, qw, a.G, a, s)) != hipSuccess) return e;      // Z = Z - W C
   if ((e = launch_zgram(1, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // Z^T Z
+  // third projection, where the test asks for it (the gated kernels return
+  // at once otherwise)
+  int *gate = reinterpret_cast<int *>(bws + L.gate);
+  if ((e = launch_bthird(a, gate, v64 ? 0x1p-53 : 0x1p-24, s)) != hipSuccess) return e;
+  BlockArgs g = a;
+  g.gate = gate;
+  if ((e = launch_bpass(3, v64, true, qw, g.G, g, s)) != hipSuccess) return e;      // D = W^T Z
+  if ((e = launch_breduce(3, g, s)) != hipSuccess) return e;                         // R3, R += R3, coef
+  if ((e = launch_bpass(2, v64, true, qw, g.G, g, s)) != hipSuccess) return e;      // Z = Z - W C
+  if ((e = launch_zgram(1, v64, x64, g.Gz, g, s)) != hipSuccess) return e;          // Z^T Z
   if ((e = launch_bchol(0, a, s)) != hipSuccess) return e;                           // shifted
   if ((e = launch_zgram(2, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // Z T0, Gram
   if ((e = launch_bchol(1, a, s)) != hipSuccess) return e;

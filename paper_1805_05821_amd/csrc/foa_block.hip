@@ -5,11 +5,18 @@
 // the QR view of Section 3.1).  The blocked form reaches the same factors in
 // exact arithmetic with a block Y of snapshots at a time:
 //   R1 = V^T Y;  Z = Y - V R1;  R2 = V^T Z;  Z = Z - V R2     (block CGS2)
+//   [R3 = V^T Z;  Z = Z - V R3]    when two projections may not be enough
 //   Z = Q S by shifted CholeskyQR3 (Fukaya et al., SIAM J. Sci. Comput. 2020)
-//   beta's new columns [R1 + R2; S], V's new columns Q, and H_bar's new
+//   beta's new columns [R1 + R2 (+ R3); S], V's new columns Q, and H_bar's new
 //   columns from the recurrence above solved column by column.
 // So the basis is swept three times per block instead of three times per
-// snapshot.  A block is committed only if its Cholesky steps succeed and every
+// snapshot.  The third projection: a stored FP32 basis is orthonormal only to
+// E = V^T V - I, the part of Z left along V after two passes is about E R2,
+// and where the block's new directions are as small as ||E|| ||Y|| (noise-
+// floor snapshots at small n) that part is as large as Z itself.  The test
+// estimates ||E|| by ||R2||_F / ||R1||_F and takes the third pass when
+// ||E|| ||R2_k|| > u_V ||Z_k|| / 10 for some k (u_V the basis's unit
+// roundoff); its kernels are always enqueued and return at once otherwise.  A block is committed only if its Cholesky steps succeed and every
 // new diagonal entry of beta is above the breakdown threshold; otherwise the
 // device state is left as it was and the host takes those snapshots one at a
 // time (the sequential kernels then apply the paper's breakdown rule).
@@ -21,6 +28,8 @@
 //               its Gram matrix, the final Q written into V);
 //   k_breduce : fixed-order reduction of the pass partials into R1 / R2 and
 //               the next pass's coefficients;
+//   k_bthird  : the test for the third projection (sets the gate of its
+//               BP_D pass, reduction, BP_Z2 pass and Gram pass);
 //   k_bchol   : Gram reduction, (shifted) Cholesky and triangular inverse;
 //   k_bcommit : breakdown test, beta, H_bar, sigma and the scalar state.
 #include <mutex>
@@ -67,13 +76,14 @@ hipError_t block_static_scratch(int device, char **ptr) {
   return g_scratch_err[device];
 }
 
-enum { BP_R1 = 0, BP_Z1 = 1, BP_Z2 = 2 };
+enum { BP_R1 = 0, BP_Z1 = 1, BP_Z2 = 2, BP_D = 3 };
 bool block_supported(bool tv_f64, int qw);
 enum { ZG_YNORM = 0, ZG_GRAM = 1, ZG_APPLY = 2, ZG_WRITEV = 3 };
 
 // ---------------------------------------------------------------------------
 // Block row pass.  MODE BP_R1: D = W^T Y (column sums only).  BP_Z1:
-// Z = Y - W C, D = W^T Z.  BP_Z2: Z = Z - W C.  W is the stored basis (the
+// Z = Y - W C, D = W^T Z.  BP_Z2: Z = Z - W C.  BP_D: D = W^T Z (column
+// sums of the block, for the third projection).  W is the stored basis (the
 // sigma scaling of its columns is folded into C and into the reduction of D).
 // Per panel, the BPK right-hand sides of a row are spread over the update
 // lanes (row, k); phase 1 and phase 2 are those of the single push with BPK
@@ -87,12 +97,13 @@ __global__ __launch_bounds__(NW * 64) void k_bpass(BlockArgs a) {
   constexpr int JCAP = QW * NW * CPW;
   constexpr int RPW = PANEL / NW;
   constexpr int GSTRIDE = NW * CPW;
-  constexpr bool HAS_P1 = MODE != BP_R1;
+  constexpr bool HAS_P1 = MODE == BP_Z1 || MODE == BP_Z2;
   constexpr bool HAS_P2 = MODE != BP_Z2;
-  constexpr bool SRC_X = MODE != BP_Z2;
+  constexpr bool SRC_X = MODE == BP_R1 || MODE == BP_Z1;
+  constexpr bool STORE_Z = MODE == BP_Z1 || MODE == BP_Z2;
   static_assert(RPW * BPK <= 64, "update lanes");
 
-  if (a.st->status != ST_ACTIVE || *a.flag) return;
+  if (a.st->status != ST_ACTIVE || *a.flag || (a.gate && !*a.gate)) return;
 
   __shared__ double s_coef[HAS_P1 ? JCAP * BPK : 1];
   __shared__ double s_red[2][NW][PANEL * BPK];
@@ -202,7 +213,7 @@ __global__ __launch_bounds__(NW * 64) void k_bpass(BlockArgs a) {
       for (int w2 = 0; w2 < NW; ++w2) us += s_red[par][w2][urow * BPK + uk];
     }
     const double wv = y - us;
-    if (MODE != BP_R1) {
+    if (STORE_Z) {
       const __amdgpu_buffer_rsrc_t rz = make_rsrc(a.Z + p * PANEL * BPK, PANEL * BPK * 8);
       buf_store_scalar<double>(wv, rz, uact ? (unsigned)((uk * PANEL + urow) * 8) : kOOR);
     }
@@ -266,7 +277,7 @@ constexpr int GSLOT = BPK * BPK;
 
 template <typename TV, typename TX, int MODE>
 __global__ __launch_bounds__(256) void k_zgram(BlockArgs a) {
-  if (a.st->status != ST_ACTIVE || *a.flag) return;
+  if (a.st->status != ST_ACTIVE || *a.flag || (a.gate && !*a.gate)) return;
   __shared__ double sh[256];
   __shared__ double sT[BPK * BPK];
   const int tid = threadIdx.x;
@@ -337,11 +348,12 @@ __global__ __launch_bounds__(256) void k_zgram(BlockArgs a) {
 // Reduction of the block-pass partials: one wavefront per (column, rhs) pair
 // in a fixed order.  MODE 1 (after BP_R1): R = sigma o D, coef = sigma o R,
 // and (extra wavefronts) ||y_k||^2 from the ZG_YNORM partials.  MODE 2 (after
-// BP_Z1): R += sigma o D, coef = sigma o (sigma o D).
+// BP_Z1): R2 = sigma o D, R += R2, coef = sigma o R2.  MODE 3 (after BP_D):
+// R += sigma o D, coef = sigma o (sigma o D).
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(256) void k_breduce(BlockArgs a) {
-  if (a.st->status != ST_ACTIVE || *a.flag) return;
+  if (a.st->status != ST_ACTIVE || *a.flag || (a.gate && !*a.gate)) return;
   const int lane = threadIdx.x & 63;
   const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int npairs = a.j * BPK;
@@ -360,6 +372,7 @@ __global__ __launch_bounds__(256) void k_breduce(BlockArgs a) {
       } else {
         a.sm[SM_R + idx] += r;
       }
+      if (MODE == 2) a.sm[SM_R2 + idx] = r;
       a.coef[idx] = a.sigma[c] * r;
     }
   } else if (MODE == 1 && wv < npairs + BPK) {
@@ -558,6 +571,55 @@ __global__ void k_bflag_clear(int *flag) {
 }
 
 // ---------------------------------------------------------------------------
+// Test for the third projection, after the Gram pass of Z = Y - V (R1 + R2):
+// ||Z_k||^2 from the Gram partials (fixed order), ||R2||_F, ||R2_k|| and
+// ||R1||_F = ||R - R2||_F from the small area.  *gate = 1 when
+// (||R2||_F / ||R1||_F) ||R2_k|| > unit ||Z_k|| / 10 for some k, else 0
+// (also for a rejected block).  One workgroup.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_bthird(BlockArgs a, int *gate, double unit) {
+  __shared__ double sh[256];
+  __shared__ double s_z2[BPK], s_r2[BPK];
+  const int tid = threadIdx.x;
+  if (a.st->status != ST_ACTIVE || *a.flag) {
+    if (tid == 0) *gate = 0;
+    return;
+  }
+  const int npairs = a.j * BPK;
+  double r1 = 0.0;
+  double r2k[BPK];
+#pragma unroll
+  for (int k = 0; k < BPK; ++k) r2k[k] = 0.0;
+  for (int e = tid; e < npairs; e += 256) {
+    const double v2 = a.sm[SM_R2 + e];
+    const double v1 = a.sm[SM_R + e] - v2;
+    r1 = fma(v1, v1, r1);
+#pragma unroll
+    for (int k = 0; k < BPK; ++k)
+      if (e % BPK == k) r2k[k] = fma(v2, v2, r2k[k]);
+  }
+  const double r1s = block_sum_256(r1, sh);
+#pragma unroll
+  for (int k = 0; k < BPK; ++k) {
+    const double v = block_sum_256(r2k[k], sh);
+    if (tid == 0) s_r2[k] = v;
+    double z = 0.0;
+    for (int g = tid; g < a.Gz; g += 256) z += a.partg[(size_t)g * GSLOT + k * BPK + k];
+    const double zs = block_sum_256(z, sh);
+    if (tid == 0) s_z2[k] = zs;
+  }
+  if (tid != 0) return;
+  int third = 0;
+  if (r1s > 0.0) {
+    double r2f = 0.0;
+    for (int k = 0; k < BPK; ++k) r2f += s_r2[k];
+    const double e = sqrt(r2f) / sqrt(r1s);
+    for (int k = 0; k < BPK; ++k) third |= e * sqrt(s_r2[k]) > 0.1 * unit * sqrt(s_z2[k]);
+  }
+  *gate = third;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 template <typename TV, typename TX, int NW, int MODE, bool PREF>
@@ -597,6 +659,9 @@ static hipError_t launch_bpass_m(int mode, int qw, int grid, const BlockArgs &a,
     case BP_Z1:
       return pref ? launch_bpass_q<TV, TX, NW, BP_Z1, true>(qw, grid, a, s)
                   : launch_bpass_q<TV, TX, NW, BP_Z1, false>(qw, grid, a, s);
+    case BP_D:
+      return pref ? launch_bpass_q<TV, double, NW, BP_D, true>(qw, grid, a, s)
+                  : launch_bpass_q<TV, double, NW, BP_D, false>(qw, grid, a, s);
     default:
       return pref ? launch_bpass_q<TV, double, NW, BP_Z2, true>(qw, grid, a, s)
                   : launch_bpass_q<TV, double, NW, BP_Z2, false>(qw, grid, a, s);
@@ -638,8 +703,10 @@ hipError_t launch_breduce(int mode, const BlockArgs &a, hipStream_t s) {
   const int blocks = (waves + 3) / 4;
   if (mode == 1)
     hipLaunchKernelGGL(k_breduce<1>, dim3(blocks), dim3(256), 0, s, a);
-  else
+  else if (mode == 2)
     hipLaunchKernelGGL(k_breduce<2>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_breduce<3>, dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -659,6 +726,11 @@ hipError_t launch_bcommit(const BlockArgs &a, hipStream_t s) {
 
 hipError_t launch_bflag_clear(int *flag, hipStream_t s) {
   hipLaunchKernelGGL(k_bflag_clear, dim3(1), dim3(64), 0, s, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_bthird(const BlockArgs &a, int *gate, double unit, hipStream_t s) {
+  hipLaunchKernelGGL(k_bthird, dim3(1), dim3(256), 0, s, a, gate, unit);
   return hipGetLastError();
 }
 

@@ -162,13 +162,15 @@ constexpr int kCtlInts = kCtlGroup0 + kCtlGroupStride * kMaxGroups;
 
 // ---- blocked form ------------------------------------------------------------
 constexpr int BPK = 4;  // snapshots per block
-// small-area offsets (doubles): R = R1 + R2 (n_max x BPK, [c * BPK + k]),
-// ||y_k||^2, S_total and T (BPK x BPK, row-major)
+// small-area offsets (doubles): R = R1 + R2 (+ R3) (n_max x BPK,
+// [c * BPK + k]), ||y_k||^2, S_total and T (BPK x BPK, row-major), R2 alone
+// (the test for a third projection)
 constexpr int SM_R = 0;
 constexpr int SM_YN2 = SM_R + 512 * BPK;
 constexpr int SM_S = SM_YN2 + BPK;
 constexpr int SM_T = SM_S + BPK * BPK;
-constexpr int SM_TOTAL = SM_T + BPK * BPK;
+constexpr int SM_R2 = SM_T + BPK * BPK;
+constexpr int SM_TOTAL = SM_R2 + 512 * BPK;
 struct BlockArgs {
   void *W;          // stored basis (panel layout)
   const void *x;    // first snapshot of the block; snapshot k at x + k * ldx (elements)
@@ -179,6 +181,7 @@ struct BlockArgs {
   double *partg;    // block Gram partials, [slot * BPK * BPK + k * BPK + l]
   double *sm;       // small area (SM_* offsets)
   int *flag;        // nonzero: the block (or an earlier one) was rejected
+  const int *gate;  // non-null: the kernel runs only while *gate is nonzero (third projection)
   DevState *st;
   double *H, *beta, *sigma;
   int64_t n, P;
@@ -240,6 +243,7 @@ hipError_t launch_breduce(int mode, const BlockArgs &a, hipStream_t s);
 hipError_t launch_bchol(int round, const BlockArgs &a, hipStream_t s);
 hipError_t launch_bcommit(const BlockArgs &a, hipStream_t s);
 hipError_t launch_bflag_clear(int *flag, hipStream_t s);
+hipError_t launch_bthird(const BlockArgs &a, int *gate, double unit, hipStream_t s);
 // Device address of this device's static block workspace (looked up once per
 // device with that device current; the result, or the lookup's error, is kept).
 hipError_t block_static_scratch(int device, char **ptr);
