@@ -102,6 +102,27 @@ def test_batch_f32_within_bound():
     bt.close()
 
 
+def test_batch_f32_noise_floor():
+    """Batched three-sweep form on the throughput recipe at small n (noise-
+    floor snapshots): every stream orthogonal to 10 sqrt(q) eps32 and within
+    10 eps32 kappa_2 of the FP64 oracle."""
+    w = datagen.get_workload("noisy_2p24x500")
+    Xs = [datagen.snapshots_numpy(w.with_n(n).with_N(N), dtype="float64")[0]
+          for n, N in ((5000, 500), (20000, 500), (3000, 77))]
+    bt, q, st = _run_batch(Xs, "f32")
+    for s, X in enumerate(Xs):
+        ref = oracle.foa_batch(X)
+        H, B, qq, m, V = _view_state(bt, s)
+        assert qq == ref.q
+        kap = kappa_of(ref.beta[:m, :m])
+        eH = np.linalg.norm(H[:m, :m] - ref.H[:m, :m], 2) / np.linalg.norm(ref.H[:m, :m], 2)
+        orth = np.linalg.norm(np.eye(qq) - V.T @ V, 2)
+        announce(f"stream {s}: n={X.shape[0]} q={qq} kappa={kap:.1e} relH2={eH:.1e} orth={orth:.1e}")
+        assert eH <= 10 * EPS32 * kap
+        assert orth <= 10 * np.sqrt(qq) * EPS32
+    bt.close()
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_batch_late_starting_streams(prec):
     """Streams that start several pushes after the reset (idle before), next

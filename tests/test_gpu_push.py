@@ -115,6 +115,28 @@ def test_f64_f32_snapshots():
     _compare_f64(g, st)
 
 
+@pytest.mark.parametrize("n,N", [(5000, 500), (20000, 500)])
+def test_f32_cgs2_noise_floor(n, N):
+    """The throughput recipe at small n (noise-floor snapshots, new directions
+    about 1e-8 of their norm, FP32 basis orthonormal only to about that): the
+    three projections per push (the Arnoldi recurrence's and CGS2's two) keep
+    the basis orthogonal to 10 sqrt(q) eps32 and H within 10 eps32 kappa_2,
+    without the corrections the one-reduction and blocked forms need there
+    (two projections that take the rounded basis as orthonormal lose it)."""
+    w = datagen.get_workload("noisy_2p24x500").with_n(n).with_N(N)
+    X, _, _ = datagen.snapshots_numpy(w, dtype="float64")
+    st = oracle.foa_batch(X)
+    g = run_gpu(X, "f32", snap_dtype=None)
+    q, m = g["q"], g["m"]
+    kap = kappa_of(st.beta[:m, :m])
+    eH = np.linalg.norm(g["H"][:m, :m] - st.H[:m, :m], 2) / np.linalg.norm(st.H[:m, :m], 2)
+    orth = np.linalg.norm(np.eye(q) - g["V"].T @ g["V"], 2)
+    announce(f"n={n} N={N}: q={q} kappa={kap:.2e} relH2={eH:.2e} (bound {10 * EPS32 * kap:.2e}) orth={orth:.2e}")
+    assert q == st.q
+    assert eH <= 10 * EPS32 * kap
+    assert orth <= 10 * np.sqrt(q) * EPS32
+
+
 @pytest.mark.parametrize("N", [40, 140])
 def test_f32_cgs2_within_bound(N):
     """FP32-stored basis, FP64 accumulation: ||H32 - H64||_2 / ||H64||_2 and
