@@ -3,10 +3,13 @@
   python -m paper_1805_05821_amd.rocprof_summary kernels DIR
       per-kernel statistics (from *kernel_stats.csv) plus the aggregate of the
       fused row-pass kernels (all k_pass instances).
-  python -m paper_1805_05821_amd.rocprof_summary window DIR PREFIX START COUNT
+  python -m paper_1805_05821_amd.rocprof_summary window DIR PREFIX START COUNT [MIN_US]
       average duration of the dispatches START .. START+COUNT-1 (time order)
       of the kernels whose name starts with PREFIX (from *kernel_trace.csv):
-      picks one run out of a trace that holds several.
+      picks one run out of a trace that holds several.  With MIN_US, the
+      dispatches shorter than MIN_US microseconds (kernels whose gate was
+      closed, which return at once) are counted apart and left out of the
+      average.
   python -m paper_1805_05821_amd.rocprof_summary counter DIR COUNTER
       average value of COUNTER per dispatch for the row-pass kernels and for
       the copy kernel of a calibration run (from *counter_collection.csv).
@@ -216,9 +219,10 @@ def traffic(fetch_dir, write_dir, fetch_copy, write_copy, copy_bytes, bench_log,
     return rec
 
 
-def window(d, prefix, start, count):
+def window(d, prefix, start, count, min_us=None):
     """Average duration of dispatches [start, start + count) in time order
-    among the kernels whose name starts with prefix."""
+    among the kernels whose name starts with prefix (without those shorter
+    than min_us microseconds, when given)."""
     rows = []
     for path in _find(d, "kernel_trace.csv"):
         with open(path) as fh:
@@ -228,8 +232,13 @@ def window(d, prefix, start, count):
     rows.sort()
     sel = rows[int(start):int(start) + int(count)]
     ms = [(b - a) / 1e6 for a, b in sel]
-    return (f"{prefix}*: dispatches {start}..{int(start) + len(sel) - 1} of {len(rows)} in time order: "
-            f"{len(sel)} dispatches, total {sum(ms):.2f} ms, average {sum(ms) / max(len(ms), 1):.4f} ms")
+    head = f"{prefix}*: dispatches {start}..{int(start) + len(sel) - 1} of {len(rows)} in time order: "
+    if min_us is None:
+        return head + f"{len(sel)} dispatches, total {sum(ms):.2f} ms, average {sum(ms) / max(len(ms), 1):.4f} ms"
+    ran = [t for t in ms if t * 1e3 >= float(min_us)]
+    short = len(ms) - len(ran)
+    return (head + f"{len(ran)} ran, total {sum(ran):.2f} ms, average {sum(ran) / max(len(ran), 1):.4f} ms; "
+            f"{short} under {float(min_us):g} us (returned at once), total {sum(ms) - sum(ran):.2f} ms")
 
 
 def batched_run(d, occurrence, steps):
@@ -316,7 +325,7 @@ def main(argv):
     if len(argv) >= 2 and argv[0] == "kernels":
         print(summarize_kernels(argv[1]))
     elif len(argv) >= 5 and argv[0] == "window":
-        print(window(argv[1], argv[2], argv[3], argv[4]))
+        print(window(argv[1], argv[2], argv[3], argv[4], argv[5] if len(argv) > 5 else None))
     elif len(argv) >= 3 and argv[0] == "counter":
         print(summarize_counter(argv[1], argv[2]))
     elif len(argv) >= 9 and argv[0] == "kernel_traffic":
