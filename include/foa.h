@@ -142,10 +142,14 @@ foa_status foa_block_workspace_bytes(int64_t n, int32_t n_max, foa_prec prec, si
  * blocks of 4: the factorisation X = V beta and H_bar of the modified FOA
  * (Section 2, eq. betacolumnupdate; the QR view of Section 3.1) reached with
  * three sweeps over the basis per block instead of per snapshot.  Per block:
- * classical Gram-Schmidt of the whole block against V, twice, then the
- * block's own QR by shifted CholeskyQR3 (Fukaya et al., SIAM J. Sci. Comput.
- * 2020), beta's new columns [R1 + R2; S] and H_bar's new columns from eq.
- * betacolumnupdate solved column by column.  The results equal the
+ * classical Gram-Schmidt of the whole block against V, twice, and a third
+ * time where two passes may leave part of the block along V (a basis stored
+ * in FP32 is orthonormal only to its rounding, which matters for snapshots
+ * whose new directions are that small: the test compares
+ * (||R2||_F / ||R1||_F) ||R2_k|| with a tenth of the basis's unit roundoff
+ * times ||Z_k||), then the block's own QR by shifted CholeskyQR3 (Fukaya et
+ * al., SIAM J. Sci. Comput. 2020), beta's new columns [R1 + R2 (+ R3); S] and
+ * H_bar's new columns from eq. betacolumnupdate solved column by column.  The results equal the
  * sequential form's in exact arithmetic and differ by rounding of the same
  * O(eps kappa_2) order.  A block whose new diagonal entry of beta falls at or
  * under the breakdown threshold, or whose Cholesky steps fail, is taken one
