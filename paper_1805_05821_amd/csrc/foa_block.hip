@@ -36,6 +36,7 @@
 
 #include "foa.h"
 #include "foa_device.h"
+#include "foa_tile.h"
 
 // Block workspace of foa_push_blocked_static, for callers that cannot
 // allocate device memory: one copy per device the library runs on, held
@@ -89,7 +90,9 @@ enum { ZG_YNORM = 0, ZG_GRAM = 1, ZG_APPLY = 2, ZG_WRITEV = 3 };
 // lanes (row, k); phase 1 and phase 2 are those of the single push with BPK
 // values per row.
 // ---------------------------------------------------------------------------
-template <typename TV, typename TX, int NW, int QW, int MODE, bool PREF>
+// PF: groups of the next panel's tile loaded ahead (0 .. QW; the rest load at
+// the start of their panel).
+template <typename TV, typename TX, int NW, int QW, int MODE, int PF>
 __global__ __launch_bounds__(NW * 64) void k_bpass(BlockArgs a) {
   constexpr int EPL = Vec<TV>::EPL;
   constexpr int LPC = 64 / EPL;
@@ -139,22 +142,14 @@ __global__ __launch_bounds__(NW * 64) void k_bpass(BlockArgs a) {
   const char *Wb = static_cast<const char *>(a.W);
   const size_t pbytes = (size_t)a.n_max * PANEL * sizeof(TV);
   TV t[QW][EPL];
-  TV tn[QW][EPL];
-  auto load_tile = [&](int64_t p, TV (&dst)[QW][EPL], unsigned bytes) {
-    const __amdgpu_buffer_rsrc_t rt = make_rsrc(Wb + (size_t)p * pbytes, bytes);
-#pragma unroll
-    for (int g = 0; g < QW; ++g) {
-      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rt, (int)(goff0 + g * GBYTES), 0, kTileLoad);
-      unpack16<TV>(v, dst[g]);
-    }
-  };
+  TV tn[PF > 0 ? PF : 1][EPL];
 
   const int64_t pend = a.P, pstep = gridDim.x;
   int64_t p = blockIdx.x;
-  if (PREF && p < pend) {
-    load_tile(p, t, tile_bytes);
+  if (PF > 0 && p < pend) {
+    load_tile_groups<TV, 0, PF, 0>(make_rsrc(Wb + (size_t)p * pbytes, tile_bytes), goff0, GBYTES, t);
 #pragma unroll
-    for (int g = 0; g < QW; ++g)
+    for (int g = 0; g < PF; ++g)
 #pragma unroll
       for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(t[g][e]));
   }
@@ -172,11 +167,12 @@ __global__ __launch_bounds__(NW * 64) void k_bpass(BlockArgs a) {
       const __amdgpu_buffer_rsrc_t rz = make_rsrc(a.Z + p * PANEL * BPK, PANEL * BPK * 8);
       y = buf_load_scalar<double>(rz, uact ? (unsigned)((uk * PANEL + urow) * 8) : kOOR);
     }
-    if (PREF) {
+    if constexpr (PF < QW)  // the groups not prefetched, straight into their place
+      load_tile_groups<TV, PF, QW, PF>(make_rsrc(Wb + (size_t)p * pbytes, tile_bytes), goff0, GBYTES, t);
+    if constexpr (PF > 0) {
       const bool more = p + pstep < pend;
-      load_tile(more ? p + pstep : p, tn, more ? tile_bytes : 0u);
-    } else {
-      load_tile(p, t, tile_bytes);
+      load_tile_groups<TV, 0, PF, 0>(make_rsrc(Wb + (size_t)(more ? p + pstep : p) * pbytes, more ? tile_bytes : 0u),
+                                     goff0, GBYTES, tn);
     }
 
     double us = 0.0;
@@ -220,31 +216,47 @@ __global__ __launch_bounds__(NW * 64) void k_bpass(BlockArgs a) {
     if (HAS_P2) {
       if (uact) s_w[par][urow * BPK + uk] = wv;
       __syncthreads();
-      double wr[EPL][BPK];
-#pragma unroll
-      for (int e = 0; e < EPL; ++e)
-#pragma unroll
-        for (int k = 0; k < BPK; ++k) wr[e][k] = s_w[par][(rg * EPL + e) * BPK + k];
       if constexpr (sizeof(TV) == 4) {
 #pragma unroll
         for (int g = 0; g < QW; ++g)
 #pragma unroll
           for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(t[g][e]));
       }
+      if constexpr (HAS_P1) {
+        // both phases: one row's right-hand sides at a time, which leaves
+        // registers for part of the next tile (each accumulator still takes
+        // its rows in order e = 0 .. EPL-1, as below)
 #pragma unroll
-      for (int g = 0; g < QW; ++g)
+        for (int e = 0; e < EPL; ++e) {
+          double wr[BPK];
 #pragma unroll
-        for (int k = 0; k < BPK; ++k)
+          for (int k = 0; k < BPK; ++k) wr[k] = s_w[par][(rg * EPL + e) * BPK + k];
 #pragma unroll
-          for (int e = 0; e < EPL; ++e) acc[g][k] = fma((double)t[g][e], wr[e][k], acc[g][k]);
+          for (int g = 0; g < QW; ++g)
+#pragma unroll
+            for (int k = 0; k < BPK; ++k) acc[g][k] = fma((double)t[g][e], wr[k], acc[g][k]);
+        }
+      } else {
+        double wr[EPL][BPK];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e)
+#pragma unroll
+          for (int k = 0; k < BPK; ++k) wr[e][k] = s_w[par][(rg * EPL + e) * BPK + k];
+#pragma unroll
+        for (int g = 0; g < QW; ++g)
+#pragma unroll
+          for (int k = 0; k < BPK; ++k)
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) acc[g][k] = fma((double)t[g][e], wr[e][k], acc[g][k]);
+      }
     }
-    if (PREF) {
+    if constexpr (PF > 0) {
 #pragma unroll
-      for (int g = 0; g < QW; ++g)
+      for (int g = 0; g < PF; ++g)
 #pragma unroll
         for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(tn[g][e]));
 #pragma unroll
-      for (int g = 0; g < QW; ++g)
+      for (int g = 0; g < PF; ++g)
 #pragma unroll
         for (int e = 0; e < EPL; ++e) t[g][e] = tn[g][e];
     }
@@ -622,23 +634,52 @@ __global__ __launch_bounds__(256) void k_bthird(BlockArgs a, int *gate, double u
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <typename TV, typename TX, int NW, int MODE, bool PREF>
+#ifndef BP_PF_Z1_12
+#define BP_PF_Z1_12 6
+#endif
+#ifndef BP_PF_Z1_16
+#define BP_PF_Z1_16 0
+#endif
+#ifndef BP_PF_R1_16
+#define BP_PF_R1_16 0
+#endif
+#ifndef BP_PF_Z2_16
+#define BP_PF_Z2_16 16
+#endif
+
+// Prefetched groups of a block pass (what fits beside the BPK accumulators).
+// FP32 basis: the whole tile up to 8 groups, and in the passes with one phase
+// at 12 groups (BP_Z2 also at 16), 6 of 12 groups in BP_Z1, none at 16 groups
+// in BP_Z1 (it spills without) nor in BP_R1 / BP_D (8 of 16 fit, measured no
+// faster); FP64 basis: up to 4 groups, in BP_Z2 up to 8.
+template <typename TV, int QW, int MODE>
+constexpr int bp_pf() {
+  if constexpr (sizeof(TV) == 8) {
+    return (QW <= 4 || MODE == BP_Z2) ? QW : 0;
+  } else {
+    if (QW <= 8) return QW;
+    if (QW == 12) return MODE == BP_Z1 ? BP_PF_Z1_12 : 12;
+    return MODE == BP_Z2 ? BP_PF_Z2_16 : (MODE == BP_Z1 ? BP_PF_Z1_16 : BP_PF_R1_16);
+  }
+}
+
+template <typename TV, typename TX, int NW, int MODE>
 static hipError_t launch_bpass_q(int qw, int grid, const BlockArgs &a, hipStream_t s) {
   constexpr int NT = NW * 64;
   switch (qw) {
-    case 1: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 1, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 2, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 4, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 8, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 1, MODE, bp_pf<TV, 1, MODE>()>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 2, MODE, bp_pf<TV, 2, MODE>()>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 4, MODE, bp_pf<TV, 4, MODE>()>), dim3(grid), dim3(NT), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_bpass<TV, TX, NW, 8, MODE, bp_pf<TV, 8, MODE>()>), dim3(grid), dim3(NT), 0, s, a); break;
     case 12:
       if constexpr (sizeof(TV) == 4 && NW == 8) {
-        hipLaunchKernelGGL((k_bpass<TV, TX, NW, 12, MODE, PREF>), dim3(grid), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_bpass<TV, TX, NW, 12, MODE, bp_pf<TV, 12, MODE>()>), dim3(grid), dim3(NT), 0, s, a);
         break;
       }
       return hipErrorInvalidValue;
     default:
       if constexpr (NW * 16 * Vec<TV>::EPL <= 512)
-        hipLaunchKernelGGL((k_bpass<TV, TX, NW, 16, MODE, false>), dim3(grid), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_bpass<TV, TX, NW, 16, MODE, bp_pf<TV, 16, MODE>()>), dim3(grid), dim3(NT), 0, s, a);
       else
         return hipErrorInvalidValue;
       break;
@@ -646,25 +687,14 @@ static hipError_t launch_bpass_q(int qw, int grid, const BlockArgs &a, hipStream
   return hipGetLastError();
 }
 
-// Prefetch only where the doubled tile fits beside the BPK accumulators (the
-// 12-group tile: not in BP_Z1, whose phase-1 values spill with it).
 template <typename TV, typename TX, int NW>
 static hipError_t launch_bpass_m(int mode, int qw, int grid, const BlockArgs &a, hipStream_t s) {
-  const bool pref = sizeof(TV) == 4 ? (qw <= 8 || (qw == 12 && mode != BP_Z1)) : qw <= 4;
   if (!block_supported(sizeof(TV) == 8, qw)) return hipErrorInvalidValue;
   switch (mode) {
-    case BP_R1:
-      return pref ? launch_bpass_q<TV, TX, NW, BP_R1, true>(qw, grid, a, s)
-                  : launch_bpass_q<TV, TX, NW, BP_R1, false>(qw, grid, a, s);
-    case BP_Z1:
-      return pref ? launch_bpass_q<TV, TX, NW, BP_Z1, true>(qw, grid, a, s)
-                  : launch_bpass_q<TV, TX, NW, BP_Z1, false>(qw, grid, a, s);
-    case BP_D:
-      return pref ? launch_bpass_q<TV, double, NW, BP_D, true>(qw, grid, a, s)
-                  : launch_bpass_q<TV, double, NW, BP_D, false>(qw, grid, a, s);
-    default:
-      return pref ? launch_bpass_q<TV, double, NW, BP_Z2, true>(qw, grid, a, s)
-                  : launch_bpass_q<TV, double, NW, BP_Z2, false>(qw, grid, a, s);
+    case BP_R1: return launch_bpass_q<TV, TX, NW, BP_R1>(qw, grid, a, s);
+    case BP_Z1: return launch_bpass_q<TV, TX, NW, BP_Z1>(qw, grid, a, s);
+    case BP_D: return launch_bpass_q<TV, double, NW, BP_D>(qw, grid, a, s);
+    default: return launch_bpass_q<TV, double, NW, BP_Z2>(qw, grid, a, s);
   }
 }
 

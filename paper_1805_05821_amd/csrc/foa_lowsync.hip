@@ -37,6 +37,7 @@
 //                   breakdown test, H_bar's column from beta, beta's column of
 //                   the new pending column, the next sweep's coefficients.
 #include "foa_device.h"
+#include "foa_tile.h"
 
 namespace foa {
 
@@ -64,18 +65,6 @@ constexpr int ls_lds_doubles() {
 template <typename TV, int NW, int QW>
 constexpr int ls_pf() {
   return sizeof(TV) == 4 && QW == 16 ? LS_PF16 : (sizeof(TV) == 4 && QW == 8 && NW < 8 ? LS_PF8 : QW);
-}
-
-// Groups [G0, G1) of a tile (16-byte loads, one per group and lane) into
-// dst[D0 + g - G0].
-template <typename TV, int G0, int G1, int D0, int D>
-__device__ __forceinline__ void ls_load_groups(__amdgpu_buffer_rsrc_t rt, unsigned goff0, unsigned gbytes,
-                                               TV (&dst)[D][Vec<TV>::EPL]) {
-#pragma unroll
-  for (int g = G0; g < G1; ++g) {
-    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rt, (int)(goff0 + g * gbytes), 0, kTileLoad);
-    unpack16<TV>(v, dst[D0 + g - G0]);
-  }
 }
 
 // One workgroup processes panels pstart, pstart + pstep, ... < pend of one
@@ -155,7 +144,7 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, int64_t pstart, in
 
   int64_t p = pstart;
   if (PF > 0 && p < pend) {
-    ls_load_groups<TV, 0, PF, 0>(make_rsrc(Wb + (size_t)p * pbytes, tile_bytes), goff0, GBYTES, t);
+    load_tile_groups<TV, 0, PF, 0>(make_rsrc(Wb + (size_t)p * pbytes, tile_bytes), goff0, GBYTES, t);
 #pragma unroll
     for (int g = 0; g < PF; ++g) {
 #pragma unroll
@@ -178,11 +167,11 @@ __device__ __forceinline__ void ls_pass_body(const LsArgs &a, int64_t pstart, in
     }
     if constexpr (PF < QW) {
       // the groups not prefetched, straight into their place
-      ls_load_groups<TV, PF, QW, PF>(make_rsrc(Wb + (size_t)p * pbytes, tile_bytes), goff0, GBYTES, t);
+      load_tile_groups<TV, PF, QW, PF>(make_rsrc(Wb + (size_t)p * pbytes, tile_bytes), goff0, GBYTES, t);
     }
     if constexpr (PF > 0) {
       const bool more = p + pstep < pend;
-      ls_load_groups<TV, 0, PF, 0>(make_rsrc(Wb + (size_t)(more ? p + pstep : p) * pbytes, more ? tile_bytes : 0u),
+      load_tile_groups<TV, 0, PF, 0>(make_rsrc(Wb + (size_t)(more ? p + pstep : p) * pbytes, more ? tile_bytes : 0u),
                                    goff0, GBYTES, tn);
     }
 
