@@ -92,8 +92,18 @@ enum { ZG_YNORM = 0, ZG_GRAM = 1, ZG_APPLY = 2, ZG_WRITEV = 3 };
 // ---------------------------------------------------------------------------
 // PF: groups of the next panel's tile loaded ahead (0 .. QW; the rest load at
 // the start of their panel).
+// Register budget as waves per SIMD: the 8-group FP32 tile of the passes
+// with one phase over the basis rows (BP_R1, BP_D) is held to 128 VGPRs, so
+// two 8-wavefront workgroups share a CU (without prefetch: measured 22%
+// faster than one workgroup with it); the others take what they need.
+template <typename TV, int QW, int MODE>
+constexpr int bp_waves() {
+  return (sizeof(TV) == 4 && (MODE == BP_R1 || MODE == BP_D) && QW == 8) ? 4 : 1;
+}
+
 template <typename TV, typename TX, int NW, int QW, int MODE, int PF>
-__global__ __launch_bounds__(NW * 64) void k_bpass(BlockArgs a) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(bp_waves<TV, QW, MODE>()))) void k_bpass(
+    BlockArgs a) {
   constexpr int EPL = Vec<TV>::EPL;
   constexpr int LPC = 64 / EPL;
   constexpr int CPW = EPL;
@@ -222,32 +232,17 @@ __global__ __launch_bounds__(NW * 64) void k_bpass(BlockArgs a) {
 #pragma unroll
           for (int e = 0; e < EPL; ++e) asm volatile("" : "+v"(t[g][e]));
       }
-      if constexpr (HAS_P1) {
-        // both phases: one row's right-hand sides at a time, which leaves
-        // registers for part of the next tile (each accumulator still takes
-        // its rows in order e = 0 .. EPL-1, as below)
+      // one row's right-hand sides at a time, which keeps fewer values live
+      // (each accumulator takes its rows in order e = 0 .. EPL-1)
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) {
-          double wr[BPK];
+      for (int e = 0; e < EPL; ++e) {
+        double wr[BPK];
 #pragma unroll
-          for (int k = 0; k < BPK; ++k) wr[k] = s_w[par][(rg * EPL + e) * BPK + k];
-#pragma unroll
-          for (int g = 0; g < QW; ++g)
-#pragma unroll
-            for (int k = 0; k < BPK; ++k) acc[g][k] = fma((double)t[g][e], wr[k], acc[g][k]);
-        }
-      } else {
-        double wr[EPL][BPK];
-#pragma unroll
-        for (int e = 0; e < EPL; ++e)
-#pragma unroll
-          for (int k = 0; k < BPK; ++k) wr[e][k] = s_w[par][(rg * EPL + e) * BPK + k];
+        for (int k = 0; k < BPK; ++k) wr[k] = s_w[par][(rg * EPL + e) * BPK + k];
 #pragma unroll
         for (int g = 0; g < QW; ++g)
 #pragma unroll
-          for (int k = 0; k < BPK; ++k)
-#pragma unroll
-            for (int e = 0; e < EPL; ++e) acc[g][k] = fma((double)t[g][e], wr[e][k], acc[g][k]);
+          for (int k = 0; k < BPK; ++k) acc[g][k] = fma((double)t[g][e], wr[k], acc[g][k]);
       }
     }
     if constexpr (PF > 0) {
@@ -634,32 +629,20 @@ __global__ __launch_bounds__(256) void k_bthird(BlockArgs a, int *gate, double u
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-#ifndef BP_PF_Z1_12
-#define BP_PF_Z1_12 6
-#endif
-#ifndef BP_PF_Z1_16
-#define BP_PF_Z1_16 0
-#endif
-#ifndef BP_PF_R1_16
-#define BP_PF_R1_16 0
-#endif
-#ifndef BP_PF_Z2_16
-#define BP_PF_Z2_16 16
-#endif
-
 // Prefetched groups of a block pass (what fits beside the BPK accumulators).
-// FP32 basis: the whole tile up to 8 groups, and in the passes with one phase
-// at 12 groups (BP_Z2 also at 16), 6 of 12 groups in BP_Z1, none at 16 groups
-// in BP_Z1 (it spills without) nor in BP_R1 / BP_D (8 of 16 fit, measured no
-// faster); FP64 basis: up to 4 groups, in BP_Z2 up to 8.
+// FP32 basis: the whole tile, except 6 of 12 groups in BP_Z1, none at 16
+// groups in BP_Z1 (it spills without), BP_R1 and BP_D (8 of 16 fit, measured
+// no faster), and none at 8 groups in BP_R1 and BP_D (their 128-VGPR budget);
+// FP64 basis: up to 4 groups, in BP_Z2 up to 8.
 template <typename TV, int QW, int MODE>
 constexpr int bp_pf() {
   if constexpr (sizeof(TV) == 8) {
     return (QW <= 4 || MODE == BP_Z2) ? QW : 0;
   } else {
+    if (QW == 8 && (MODE == BP_R1 || MODE == BP_D)) return 0;
     if (QW <= 8) return QW;
-    if (QW == 12) return MODE == BP_Z1 ? BP_PF_Z1_12 : 12;
-    return MODE == BP_Z2 ? BP_PF_Z2_16 : (MODE == BP_Z1 ? BP_PF_Z1_16 : BP_PF_R1_16);
+    if (QW == 12) return MODE == BP_Z1 ? 6 : 12;
+    return MODE == BP_Z2 ? 16 : 0;
   }
 }
 
