@@ -47,9 +47,12 @@ def _run(X, prec, static):
 def test_static_block_workspace_matches_caller_workspace():
     import torch
 
-    cases = [("f32", 300007, 44), ("f64", 50021, 22)]   # the second call is smaller
-    for prec, n, N in cases:
-        w = datagen.get_workload("noisy_2p20x200").with_n(n).with_N(N)
+    # each call smaller than the one before; the last one, noise-floor snapshots
+    # at small n, takes the third projection in many of its blocks
+    cases = [("f32", 300007, 44, "noisy_2p20x200"), ("f64", 50021, 22, "noisy_2p20x200"),
+             ("f32", 5000, 400, "noisy_2p24x500")]
+    for prec, n, N, name in cases:
+        w = datagen.get_workload(name).with_n(n).with_N(N)
         Xh, _, _ = datagen.snapshots_numpy(w)
         X = torch.from_numpy(np.ascontiguousarray(Xh.T)).cuda()
         announce(f"blocked push, prec={prec} n={n} N={N}: caller workspace, then static workspace")
