@@ -70,8 +70,9 @@ hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const vo
   a.G = (int)std::min<int64_t>({(int64_t)c->L.ldg, c->L.P, (int64_t)2 * c->cus});
   a.Gz = (int)std::min<int64_t>(kGramGrid, std::max<int64_t>(1, (c->L.P * PANEL + 255) / 256));
   // FP32 basis: a 12-group tile for 257-384 columns (the 16-group one is up to
-  // a half empty there; the blocked run measured 4-7% faster)
-  const int qw = (!v64 && j > 256 && j <= 384) ? 12 : pick_qw(j, 32);
+  // a half empty there; the blocked run measured 4-7% faster) and a 14-group
+  // one for 385-448 (the 16-group both-phase sweep spills)
+  const int qw = (!v64 && j > 256 && j <= 384) ? 12 : ((!v64 && j > 384 && j <= 448) ? 14 : pick_qw(j, 32));
   hipStream_t s = c->stream;
   hipError_t e;
   if ((e = launch_zgram(0, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // ||y_k||^2

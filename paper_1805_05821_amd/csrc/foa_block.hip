@@ -630,10 +630,11 @@ __global__ __launch_bounds__(256) void k_bthird(BlockArgs a, int *gate, double u
 // Launchers
 // ---------------------------------------------------------------------------
 // Prefetched groups of a block pass (what fits beside the BPK accumulators).
-// FP32 basis: the whole tile, except 6 of 12 groups in BP_Z1, none at 16
-// groups in BP_Z1 (it spills without), BP_R1 and BP_D (8 of 16 fit, measured
-// no faster), and none at 8 groups in BP_R1 and BP_D (their 128-VGPR budget);
-// FP64 basis: up to 4 groups, in BP_Z2 up to 8.
+// FP32 basis: the whole tile, except 6 of 12 groups in BP_Z1, none at 14 and
+// 16 groups in BP_Z1, BP_R1 and BP_D (the 16-group BP_Z1 spills even without;
+// 2 of 14 in BP_Z1 and 8 of 14 or 16 in BP_R1 fit and were no faster), and
+// none at 8 groups in BP_R1 and BP_D (their 128-VGPR budget); FP64 basis: up
+// to 4 groups, in BP_Z2 up to 8.
 template <typename TV, int QW, int MODE>
 constexpr int bp_pf() {
   if constexpr (sizeof(TV) == 8) {
@@ -642,7 +643,7 @@ constexpr int bp_pf() {
     if (QW == 8 && (MODE == BP_R1 || MODE == BP_D)) return 0;
     if (QW <= 8) return QW;
     if (QW == 12) return MODE == BP_Z1 ? 6 : 12;
-    return MODE == BP_Z2 ? 16 : 0;
+    return MODE == BP_Z2 ? QW : 0;  // 14 and 16 groups
   }
 }
 
@@ -657,6 +658,12 @@ static hipError_t launch_bpass_q(int qw, int grid, const BlockArgs &a, hipStream
     case 12:
       if constexpr (sizeof(TV) == 4 && NW == 8) {
         hipLaunchKernelGGL((k_bpass<TV, TX, NW, 12, MODE, bp_pf<TV, 12, MODE>()>), dim3(grid), dim3(NT), 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
+    case 14:
+      if constexpr (sizeof(TV) == 4 && NW == 8) {
+        hipLaunchKernelGGL((k_bpass<TV, TX, NW, 14, MODE, bp_pf<TV, 14, MODE>()>), dim3(grid), dim3(NT), 0, s, a);
         break;
       }
       return hipErrorInvalidValue;
