@@ -298,18 +298,37 @@ __global__ __launch_bounds__(256) void k_zgram(BlockArgs a) {
 #pragma unroll
     for (int l = 0; l < BPK; ++l) g[k][l] = 0.0;
   const int64_t npad = a.P * PANEL;
-  for (int64_t r = (int64_t)blockIdx.x * 256 + tid; r < npad; r += (int64_t)gridDim.x * 256) {
+  if constexpr (MODE == ZG_YNORM) {
+    // the snapshots' rows, four grid strides in flight per thread (each sum
+    // still takes its rows in the order of the plain loop below)
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const TX *x = static_cast<const TX *>(a.x);
+    int64_t r = (int64_t)blockIdx.x * 256 + tid;
+    for (; r + 3 * stride < a.n; r += 4 * stride) {
+      double v[4][BPK];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < BPK; ++k) v[u][k] = (double)x[(int64_t)k * a.ldx + r + u * stride];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int k = 0; k < BPK; ++k) g[k][k] = fma(v[u][k], v[u][k], g[k][k]);
+    }
+    for (; r < a.n; r += stride) {
+#pragma unroll
+      for (int k = 0; k < BPK; ++k) {
+        const double v = (double)x[(int64_t)k * a.ldx + r];
+        g[k][k] = fma(v, v, g[k][k]);
+      }
+    }
+  }
+  // the other passes take one row per grid stride (four in flight, as for
+  // the snapshots above, measured 6-12% slower here)
+  for (int64_t r = (int64_t)blockIdx.x * 256 + tid; MODE != ZG_YNORM && r < npad; r += (int64_t)gridDim.x * 256) {
     const int64_t p = r / PANEL;
     const int rr = (int)(r % PANEL);
     double z[BPK];
-    if (MODE == ZG_YNORM) {
-#pragma unroll
-      for (int k = 0; k < BPK; ++k)
-        z[k] = r < a.n ? (double)static_cast<const TX *>(a.x)[(int64_t)k * a.ldx + r] : 0.0;
-#pragma unroll
-      for (int k = 0; k < BPK; ++k) g[k][k] = fma(z[k], z[k], g[k][k]);
-      continue;
-    }
     double *zr = a.Z + p * PANEL * BPK + rr;
 #pragma unroll
     for (int k = 0; k < BPK; ++k) z[k] = zr[k * PANEL];
