@@ -412,6 +412,40 @@ __global__ __launch_bounds__(256) void k_breduce(BlockArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// The Gram partials of the workgroups of a block pass, reduced in a fixed
+// order into sG[0 .. GSLOT): thread t sums entry t % GSLOT over the slots
+// t / GSLOT, + 16, + 32, ... (eight interleaved sums, so eight loads are in
+// flight, then added in order); the 16 partial sums of an entry are then
+// added in slot order.  One workgroup of 256 threads; sG is complete on
+// return.
+// ---------------------------------------------------------------------------
+static_assert(GSLOT == 16, "256 threads as 16 entries x 16 slot lanes");
+__device__ inline void gram_reduce(const BlockArgs &a, int tid, double *sh, double *sG) {
+  constexpr int SL = 256 / GSLOT;  // slot lanes per entry
+  const int e = tid % GSLOT, s0 = tid / GSLOT;
+  double t8[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) t8[m] = 0.0;
+  int g = s0;
+  for (; g + 7 * SL < a.Gz; g += 8 * SL) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) t8[m] += a.partg[(size_t)(g + m * SL) * GSLOT + e];
+  }
+  double t = 0.0;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) t += t8[m];
+  for (; g < a.Gz; g += SL) t += a.partg[(size_t)g * GSLOT + e];
+  sh[tid] = t;
+  __syncthreads();
+  if (tid < GSLOT) {
+    double v = 0.0;
+    for (int j = 0; j < 256 / GSLOT; ++j) v += sh[j * GSLOT + tid];
+    sG[tid] = v;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // Cholesky step ROUND (0: shifted) of the block QR: reduce the Gram partials
 // (fixed order), factor G (+ s I) = S^T S, store T = S^{-1} and accumulate
 // S_total = S S_total.  A non-finite Gram matrix or a non-positive pivot
@@ -423,13 +457,7 @@ __global__ __launch_bounds__(256) void k_bchol(BlockArgs a) {
   __shared__ double sh[256];
   __shared__ double sG[GSLOT];
   const int tid = threadIdx.x;
-  for (int e = 0; e < GSLOT; ++e) {
-    double t = 0.0;
-    for (int g = tid; g < a.Gz; g += 256) t += a.partg[(size_t)g * GSLOT + e];
-    const double s = block_sum_256(t, sh);
-    if (tid == 0) sG[e] = s;
-  }
-  __syncthreads();
+  gram_reduce(a, tid, sh, sG);
   if (tid != 0) return;
   double G[BPK][BPK], S[BPK][BPK], T[BPK][BPK];
   bool ok = true;
@@ -605,6 +633,7 @@ __global__ void k_bflag_clear(int *flag) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_bthird(BlockArgs a, int *gate, double unit) {
   __shared__ double sh[256];
+  __shared__ double sG[GSLOT];
   __shared__ double s_z2[BPK], s_r2[BPK];
   const int tid = threadIdx.x;
   if (a.st->status != ST_ACTIVE || *a.flag) {
@@ -629,11 +658,10 @@ __global__ __launch_bounds__(256) void k_bthird(BlockArgs a, int *gate, double u
   for (int k = 0; k < BPK; ++k) {
     const double v = block_sum_256(r2k[k], sh);
     if (tid == 0) s_r2[k] = v;
-    double z = 0.0;
-    for (int g = tid; g < a.Gz; g += 256) z += a.partg[(size_t)g * GSLOT + k * BPK + k];
-    const double zs = block_sum_256(z, sh);
-    if (tid == 0) s_z2[k] = zs;
   }
+  gram_reduce(a, tid, sh, sG);
+  if (tid < BPK) s_z2[tid] = sG[tid * BPK + tid];
+  __syncthreads();
   if (tid != 0) return;
   int third = 0;
   if (r1s > 0.0) {
