@@ -14,7 +14,10 @@ using namespace foa;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kGramGrid = 1024;  // workgroups of the block Gram passes (partial slots)
+constexpr int kGramGrid = 1024;
+#ifndef BP_NARROW_COLS
+#define BP_NARROW_COLS 128
+#endif  // workgroups of the block Gram passes (partial slots)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -67,20 +70,26 @@ hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const vo
   a.ldg = c->L.ldg;
   a.ldH = c->L.ldH;
   a.ldB = c->L.ldB;
-  a.G = (int)std::min<int64_t>({(int64_t)c->L.ldg, c->L.P, (int64_t)2 * c->cus});
+  // FP32 basis up to 128 columns: 4-wavefront workgroups, four per CU (the
+  // panels carry little data and the per-panel chain of barriers and LDS
+  // round trips dominates; smaller independent workgroups overlap it)
+  const bool narrow = !v64 && j <= BP_NARROW_COLS;
+  const int nw = v64 ? 16 : (narrow ? 4 : 8);
+  a.G = (int)std::min<int64_t>({(int64_t)c->L.ldg, c->L.P, (int64_t)(narrow ? 4 : 2) * c->cus});
   a.Gz = (int)std::min<int64_t>(kGramGrid, std::max<int64_t>(1, (c->L.P * PANEL + 255) / 256));
   // FP32 basis: a 12-group tile for 257-384 columns (the 16-group one is up to
   // a half empty there; the blocked run measured 4-7% faster) and a 14-group
   // one for 385-448 (the 16-group both-phase sweep spills)
-  const int qw = (!v64 && j > 256 && j <= 384) ? 12 : ((!v64 && j > 384 && j <= 448) ? 14 : pick_qw(j, 32));
+  const int qw = narrow ? pick_qw(j, 16)
+                        : ((!v64 && j > 256 && j <= 384) ? 12 : ((!v64 && j > 384 && j <= 448) ? 14 : pick_qw(j, 32)));
   hipStream_t s = c->stream;
   hipError_t e;
   if ((e = launch_zgram(0, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // ||y_k||^2
-  if ((e = launch_bpass(0, v64, x64, qw, a.G, a, s)) != hipSuccess) return e;       // D = W^T Y
+  if ((e = launch_bpass(0, v64, x64, nw, qw, a.G, a, s)) != hipSuccess) return e;       // D = W^T Y
   if ((e = launch_breduce(1, a, s)) != hipSuccess) return e;                         // R1, coef
-  if ((e = launch_bpass(1, v64, x64, qw, a.G, a, s)) != hipSuccess) return e;       // Z = Y - W C, D
+  if ((e = launch_bpass(1, v64, x64, nw, qw, a.G, a, s)) != hipSuccess) return e;       // Z = Y - W C, D
   if ((e = launch_breduce(2, a, s)) != hipSuccess) return e;                         // R2, R += R2, coef
-  if ((e = launch_bpass(2, v64, true, qw, a.G, a, s)) != hipSuccess) return e;      // Z = Z - W C
+  if ((e = launch_bpass(2, v64, true, nw, qw, a.G, a, s)) != hipSuccess) return e;      // Z = Z - W C
   if ((e = launch_zgram(1, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // Z^T Z
   // third projection, where the test asks for it (the gated kernels return
   // at once otherwise)
@@ -88,9 +97,9 @@ hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const vo
   if ((e = launch_bthird(a, gate, v64 ? 0x1p-53 : 0x1p-24, s)) != hipSuccess) return e;
   BlockArgs g = a;
   g.gate = gate;
-  if ((e = launch_bpass(3, v64, true, qw, g.G, g, s)) != hipSuccess) return e;      // D = W^T Z
+  if ((e = launch_bpass(3, v64, true, nw, qw, g.G, g, s)) != hipSuccess) return e;      // D = W^T Z
   if ((e = launch_breduce(3, g, s)) != hipSuccess) return e;                         // R3, R += R3, coef
-  if ((e = launch_bpass(2, v64, true, qw, g.G, g, s)) != hipSuccess) return e;      // Z = Z - W C
+  if ((e = launch_bpass(2, v64, true, nw, qw, g.G, g, s)) != hipSuccess) return e;      // Z = Z - W C
   if ((e = launch_zgram(1, v64, x64, g.Gz, g, s)) != hipSuccess) return e;          // Z^T Z
   if ((e = launch_bchol(0, a, s)) != hipSuccess) return e;                           // shifted
   if ((e = launch_zgram(2, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // Z T0, Gram

@@ -740,10 +740,14 @@ static hipError_t launch_bpass_m(int mode, int qw, int grid, const BlockArgs &a,
 // run one snapshot at a time).
 bool block_supported(bool tv_f64, int qw) { return !tv_f64 || qw <= 8; }
 
-hipError_t launch_bpass(int mode, bool tv_f64, bool tx_f64, int qw, int grid, const BlockArgs &a, hipStream_t s) {
+hipError_t launch_bpass(int mode, bool tv_f64, bool tx_f64, int nw, int qw, int grid, const BlockArgs &a,
+                        hipStream_t s) {
   if (tv_f64)
     return tx_f64 ? launch_bpass_m<double, double, 16>(mode, qw, grid, a, s)
                   : launch_bpass_m<double, float, 16>(mode, qw, grid, a, s);
+  if (nw == 4)
+    return tx_f64 ? launch_bpass_m<float, double, 4>(mode, qw, grid, a, s)
+                  : launch_bpass_m<float, float, 4>(mode, qw, grid, a, s);
   return tx_f64 ? launch_bpass_m<float, double, 8>(mode, qw, grid, a, s)
                 : launch_bpass_m<float, float, 8>(mode, qw, grid, a, s);
 }

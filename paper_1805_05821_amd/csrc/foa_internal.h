@@ -237,7 +237,8 @@ hipError_t launch_pass(int mode, bool tv_f64, bool tx_f64, bool prefetch, int nw
                        const PassArgs &a, hipStream_t s);
 // blocked form (foa_block.hip)
 bool block_supported(bool tv_f64, int qw);
-hipError_t launch_bpass(int mode, bool tv_f64, bool tx_f64, int qw, int grid, const BlockArgs &a, hipStream_t s);
+hipError_t launch_bpass(int mode, bool tv_f64, bool tx_f64, int nw, int qw, int grid, const BlockArgs &a,
+                        hipStream_t s);
 hipError_t launch_zgram(int mode, bool tv_f64, bool tx_f64, int grid, const BlockArgs &a, hipStream_t s);
 hipError_t launch_breduce(int mode, const BlockArgs &a, hipStream_t s);
 hipError_t launch_bchol(int round, const BlockArgs &a, hipStream_t s);
