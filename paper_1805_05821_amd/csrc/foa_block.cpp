@@ -14,10 +14,9 @@ using namespace foa;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kGramGrid = 1024;
-#ifndef BP_NARROW_COLS
-#define BP_NARROW_COLS 128
-#endif  // workgroups of the block Gram passes (partial slots)
+constexpr int kGramGrid = 1024;    // workgroups of the block Gram passes (partial slots)
+constexpr int kBlockSlots = 1024;  // partial slots of the block passes (their largest grid)
+constexpr int kNarrowCols = 128;   // FP32 basis sizes that take 4-wavefront block passes
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -67,15 +66,15 @@ hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const vo
   a.P = c->L.P;
   a.j = j;
   a.n_max = c->n_max;
-  a.ldg = c->L.ldg;
+  a.ldg = kBlockSlots;
   a.ldH = c->L.ldH;
   a.ldB = c->L.ldB;
   // FP32 basis up to 128 columns: 4-wavefront workgroups, four per CU (the
   // panels carry little data and the per-panel chain of barriers and LDS
   // round trips dominates; smaller independent workgroups overlap it)
-  const bool narrow = !v64 && j <= BP_NARROW_COLS;
+  const bool narrow = !v64 && j <= kNarrowCols;
   const int nw = v64 ? 16 : (narrow ? 4 : 8);
-  a.G = (int)std::min<int64_t>({(int64_t)c->L.ldg, c->L.P, (int64_t)(narrow ? 4 : 2) * c->cus});
+  a.G = (int)std::min<int64_t>({(int64_t)kBlockSlots, c->L.P, (int64_t)(narrow ? 4 : 2) * c->cus});
   a.Gz = (int)std::min<int64_t>(kGramGrid, std::max<int64_t>(1, (c->L.P * PANEL + 255) / 256));
   // FP32 basis: a 12-group tile for 257-384 columns (the 16-group one is up to
   // a half empty there; the blocked run measured 4-7% faster) and a 14-group
@@ -124,7 +123,7 @@ foa_status foa_block_workspace_bytes(int64_t n, int32_t n_max, foa_prec prec, si
   if (!bytes || n < 1 || n_max < 1 || n_max > FOA_MAX_CAPACITY ||
       (prec != FOA_PREC_F32 && prec != FOA_PREC_F64))
     return FOA_E_ARG;
-  *bytes = block_layout(n, n_max, kStreamSlots).total;
+  *bytes = block_layout(n, n_max, kBlockSlots).total;
   return FOA_OK;
 }
 
@@ -134,7 +133,7 @@ foa_status foa_push_blocked(foa_ctx c, const void *d_X, int64_t ld, int32_t p, f
   if (!d_X || (x_dtype != FOA_F32 && x_dtype != FOA_F64) || p < 0 || (p > 0 && ld < c->n) || !d_bws)
     return set_err(c, FOA_E_ARG, "bad blocked-push arguments");
   if (c->is_view) return set_err(c, FOA_E_STATE, "blocked pushes go to a single stream, not a batch view");
-  const BlockLayout L = block_layout(c->n, c->n_max, c->L.ldg);
+  const BlockLayout L = block_layout(c->n, c->n_max, kBlockSlots);
   if (bws_bytes < L.total || reinterpret_cast<uintptr_t>(d_bws) % kAlign)
     return set_err(c, FOA_E_NOMEM, "block workspace of %zu bytes needed", L.total);
   return push_blocked_impl(c, d_X, ld, p, x_dtype, static_cast<char *>(d_bws), L);
@@ -145,7 +144,7 @@ foa_status foa_push_blocked_static(foa_ctx c, const void *d_X, int64_t ld, int32
   if (!d_X || (x_dtype != FOA_F32 && x_dtype != FOA_F64) || p < 0 || (p > 0 && ld < c->n))
     return set_err(c, FOA_E_ARG, "bad blocked-push arguments");
   if (c->is_view) return set_err(c, FOA_E_STATE, "blocked pushes go to a single stream, not a batch view");
-  const BlockLayout L = block_layout(c->n, c->n_max, c->L.ldg);
+  const BlockLayout L = block_layout(c->n, c->n_max, kBlockSlots);
   if (L.total > FOA_BLOCK_STATIC_BYTES)
     return set_err(c, FOA_E_NOMEM,
                    "the static block workspace holds %zu bytes; this stream needs %zu (n or n_max too large)",
