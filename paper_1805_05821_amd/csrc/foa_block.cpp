@@ -100,12 +100,18 @@ hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const vo
   if ((e = launch_breduce(3, g, s)) != hipSuccess) return e;                         // R3, R += R3, coef
   if ((e = launch_bpass(2, v64, true, nw, qw, g.G, g, s)) != hipSuccess) return e;      // Z = Z - W C
   if ((e = launch_zgram(1, v64, x64, g.Gz, g, s)) != hipSuccess) return e;          // Z^T Z
-  if ((e = launch_bchol(0, a, s)) != hipSuccess) return e;                           // shifted
-  if ((e = launch_zgram(2, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // Z T0, Gram
-  if ((e = launch_bchol(1, a, s)) != hipSuccess) return e;
-  if ((e = launch_zgram(2, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // Z T1, Gram
-  if ((e = launch_bchol(1, a, s)) != hipSuccess) return e;
-  if ((e = launch_zgram(3, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // V <- Z T2
+  // shifted CholeskyQR3: each Gram pass forms Z T_0 .. T_{t-1} row by row
+  // from the unchanged Z, the last one writes Z T_0 T_1 T_2 into V
+  BlockArgs q = a;
+  if ((e = launch_bchol(0, a, s)) != hipSuccess) return e;                           // shifted: T_0
+  q.tlev = 1;
+  if ((e = launch_zgram(1, v64, x64, q.Gz, q, s)) != hipSuccess) return e;          // Gram of Z T_0
+  if ((e = launch_bchol(1, a, s)) != hipSuccess) return e;                           // T_1
+  q.tlev = 2;
+  if ((e = launch_zgram(1, v64, x64, q.Gz, q, s)) != hipSuccess) return e;          // Gram of Z T_0 T_1
+  if ((e = launch_bchol(2, a, s)) != hipSuccess) return e;                           // T_2
+  q.tlev = 3;
+  if ((e = launch_zgram(2, v64, x64, q.Gz, q, s)) != hipSuccess) return e;          // V <- Z T_0 T_1 T_2
   if ((e = launch_bcommit(a, s)) != hipSuccess) return e;
   SmallArgs sa = c->sa;
   sa.j = j + BPK;  // nextb sizes its grid from j + 1 and reads the committed q itself

@@ -79,7 +79,7 @@ hipError_t block_static_scratch(int device, char **ptr) {
 
 enum { BP_R1 = 0, BP_Z1 = 1, BP_Z2 = 2, BP_D = 3 };
 bool block_supported(bool tv_f64, int qw);
-enum { ZG_YNORM = 0, ZG_GRAM = 1, ZG_APPLY = 2, ZG_WRITEV = 3 };
+enum { ZG_YNORM = 0, ZG_GRAM = 1, ZG_WRITEV = 2 };
 
 // ---------------------------------------------------------------------------
 // Block row pass.  MODE BP_R1: D = W^T Y (column sums only).  BP_Z1:
@@ -275,10 +275,14 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(bp_wave
 
 // ---------------------------------------------------------------------------
 // Passes over the n x BPK block, one thread per row (rows grid-strided).
-// ZG_YNORM: partial ||y_k||^2 of the snapshots.  ZG_GRAM: partial Z^T Z.
-// ZG_APPLY: Z <- Z T (T upper triangular) and the partial Gram of the result.
-// ZG_WRITEV: V's columns j .. j+BPK-1 <- Z T, rounded to the storage type.
-// Partials: partg[slot * GSLOT + (k * BPK + l)], slot = workgroup.
+// ZG_YNORM: partial ||y_k||^2 of the snapshots.  ZG_GRAM: the partial Gram
+// matrix of Z T_0 .. T_{tlev-1} (T_t upper triangular, the inverses of the
+// Cholesky steps so far), formed row by row from Z, which is never
+// rewritten: the products are those a pass that stored Z T_0, then read it
+// back for T_1, ... would form, in the same order, without the write streams.
+// ZG_WRITEV: V's columns j .. j+BPK-1 <- Z T_0 T_1 T_2, rounded to the
+// storage type.  Partials: partg[slot * GSLOT + (k * BPK + l)], slot =
+// workgroup.
 // ---------------------------------------------------------------------------
 constexpr int GSLOT = BPK * BPK;
 
@@ -286,10 +290,11 @@ template <typename TV, typename TX, int MODE>
 __global__ __launch_bounds__(256) void k_zgram(BlockArgs a) {
   if (a.st->status != ST_ACTIVE || *a.flag || (a.gate && !*a.gate)) return;
   __shared__ double sh[256];
-  __shared__ double sT[BPK * BPK];
+  __shared__ double sT[3 * BPK * BPK];
   const int tid = threadIdx.x;
-  if (MODE == ZG_APPLY || MODE == ZG_WRITEV) {
-    if (tid < BPK * BPK) sT[tid] = a.sm[SM_T + tid];
+  const int tlev = a.tlev;
+  if (MODE != ZG_YNORM && tlev > 0) {
+    if (tid < tlev * BPK * BPK) sT[tid] = a.sm[SM_T + tid];
     __syncthreads();
   }
   double g[BPK][BPK];
@@ -329,16 +334,17 @@ __global__ __launch_bounds__(256) void k_zgram(BlockArgs a) {
     const int64_t p = r / PANEL;
     const int rr = (int)(r % PANEL);
     double z[BPK];
-    double *zr = a.Z + p * PANEL * BPK + rr;
+    const double *zr = a.Z + p * PANEL * BPK + rr;
 #pragma unroll
     for (int k = 0; k < BPK; ++k) z[k] = zr[k * PANEL];
-    if (MODE == ZG_APPLY || MODE == ZG_WRITEV) {
+    for (int t = 0; t < tlev; ++t) {  // z <- z T_t
+      const double *T = sT + t * BPK * BPK;
       double o[BPK];
 #pragma unroll
       for (int l = 0; l < BPK; ++l) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k <= l; ++k) s = fma(z[k], sT[k * BPK + l], s);  // T[k][l], k <= l
+        for (int k = 0; k <= l; ++k) s = fma(z[k], T[k * BPK + l], s);  // T[k][l], k <= l
         o[l] = s;
       }
 #pragma unroll
@@ -349,10 +355,6 @@ __global__ __launch_bounds__(256) void k_zgram(BlockArgs a) {
 #pragma unroll
       for (int k = 0; k < BPK; ++k) vc[k * PANEL] = (TV)z[k];
       continue;
-    }
-    if (MODE == ZG_APPLY) {
-#pragma unroll
-      for (int k = 0; k < BPK; ++k) zr[k * PANEL] = z[k];
     }
 #pragma unroll
     for (int k = 0; k < BPK; ++k)
@@ -446,9 +448,9 @@ __device__ inline void gram_reduce(const BlockArgs &a, int tid, double *sh, doub
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky step ROUND (0: shifted) of the block QR: reduce the Gram partials
-// (fixed order), factor G (+ s I) = S^T S, store T = S^{-1} and accumulate
-// S_total = S S_total.  A non-finite Gram matrix or a non-positive pivot
+// Cholesky step ROUND (0: shifted; 0, 1, 2) of the block QR: reduce the Gram
+// partials (fixed order), factor G (+ s I) = S^T S, store T_ROUND = S^{-1}
+// and accumulate S_total = S S_total.  A non-finite Gram matrix or a non-positive pivot
 // rejects the block.  One workgroup; the 4 x 4 algebra runs in thread 0.
 // ---------------------------------------------------------------------------
 template <int ROUND>
@@ -517,7 +519,7 @@ __global__ __launch_bounds__(256) void k_bchol(BlockArgs a) {
   for (int k = 0; k < BPK; ++k)
     for (int l = 0; l < BPK; ++l) {
       Stot[k * BPK + l] = P[k][l];
-      a.sm[SM_T + k * BPK + l] = T[k][l];
+      a.sm[SM_T + ROUND * GSLOT + k * BPK + l] = T[k][l];
     }
 }
 
@@ -757,7 +759,6 @@ static hipError_t launch_zgram_t(int mode, int grid, const BlockArgs &a, hipStre
   switch (mode) {
     case ZG_YNORM: hipLaunchKernelGGL((k_zgram<TV, TX, ZG_YNORM>), dim3(grid), dim3(256), 0, s, a); break;
     case ZG_GRAM: hipLaunchKernelGGL((k_zgram<TV, TX, ZG_GRAM>), dim3(grid), dim3(256), 0, s, a); break;
-    case ZG_APPLY: hipLaunchKernelGGL((k_zgram<TV, TX, ZG_APPLY>), dim3(grid), dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL((k_zgram<TV, TX, ZG_WRITEV>), dim3(grid), dim3(256), 0, s, a); break;
   }
   return hipGetLastError();
@@ -784,8 +785,10 @@ hipError_t launch_breduce(int mode, const BlockArgs &a, hipStream_t s) {
 hipError_t launch_bchol(int round, const BlockArgs &a, hipStream_t s) {
   if (round == 0)
     hipLaunchKernelGGL(k_bchol<0>, dim3(1), dim3(256), 0, s, a);
-  else
+  else if (round == 1)
     hipLaunchKernelGGL(k_bchol<1>, dim3(1), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_bchol<2>, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

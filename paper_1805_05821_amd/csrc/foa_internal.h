@@ -163,13 +163,13 @@ constexpr int kCtlInts = kCtlGroup0 + kCtlGroupStride * kMaxGroups;
 // ---- blocked form ------------------------------------------------------------
 constexpr int BPK = 4;  // snapshots per block
 // small-area offsets (doubles): R = R1 + R2 (+ R3) (n_max x BPK,
-// [c * BPK + k]), ||y_k||^2, S_total and T (BPK x BPK, row-major), R2 alone
-// (the test for a third projection)
+// [c * BPK + k]), ||y_k||^2, S_total and T_0 .. T_2 (BPK x BPK, row-major),
+// R2 alone (the test for a third projection)
 constexpr int SM_R = 0;
 constexpr int SM_YN2 = SM_R + 512 * BPK;
 constexpr int SM_S = SM_YN2 + BPK;
-constexpr int SM_T = SM_S + BPK * BPK;
-constexpr int SM_R2 = SM_T + BPK * BPK;
+constexpr int SM_T = SM_S + BPK * BPK;       // T_0, T_1, T_2: the Cholesky steps' inverses
+constexpr int SM_R2 = SM_T + 3 * BPK * BPK;
 constexpr int SM_TOTAL = SM_R2 + 512 * BPK;
 struct BlockArgs {
   void *W;          // stored basis (panel layout)
@@ -182,6 +182,7 @@ struct BlockArgs {
   double *sm;       // small area (SM_* offsets)
   int *flag;        // nonzero: the block (or an earlier one) was rejected
   const int *gate;  // non-null: the kernel runs only while *gate is nonzero (third projection)
+  int tlev;         // block passes: triangular factors T_0 .. T_{tlev-1} applied to each row of Z
   DevState *st;
   double *H, *beta, *sigma;
   int64_t n, P;
