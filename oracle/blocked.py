@@ -29,7 +29,9 @@ above the breakdown threshold of the sequential form (tol * ||X_1^{q+k}||_F)
 and the three Cholesky factorisations succeed; otherwise its snapshots are
 taken one at a time by the sequential oracle (foa.py), which applies the
 paper's breakdown and non-finite rules.  The first snapshot (its
-normalisation in Algorithm 1) is always taken by the sequential oracle.
+normalisation in Algorithm 1) is always taken by the sequential oracle, and
+so are the (N - 1) mod p snapshots after it that do not fill a block: first,
+while the basis is smallest.
 
 With storage="f32" every stored column of V is rounded to FP32 once it is
 final (the FP32 basis of the device form); all arithmetic stays FP64.  Two
@@ -168,6 +170,12 @@ def foa_blocked(X, p=PB, tol=None, capacity=None, storage="f64"):
     foa.foa_stream_update(st, X[:, :1])
     round_new_columns(st, 0, storage)
     k = 1
+    lead = (N - k) % p
+    if lead and st.status == foa.ACTIVE:
+        q0 = st.q
+        foa.foa_stream_update(st, X[:, k:k + lead])
+        round_new_columns(st, q0, storage)
+        k += lead
     while k < N:
         q0 = st.q
         if (st.status == foa.ACTIVE and k + p <= N and st.q + p <= cap

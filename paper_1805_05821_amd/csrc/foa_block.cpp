@@ -190,6 +190,14 @@ foa_status push_blocked_impl(foa_ctx_s *c, const void *d_X, int64_t ld, int32_t 
     ++k;
     if ((r = sync_state(c)) != FOA_OK) return r;
   }
+  // the part that does not fill whole blocks goes first, one snapshot at a
+  // time, while the basis is smallest (a single push sweeps it three times)
+  const int lead = (p - k) % BPK;
+  if (lead > 0 && c->dev_status == ST_ACTIVE) {
+    for (int i = 0; i < lead; ++i, ++k)
+      if ((r = push_one(k)) != FOA_OK) return r;
+    if ((r = sync_state(c)) != FOA_OK) return r;
+  }
   const bool v64 = c->prec == FOA_PREC_F64;
   while (k < p) {
     if (c->dev_status != ST_ACTIVE) break;

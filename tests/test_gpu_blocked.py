@@ -2,7 +2,7 @@
 the C ABI: against the blocked oracle (same algorithm, different summation
 order), against the sequential oracle within the O(eps kappa) bounds, and the
 fallbacks (breakdown, non-finite snapshots, an FP64 basis above 256 columns,
-trailing snapshots)."""
+the snapshots of a call that do not fill a block)."""
 
 import numpy as np
 import pytest
@@ -134,7 +134,7 @@ def test_blocked_exact_rank_breakdown():
 
 
 def test_blocked_mixed_with_single_pushes():
-    """Single pushes, blocked pushes and a trailing part of fewer than 4, in
+    """Single pushes, blocked pushes and parts of fewer than 4, in
     any order, continue one factorisation; FP32 snapshots."""
     import torch
 

@@ -180,6 +180,12 @@ def _foa_blocked(M, X, p, tol, capacity, storage):
     ofoa.foa_stream_update(st, X[:, :1])
     M.round_new_columns(st, 0, storage)
     k = 1
+    lead = (N - k) % p
+    if lead and st.status == ofoa.ACTIVE:
+        q0 = st.q
+        ofoa.foa_stream_update(st, X[:, k:k + lead])
+        M.round_new_columns(st, q0, storage)
+        k += lead
     while k < N:
         q0 = st.q
         if (st.status == ofoa.ACTIVE and k + p <= N and st.q + p <= cap
