@@ -12,9 +12,10 @@ q = 0.  The headline form stores the basis in FP32 with FP64 accumulation
 beside it, with the FP32-vs-FP64 error and kappa_2.
 
 Further legs (each reported in its own object of the JSON line): the blocked
-form on the same snapshots (4 snapshots per sweep of the basis), the batched
-form on batched_256 (256 streams, one graph launch per step), the n = 1e8
-run with its FP32-MFMA mode reconstruction, and the CPU oracle on a sample.
+form on the same snapshots (4 snapshots per sweep of the basis; FP32 and FP64
+basis), the batched form on batched_256 (256 streams, one graph launch per
+step), the n = 1e8 run with its FP32-MFMA mode reconstruction, and the CPU
+oracle on a sample.
 
 Output: one JSON line on stdout; progress on stderr.
 """
@@ -31,6 +32,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 EPS32 = 2.0 ** -23
+EPS64 = 2.0 ** -52
 
 
 def log(*a):
@@ -771,6 +773,23 @@ def main():
             out["blocked_form"] = blk
         except Exception as e:  # reported, never silently dropped
             out["blocked_form"] = {"error": f"{type(e).__name__}: {e}"}
+        if r64 is not None:
+            # FP64 basis: above 256 columns its row passes go over two column windows
+            try:
+                rb = run_blocked("f64", X, n, N, args.warmup, args.steps)
+                m = min(rb["m"], r64["m"])
+                Hb, H64 = rb["H"][:m, :m], r64["H"][:m, :m]
+                eH = float(np.linalg.norm(Hb - H64, 2) / np.linalg.norm(H64, 2))
+                kap = out["error_f32_vs_f64"]["kappa2"]
+                out["blocked_form_f64"] = {
+                    "form": "fp64-basis, blocked (4 snapshots per basis sweep, column windows above 256)",
+                    "value": round(N / (rb["ms_per_step"] / 1e3), 3), "unit": "snapshots/s",
+                    "ms_per_step": round(rb["ms_per_step"], 3), "q": rb["q"],
+                    "speedup_vs_sequential_f64": round(r64["ms_per_step"] / rb["ms_per_step"], 3),
+                    "error_vs_f64_sequential": {"rel_H_2norm": eH, "bound_10_q_eps64_kappa": 10 * N * EPS64 * kap,
+                                                "within_bound": bool(eH <= 10 * N * EPS64 * kap)}}
+            except Exception as e:  # reported, never silently dropped
+                out["blocked_form_f64"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_indicators:
         try:
             out["indicator_log"] = run_indicator_log(X, n, N, args.indicator_every)

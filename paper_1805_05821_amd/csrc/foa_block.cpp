@@ -17,6 +17,7 @@ constexpr size_t kAlign = 256;
 constexpr int kGramGrid = 1024;    // workgroups of the block Gram passes (partial slots)
 constexpr int kBlockSlots = 1024;  // partial slots of the block passes (their largest grid)
 constexpr int kNarrowCols = 128;   // FP32 basis sizes that take 4-wavefront block passes
+constexpr int kWindowCols = 256;   // widest column window of an FP64-basis block pass
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -83,12 +84,41 @@ hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const vo
                         : ((!v64 && j > 256 && j <= 384) ? 12 : ((!v64 && j > 384 && j <= 448) ? 14 : pick_qw(j, 32)));
   hipStream_t s = c->stream;
   hipError_t e;
+  // An FP64 basis above kWindowCols columns goes through the row passes in
+  // column windows of at most kWindowCols (the accumulators of a wider one
+  // do not fit a workgroup's registers).  Column sums (D) of the windows are
+  // independent; Z = Y - W C takes the windows one after the other (Z = Y -
+  // W_0 C_0, then Z -= W_i C_i), and D = W^T Z is then a pass of its own.
+  const bool split = v64 && j > kWindowCols;
+  auto bpass = [&](int mode, bool src64, const BlockArgs &b) -> hipError_t {
+    if (!split) return launch_bpass(mode, v64, src64, nw, qw, b.G, b, s);
+    hipError_t r = hipSuccess;
+    for (int c0 = 0; c0 < j && r == hipSuccess; c0 += kWindowCols) {
+      BlockArgs w = b;
+      w.c0 = c0;
+      w.j = std::min(kWindowCols, j - c0);
+      r = launch_bpass(mode, v64, src64, nw, pick_qw(w.j, 32), w.G, w, s);
+    }
+    return r;
+  };
+  auto bpass_z1 = [&](const BlockArgs &b) -> hipError_t {
+    if (!split) return launch_bpass(1, v64, x64, nw, qw, b.G, b, s);
+    BlockArgs w = b;
+    w.j = kWindowCols;
+    hipError_t r = launch_bpass(4, v64, x64, nw, pick_qw(w.j, 32), w.G, w, s);  // Z = Y - W_0 C_0
+    for (int c0 = kWindowCols; c0 < j && r == hipSuccess; c0 += kWindowCols) {
+      w.c0 = c0;
+      w.j = std::min(kWindowCols, j - c0);
+      r = launch_bpass(2, v64, true, nw, pick_qw(w.j, 32), w.G, w, s);           // Z -= W_i C_i
+    }
+    return r != hipSuccess ? r : bpass(3, true, b);                               // D = W^T Z
+  };
   if ((e = launch_zgram(0, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // ||y_k||^2
-  if ((e = launch_bpass(0, v64, x64, nw, qw, a.G, a, s)) != hipSuccess) return e;       // D = W^T Y
+  if ((e = bpass(0, x64, a)) != hipSuccess) return e;                               // D = W^T Y
   if ((e = launch_breduce(1, a, s)) != hipSuccess) return e;                         // R1, coef
-  if ((e = launch_bpass(1, v64, x64, nw, qw, a.G, a, s)) != hipSuccess) return e;       // Z = Y - W C, D
+  if ((e = bpass_z1(a)) != hipSuccess) return e;                                    // Z = Y - W C, D
   if ((e = launch_breduce(2, a, s)) != hipSuccess) return e;                         // R2, R += R2, coef
-  if ((e = launch_bpass(2, v64, true, nw, qw, a.G, a, s)) != hipSuccess) return e;      // Z = Z - W C
+  if ((e = bpass(2, true, a)) != hipSuccess) return e;                              // Z = Z - W C
   if ((e = launch_zgram(1, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // Z^T Z
   // third projection, where the test asks for it (the gated kernels return
   // at once otherwise)
@@ -96,9 +126,9 @@ hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const vo
   if ((e = launch_bthird(a, gate, v64 ? 0x1p-53 : 0x1p-24, s)) != hipSuccess) return e;
   BlockArgs g = a;
   g.gate = gate;
-  if ((e = launch_bpass(3, v64, true, nw, qw, g.G, g, s)) != hipSuccess) return e;      // D = W^T Z
+  if ((e = bpass(3, true, g)) != hipSuccess) return e;                              // D = W^T Z
   if ((e = launch_breduce(3, g, s)) != hipSuccess) return e;                         // R3, R += R3, coef
-  if ((e = launch_bpass(2, v64, true, nw, qw, g.G, g, s)) != hipSuccess) return e;      // Z = Z - W C
+  if ((e = bpass(2, true, g)) != hipSuccess) return e;                              // Z = Z - W C
   if ((e = launch_zgram(1, v64, x64, g.Gz, g, s)) != hipSuccess) return e;          // Z^T Z
   // shifted CholeskyQR3: each Gram pass forms Z T_0 .. T_{t-1} row by row
   // from the unchanged Z, the last one writes Z T_0 T_1 T_2 into V
@@ -198,14 +228,11 @@ foa_status push_blocked_impl(foa_ctx_s *c, const void *d_X, int64_t ld, int32_t 
       if ((r = push_one(k)) != FOA_OK) return r;
     if ((r = sync_state(c)) != FOA_OK) return r;
   }
-  const bool v64 = c->prec == FOA_PREC_F64;
   while (k < p) {
     if (c->dev_status != ST_ACTIVE) break;
-    // blocks that can go now: whole blocks, basis sizes the block passes take
+    // blocks that can go now: the whole ones
     int nblk = 0;
-    while (k + (nblk + 1) * BPK <= p && range_ok &&
-           block_supported(v64, pick_qw(c->q_host + nblk * BPK, 32)))
-      ++nblk;
+    while (k + (nblk + 1) * BPK <= p && range_ok) ++nblk;
     if (nblk == 0) {
       while (k < p) {
         if ((r = push_one(k)) != FOA_OK) return r;

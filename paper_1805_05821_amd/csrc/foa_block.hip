@@ -77,14 +77,17 @@ hipError_t block_static_scratch(int device, char **ptr) {
   return g_scratch_err[device];
 }
 
-enum { BP_R1 = 0, BP_Z1 = 1, BP_Z2 = 2, BP_D = 3 };
+enum { BP_R1 = 0, BP_Z1 = 1, BP_Z2 = 2, BP_D = 3, BP_Z0 = 4 };
 bool block_supported(bool tv_f64, int qw);
 enum { ZG_YNORM = 0, ZG_GRAM = 1, ZG_WRITEV = 2 };
 
 // ---------------------------------------------------------------------------
-// Block row pass.  MODE BP_R1: D = W^T Y (column sums only).  BP_Z1:
-// Z = Y - W C, D = W^T Z.  BP_Z2: Z = Z - W C.  BP_D: D = W^T Z (column
-// sums of the block, for the third projection).  W is the stored basis (the
+// Block row pass over the basis columns c0 .. c0 + j - 1 (a.c0, a.j; the
+// whole basis unless an FP64 basis is split in two windows).  MODE BP_R1:
+// D = W^T Y (column sums only).  BP_Z1: Z = Y - W C, D = W^T Z.  BP_Z2:
+// Z = Z - W C.  BP_D: D = W^T Z (column sums of the block: the split form of
+// BP_Z1's second phase and the third projection).  BP_Z0: Z = Y - W C (the
+// split form of BP_Z1's first phase).  W is the stored basis (the
 // sigma scaling of its columns is folded into C and into the reduction of D).
 // Per panel, the BPK right-hand sides of a row are spread over the update
 // lanes (row, k); phase 1 and phase 2 are those of the single push with BPK
@@ -110,10 +113,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(bp_wave
   constexpr int JCAP = QW * NW * CPW;
   constexpr int RPW = PANEL / NW;
   constexpr int GSTRIDE = NW * CPW;
-  constexpr bool HAS_P1 = MODE == BP_Z1 || MODE == BP_Z2;
-  constexpr bool HAS_P2 = MODE != BP_Z2;
-  constexpr bool SRC_X = MODE == BP_R1 || MODE == BP_Z1;
-  constexpr bool STORE_Z = MODE == BP_Z1 || MODE == BP_Z2;
+  constexpr bool HAS_P1 = MODE == BP_Z1 || MODE == BP_Z2 || MODE == BP_Z0;
+  constexpr bool HAS_P2 = MODE == BP_R1 || MODE == BP_Z1 || MODE == BP_D;
+  constexpr bool SRC_X = MODE == BP_R1 || MODE == BP_Z1 || MODE == BP_Z0;
+  constexpr bool STORE_Z = MODE == BP_Z1 || MODE == BP_Z2 || MODE == BP_Z0;
   static_assert(RPW * BPK <= 64, "update lanes");
 
   if (a.st->status != ST_ACTIVE || *a.flag || (a.gate && !*a.gate)) return;
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(bp_wave
   const int slot = blockIdx.x;
 
   if (HAS_P1)
-    for (int c = tid; c < JCAP * BPK; c += NW * 64) s_coef[c] = (c < j * BPK) ? a.coef[c] : 0.0;
+    for (int c = tid; c < JCAP * BPK; c += NW * 64) s_coef[c] = (c < j * BPK) ? a.coef[a.c0 * BPK + c] : 0.0;
   __syncthreads();
 
   const int cbase = wave * CPW + cs;
@@ -149,7 +152,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(bp_wave
 #pragma unroll
     for (int k = 0; k < BPK; ++k) acc[g][k] = 0.0;
 
-  const char *Wb = static_cast<const char *>(a.W);
+  // the window's first column within each panel
+  const char *Wb = static_cast<const char *>(a.W) + (size_t)a.c0 * PANEL * sizeof(TV);
   const size_t pbytes = (size_t)a.n_max * PANEL * sizeof(TV);
   TV t[QW][EPL];
   TV tn[PF > 0 ? PF : 1][EPL];
@@ -267,7 +271,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(bp_wave
         double v = acc[g][k];
 #pragma unroll
         for (int m = 1; m < LPC; m <<= 1) v += xor_shfl(v, m);
-        if (rg == 0 && c < j) a.partb[((size_t)c * BPK + k) * a.ldg + slot] = v;
+        if (rg == 0 && c < j) a.partb[((size_t)(a.c0 + c) * BPK + k) * a.ldg + slot] = v;
       }
     }
   }
@@ -687,7 +691,7 @@ __global__ __launch_bounds__(256) void k_bthird(BlockArgs a, int *gate, double u
 template <typename TV, int QW, int MODE>
 constexpr int bp_pf() {
   if constexpr (sizeof(TV) == 8) {
-    return (QW <= 4 || MODE == BP_Z2) ? QW : 0;
+    return (QW <= 4 || MODE == BP_Z2 || MODE == BP_Z0) ? QW : 0;
   } else {
     if (QW == 8 && (MODE == BP_R1 || MODE == BP_D)) return 0;
     if (QW <= 8) return QW;
@@ -733,13 +737,16 @@ static hipError_t launch_bpass_m(int mode, int qw, int grid, const BlockArgs &a,
     case BP_R1: return launch_bpass_q<TV, TX, NW, BP_R1>(qw, grid, a, s);
     case BP_Z1: return launch_bpass_q<TV, TX, NW, BP_Z1>(qw, grid, a, s);
     case BP_D: return launch_bpass_q<TV, double, NW, BP_D>(qw, grid, a, s);
+    case BP_Z0:
+      if constexpr (sizeof(TV) == 8) return launch_bpass_q<TV, TX, NW, BP_Z0>(qw, grid, a, s);
+      return hipErrorInvalidValue;
     default: return launch_bpass_q<TV, double, NW, BP_Z2>(qw, grid, a, s);
   }
 }
 
-// Basis sizes the block passes take: an FP64 basis beyond 256 columns needs
-// more accumulator registers than a 16-wavefront workgroup has (those pushes
-// run one snapshot at a time).
+// Tile widths the block passes take: an FP64 window beyond 256 columns needs
+// more accumulator registers than a 16-wavefront workgroup has (a wider FP64
+// basis goes through the passes in windows of at most 256 columns).
 bool block_supported(bool tv_f64, int qw) { return !tv_f64 || qw <= 8; }
 
 hipError_t launch_bpass(int mode, bool tv_f64, bool tx_f64, int nw, int qw, int grid, const BlockArgs &a,

@@ -183,6 +183,7 @@ struct BlockArgs {
   int *flag;        // nonzero: the block (or an earlier one) was rejected
   const int *gate;  // non-null: the kernel runs only while *gate is nonzero (third projection)
   int tlev;         // block passes: triangular factors T_0 .. T_{tlev-1} applied to each row of Z
+  int c0;           // block row passes: first basis column of the window (j columns from it)
   DevState *st;
   double *H, *beta, *sigma;
   int64_t n, P;

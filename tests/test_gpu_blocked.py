@@ -1,8 +1,8 @@
 """Blocked form (foa_push_blocked, 4 snapshots per sweep of the basis) through
 the C ABI: against the blocked oracle (same algorithm, different summation
 order), against the sequential oracle within the O(eps kappa) bounds, and the
-fallbacks (breakdown, non-finite snapshots, an FP64 basis above 256 columns,
-the snapshots of a call that do not fill a block)."""
+fallbacks (breakdown, non-finite snapshots, the snapshots of a call that do
+not fill a block); an FP64 basis above 256 columns in column windows."""
 
 import numpy as np
 import pytest
@@ -108,13 +108,18 @@ def test_blocked_f32_within_bound(n, N):
     g["stream"].close()
 
 
-def test_blocked_f64_wide_basis_falls_back():
-    """FP64 basis beyond 256 columns: single pushes take over; results still
-    within the bound of the sequential oracle."""
-    X = _noisy(3000, 300)
+@pytest.mark.parametrize("n,N", [(3000, 300), (64 * 33 + 17, 512)])
+def test_blocked_f64_column_windows(n, N):
+    """FP64 basis beyond 256 columns: the row passes go over column windows
+    of at most 256 (the second window from 1 to 252 columns; N = 512 fills
+    the capacity).  Against the blocked and the sequential oracle."""
+    X = _noisy(n, N)
     g = _run_blocked(X, "f64")
+    ref = ob.foa_blocked(X)
+    kap, orth = _compare(g, ref, 10.0, EPS64, f"f64 windows N={N} vs blocked oracle")
+    assert orth <= 10 * np.sqrt(g["q"]) * EPS64
     seq = oracle.foa_batch(X)
-    _compare(g, seq, 10.0, EPS64, "f64 N=300")
+    _compare(g, seq, 10.0, EPS64, f"f64 windows N={N} vs sequential oracle")
     g["stream"].close()
 
 
