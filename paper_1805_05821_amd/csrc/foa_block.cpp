@@ -85,33 +85,43 @@ hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const vo
   hipStream_t s = c->stream;
   hipError_t e;
   // An FP64 basis above kWindowCols columns goes through the row passes in
-  // column windows of at most kWindowCols (the accumulators of a wider one
-  // do not fit a workgroup's registers).  Column sums (D) of the windows are
-  // independent; Z = Y - W C takes the windows one after the other (Z = Y -
-  // W_0 C_0, then Z -= W_i C_i), and D = W^T Z is then a pass of its own.
-  const bool split = v64 && j > kWindowCols;
+  // column windows (the accumulators of a wider one do not fit a
+  // workgroup's registers): the first window takes what the others, of
+  // kWindowCols each, leave.  Column sums (D) of the windows are
+  // independent.  Z = Y - W C goes window by window: Z = Y - W_0 C_0, then
+  // Z -= W_i C_i, the last window forming its D = W_i^T Z in the same pass;
+  // the other windows' D follow in passes of their own (with the narrow
+  // window first, the widest one is read once).
+  const int nwin = v64 ? (j + kWindowCols - 1) / kWindowCols : 1;
+  auto window = [&](const BlockArgs &b, int i) {
+    BlockArgs w = b;
+    const int first = j - (nwin - 1) * kWindowCols;
+    w.c0 = i == 0 ? 0 : first + (i - 1) * kWindowCols;
+    w.j = i == 0 ? first : kWindowCols;
+    return w;
+  };
   auto bpass = [&](int mode, bool src64, const BlockArgs &b) -> hipError_t {
-    if (!split) return launch_bpass(mode, v64, src64, nw, qw, b.G, b, s);
+    if (nwin == 1) return launch_bpass(mode, v64, src64, nw, qw, b.G, b, s);
     hipError_t r = hipSuccess;
-    for (int c0 = 0; c0 < j && r == hipSuccess; c0 += kWindowCols) {
-      BlockArgs w = b;
-      w.c0 = c0;
-      w.j = std::min(kWindowCols, j - c0);
+    for (int i = 0; i < nwin && r == hipSuccess; ++i) {
+      const BlockArgs w = window(b, i);
       r = launch_bpass(mode, v64, src64, nw, pick_qw(w.j, 32), w.G, w, s);
     }
     return r;
   };
   auto bpass_z1 = [&](const BlockArgs &b) -> hipError_t {
-    if (!split) return launch_bpass(1, v64, x64, nw, qw, b.G, b, s);
-    BlockArgs w = b;
-    w.j = kWindowCols;
+    if (nwin == 1) return launch_bpass(1, v64, x64, nw, qw, b.G, b, s);
+    BlockArgs w = window(b, 0);
     hipError_t r = launch_bpass(4, v64, x64, nw, pick_qw(w.j, 32), w.G, w, s);  // Z = Y - W_0 C_0
-    for (int c0 = kWindowCols; c0 < j && r == hipSuccess; c0 += kWindowCols) {
-      w.c0 = c0;
-      w.j = std::min(kWindowCols, j - c0);
-      r = launch_bpass(2, v64, true, nw, pick_qw(w.j, 32), w.G, w, s);           // Z -= W_i C_i
+    for (int i = 1; i < nwin && r == hipSuccess; ++i) {
+      w = window(b, i);                                                          // Z -= W_i C_i
+      r = launch_bpass(i == nwin - 1 ? 5 : 2, v64, true, nw, pick_qw(w.j, 32), w.G, w, s);
     }
-    return r != hipSuccess ? r : bpass(3, true, b);                               // D = W^T Z
+    for (int i = 0; i < nwin - 1 && r == hipSuccess; ++i) {
+      w = window(b, i);                                                          // D_i = W_i^T Z
+      r = launch_bpass(3, v64, true, nw, pick_qw(w.j, 32), w.G, w, s);
+    }
+    return r;
   };
   if ((e = launch_zgram(0, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // ||y_k||^2
   if ((e = bpass(0, x64, a)) != hipSuccess) return e;                               // D = W^T Y

@@ -77,7 +77,7 @@ hipError_t block_static_scratch(int device, char **ptr) {
   return g_scratch_err[device];
 }
 
-enum { BP_R1 = 0, BP_Z1 = 1, BP_Z2 = 2, BP_D = 3, BP_Z0 = 4 };
+enum { BP_R1 = 0, BP_Z1 = 1, BP_Z2 = 2, BP_D = 3, BP_Z0 = 4, BP_ZD = 5 };
 bool block_supported(bool tv_f64, int qw);
 enum { ZG_YNORM = 0, ZG_GRAM = 1, ZG_WRITEV = 2 };
 
@@ -86,8 +86,9 @@ enum { ZG_YNORM = 0, ZG_GRAM = 1, ZG_WRITEV = 2 };
 // whole basis unless an FP64 basis is split in two windows).  MODE BP_R1:
 // D = W^T Y (column sums only).  BP_Z1: Z = Y - W C, D = W^T Z.  BP_Z2:
 // Z = Z - W C.  BP_D: D = W^T Z (column sums of the block: the split form of
-// BP_Z1's second phase and the third projection).  BP_Z0: Z = Y - W C (the
-// split form of BP_Z1's first phase).  W is the stored basis (the
+// BP_Z1's second phase and the third projection).  BP_Z0: Z = Y - W C, and
+// BP_ZD: Z = Z - W C, D = W^T Z (the first and last window of BP_Z1 over a
+// split basis).  W is the stored basis (the
 // sigma scaling of its columns is folded into C and into the reduction of D).
 // Per panel, the BPK right-hand sides of a row are spread over the update
 // lanes (row, k); phase 1 and phase 2 are those of the single push with BPK
@@ -113,10 +114,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(bp_wave
   constexpr int JCAP = QW * NW * CPW;
   constexpr int RPW = PANEL / NW;
   constexpr int GSTRIDE = NW * CPW;
-  constexpr bool HAS_P1 = MODE == BP_Z1 || MODE == BP_Z2 || MODE == BP_Z0;
-  constexpr bool HAS_P2 = MODE == BP_R1 || MODE == BP_Z1 || MODE == BP_D;
+  constexpr bool HAS_P1 = MODE == BP_Z1 || MODE == BP_Z2 || MODE == BP_Z0 || MODE == BP_ZD;
+  constexpr bool HAS_P2 = MODE == BP_R1 || MODE == BP_Z1 || MODE == BP_D || MODE == BP_ZD;
   constexpr bool SRC_X = MODE == BP_R1 || MODE == BP_Z1 || MODE == BP_Z0;
-  constexpr bool STORE_Z = MODE == BP_Z1 || MODE == BP_Z2 || MODE == BP_Z0;
+  constexpr bool STORE_Z = MODE == BP_Z1 || MODE == BP_Z2 || MODE == BP_Z0 || MODE == BP_ZD;
   static_assert(RPW * BPK <= 64, "update lanes");
 
   if (a.st->status != ST_ACTIVE || *a.flag || (a.gate && !*a.gate)) return;
@@ -691,7 +692,7 @@ __global__ __launch_bounds__(256) void k_bthird(BlockArgs a, int *gate, double u
 template <typename TV, int QW, int MODE>
 constexpr int bp_pf() {
   if constexpr (sizeof(TV) == 8) {
-    return (QW <= 4 || MODE == BP_Z2 || MODE == BP_Z0) ? QW : 0;
+    return (QW <= 4 || MODE == BP_Z2 || MODE == BP_Z0) ? QW : 0;  // BP_ZD as BP_Z1
   } else {
     if (QW == 8 && (MODE == BP_R1 || MODE == BP_D)) return 0;
     if (QW <= 8) return QW;
@@ -739,6 +740,9 @@ static hipError_t launch_bpass_m(int mode, int qw, int grid, const BlockArgs &a,
     case BP_D: return launch_bpass_q<TV, double, NW, BP_D>(qw, grid, a, s);
     case BP_Z0:
       if constexpr (sizeof(TV) == 8) return launch_bpass_q<TV, TX, NW, BP_Z0>(qw, grid, a, s);
+      return hipErrorInvalidValue;
+    case BP_ZD:
+      if constexpr (sizeof(TV) == 8) return launch_bpass_q<TV, double, NW, BP_ZD>(qw, grid, a, s);
       return hipErrorInvalidValue;
     default: return launch_bpass_q<TV, double, NW, BP_Z2>(qw, grid, a, s);
   }
