@@ -156,8 +156,9 @@ foa_status foa_block_workspace_bytes(int64_t n, int32_t n_max, foa_prec prec, si
  * snapshot at a time by the sequential kernels (which apply the breakdown
  * and non-finite rules), as are the first snapshot of a stream, the
  * snapshots of the call that do not fill a block (p mod 4 of them, counted
- * after that first snapshot; taken first, while the basis is smallest) and,
- * for an FP64 basis, basis sizes above 256.
+ * after that first snapshot; taken first, while the basis is smallest).  An
+ * FP64 basis above 256 columns is swept in column windows of at most 256
+ * (same results up to rounding order).
  * d_bws: device buffer of foa_block_workspace_bytes bytes, 256-byte aligned,
  * caller-owned, contents not preserved.  Synchronising (the host checks each
  * run of blocks).  FOA_E_CAPACITY if q + p > n_max; FOA_E_STATE on a batch
