@@ -123,6 +123,51 @@ def test_blocked_f64_column_windows(n, N):
     g["stream"].close()
 
 
+def test_blocked_f64_windows_third_projection(monkeypatch):
+    """FP64 basis, rank-250 snapshots plus relative noise 1e-15 and no
+    breakdown rule (tol 0): the snapshots past the rank sit at the FP64 noise
+    floor and the blocked oracle takes the third projection in about ten of
+    the blocks from j = 256 on (which ones depends on the host's rounding),
+    i.e. through the column windows.  The oracle's basis keeps
+    ||I - V^T V||_2 about 2e-13 with it and 1.3e-10 without it, so the bound
+    1e-12 holds only if the gated passes run over both windows.  The leading
+    200 columns of H_bar (fixed by the first 201 snapshots) against the
+    blocked oracle within 10 m eps kappa_2; the factorisation X = V beta
+    within 100 eps."""
+    import dataclasses
+
+    base = datagen.get_workload("exact_rank_4096x64")
+    w = dataclasses.replace(base, pairs=125, noise=1e-15, kappa_max=None).with_n(2000).with_N(300)
+    X, lam, b = datagen.snapshots_numpy(w, dtype="float64")
+    g = _run_blocked(X, "f64", tol=0.0)
+    fired = []
+    test = ob.third_projection_needed
+
+    def record(R1, R2, Z, unit):
+        t = test(R1, R2, Z, unit)
+        if t:
+            fired.append(R1.shape[0])
+        return t
+
+    monkeypatch.setattr(ob, "third_projection_needed", record)
+    ref = ob.foa_blocked(X, tol=0.0)
+    announce(f"oracle third projections at j = {fired}")
+    assert len(fired) >= 5 and sum(j > 256 for j in fired) >= 4
+    assert g["q"] == ref.q == 300
+    V, B = g["V"], g["beta"][:300, :300]
+    orth = np.linalg.norm(np.eye(300) - V.T @ V, 2)
+    res = np.linalg.norm(X - V @ B) / np.linalg.norm(X)
+    m0 = 200
+    kap = kappa_of(ref.beta[:m0, :m0])
+    eH = rel(g["H"][:m0 + 1, :m0], ref.H[:m0 + 1, :m0])
+    announce(f"f64 windows, third projection: orth={orth:.2e} resid={res:.2e} relH[:200]={eH:.2e} "
+             f"(bound {10 * m0 * EPS64 * kap:.2e}, kappa {kap:.2e})")
+    assert orth <= 1e-12
+    assert res <= 100 * EPS64
+    assert eH <= 10 * m0 * EPS64 * kap
+    g["stream"].close()
+
+
 def test_blocked_exact_rank_breakdown():
     """The block that crosses the rank is taken one snapshot at a time: the
     breakdown rule fires at snapshot 21 and the generating eigenvalues are exact."""
