@@ -22,7 +22,7 @@ constexpr int kWindowCols = 256;   // widest column window of an FP64-basis bloc
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct BlockLayout {
-  size_t Z = 0, coef = 0, partb = 0, partg = 0, sm = 0, flag = 0, gate = 0, total = 0;
+  size_t Z = 0, coef = 0, partb = 0, partg = 0, partq = 0, dnext = 0, sm = 0, flag = 0, gate = 0, total = 0;
 };
 
 BlockLayout block_layout(int64_t n, int n_max, int ldg) {
@@ -38,6 +38,8 @@ BlockLayout block_layout(int64_t n, int n_max, int ldg) {
   B.coef = take((size_t)n_max * BPK * 8);
   B.partb = take((size_t)n_max * BPK * ldg * 8);
   B.partg = take((size_t)kGramGrid * BPK * BPK * 8);
+  B.partq = take((size_t)kGramGrid * BPK * BPK * 8);
+  B.dnext = take((size_t)n_max * BPK * 8);
   B.sm = take((size_t)SM_TOTAL * 8);
   B.flag = take(sizeof(int));
   B.gate = take(sizeof(int));
@@ -45,9 +47,13 @@ BlockLayout block_layout(int64_t n, int n_max, int ldg) {
   return B;
 }
 
-// All kernels of one block of BPK snapshots starting at basis size j.
+// All kernels of one block of BPK snapshots starting at basis size j.  xn:
+// the next block's snapshots when it follows in the same run (its first
+// projection over these j columns then rides on this block's last sweep);
+// have_d: this block's V^T Y over its first j - BPK columns was formed so
+// by the block before.
 hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const void *x, int64_t ldx, bool x64,
-                         int j) {
+                         int j, const void *xn, bool have_d) {
   const bool v64 = c->prec == FOA_PREC_F64;
   BlockArgs a{};
   a.W = c->W;
@@ -57,6 +63,9 @@ hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const vo
   a.coef = reinterpret_cast<double *>(bws + L.coef);
   a.partb = reinterpret_cast<double *>(bws + L.partb);
   a.partg = reinterpret_cast<double *>(bws + L.partg);
+  a.partq = reinterpret_cast<double *>(bws + L.partq);
+  a.dnext = reinterpret_cast<double *>(bws + L.dnext);
+  a.qy = have_d ? 1 : 0;
   a.sm = reinterpret_cast<double *>(bws + L.sm);
   a.flag = reinterpret_cast<int *>(bws + L.flag);
   a.st = c->sa.st;
@@ -123,12 +132,23 @@ hipError_t enqueue_block(foa_ctx_s *c, const BlockLayout &L, char *bws, const vo
     }
     return r;
   };
-  if ((e = launch_zgram(0, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // ||y_k||^2
-  if ((e = bpass(0, x64, a)) != hipSuccess) return e;                               // D = W^T Y
+  if (have_d) {
+    if ((e = launch_zgram(3, v64, x64, a.Gz, a, s)) != hipSuccess) return e;        // ||y_k||^2, q^T y_k
+  } else {
+    if ((e = launch_zgram(0, v64, x64, a.Gz, a, s)) != hipSuccess) return e;        // ||y_k||^2
+    if ((e = bpass(0, x64, a)) != hipSuccess) return e;                             // D = W^T Y
+  }
   if ((e = launch_breduce(1, a, s)) != hipSuccess) return e;                         // R1, coef
   if ((e = bpass_z1(a)) != hipSuccess) return e;                                    // Z = Y - W C, D
   if ((e = launch_breduce(2, a, s)) != hipSuccess) return e;                         // R2, R += R2, coef
-  if ((e = bpass(2, true, a)) != hipSuccess) return e;                              // Z = Z - W C
+  if (xn) {
+    BlockArgs r = a;
+    r.xn = xn;
+    if ((e = bpass(6, x64, r)) != hipSuccess) return e;                             // Z = Z - W C, D' = W^T Y'
+    if ((e = launch_breduce(4, r, s)) != hipSuccess) return e;                       // D' -> dnext
+  } else {
+    if ((e = bpass(2, true, a)) != hipSuccess) return e;                            // Z = Z - W C
+  }
   if ((e = launch_zgram(1, v64, x64, a.Gz, a, s)) != hipSuccess) return e;          // Z^T Z
   // third projection, where the test asks for it (the gated kernels return
   // at once otherwise)
@@ -253,7 +273,8 @@ foa_status push_blocked_impl(foa_ctx_s *c, const void *d_X, int64_t ld, int32_t 
     const int q0 = c->q_host;
     hipError_t e = launch_bflag_clear(flag, c->stream);
     for (int b = 0; b < nblk && e == hipSuccess; ++b)
-      e = enqueue_block(c, L, bws, X + (size_t)(k + b * BPK) * ld * es, ld, x64, q0 + b * BPK);
+      e = enqueue_block(c, L, bws, X + (size_t)(k + b * BPK) * ld * es, ld, x64, q0 + b * BPK,
+                        b + 1 < nblk ? X + (size_t)(k + (b + 1) * BPK) * ld * es : nullptr, b > 0);
     if (e != hipSuccess) return hip_err(c, e, "blocked push");
     c->mirror_valid = false;
     c->dmd.valid = false;

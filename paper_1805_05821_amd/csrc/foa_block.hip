@@ -77,9 +77,9 @@ hipError_t block_static_scratch(int device, char **ptr) {
   return g_scratch_err[device];
 }
 
-enum { BP_R1 = 0, BP_Z1 = 1, BP_Z2 = 2, BP_D = 3, BP_Z0 = 4, BP_ZD = 5 };
+enum { BP_R1 = 0, BP_Z1 = 1, BP_Z2 = 2, BP_D = 3, BP_Z0 = 4, BP_ZD = 5, BP_ZR = 6 };
 bool block_supported(bool tv_f64, int qw);
-enum { ZG_YNORM = 0, ZG_GRAM = 1, ZG_WRITEV = 2 };
+enum { ZG_YNORM = 0, ZG_GRAM = 1, ZG_WRITEV = 2, ZG_YNQ = 3 };
 
 // ---------------------------------------------------------------------------
 // Block row pass over the basis columns c0 .. c0 + j - 1 (a.c0, a.j; the
@@ -88,7 +88,10 @@ enum { ZG_YNORM = 0, ZG_GRAM = 1, ZG_WRITEV = 2 };
 // Z = Z - W C.  BP_D: D = W^T Z (column sums of the block: the split form of
 // BP_Z1's second phase and the third projection).  BP_Z0: Z = Y - W C, and
 // BP_ZD: Z = Z - W C, D = W^T Z (the first and last window of BP_Z1 over a
-// split basis).  W is the stored basis (the
+// split basis).  BP_ZR: Z = Z - W C and D = W^T Y' for the next block's
+// snapshots Y' (a.xn) in the same sweep (the next block's first projection
+// over these columns; the two phases are independent, so Y' goes to LDS at
+// phase 1's barrier).  W is the stored basis (the
 // sigma scaling of its columns is folded into C and into the reduction of D).
 // Per panel, the BPK right-hand sides of a row are spread over the update
 // lanes (row, k); phase 1 and phase 2 are those of the single push with BPK
@@ -114,10 +117,11 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(bp_wave
   constexpr int JCAP = QW * NW * CPW;
   constexpr int RPW = PANEL / NW;
   constexpr int GSTRIDE = NW * CPW;
-  constexpr bool HAS_P1 = MODE == BP_Z1 || MODE == BP_Z2 || MODE == BP_Z0 || MODE == BP_ZD;
-  constexpr bool HAS_P2 = MODE == BP_R1 || MODE == BP_Z1 || MODE == BP_D || MODE == BP_ZD;
+  constexpr bool NEXT_Y = MODE == BP_ZR;
+  constexpr bool HAS_P1 = MODE == BP_Z1 || MODE == BP_Z2 || MODE == BP_Z0 || MODE == BP_ZD || NEXT_Y;
+  constexpr bool HAS_P2 = MODE == BP_R1 || MODE == BP_Z1 || MODE == BP_D || MODE == BP_ZD || NEXT_Y;
   constexpr bool SRC_X = MODE == BP_R1 || MODE == BP_Z1 || MODE == BP_Z0;
-  constexpr bool STORE_Z = MODE == BP_Z1 || MODE == BP_Z2 || MODE == BP_Z0 || MODE == BP_ZD;
+  constexpr bool STORE_Z = MODE == BP_Z1 || MODE == BP_Z2 || MODE == BP_Z0 || MODE == BP_ZD || NEXT_Y;
   static_assert(RPW * BPK <= 64, "update lanes");
 
   if (a.st->status != ST_ACTIVE || *a.flag || (a.gate && !*a.gate)) return;
@@ -182,6 +186,14 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(bp_wave
       const __amdgpu_buffer_rsrc_t rz = make_rsrc(a.Z + p * PANEL * BPK, PANEL * BPK * 8);
       y = buf_load_scalar<double>(rz, uact ? (unsigned)((uk * PANEL + urow) * 8) : kOOR);
     }
+    double yn = 0.0;
+    if constexpr (NEXT_Y) {
+      const int64_t rem = a.n - p * PANEL;
+      const int valid = (int)(rem >= PANEL ? PANEL : (rem > 0 ? rem : 0));
+      const __amdgpu_buffer_rsrc_t rx = make_rsrc(static_cast<const TX *>(a.xn) + p * PANEL,
+                                                  (unsigned)(((BPK - 1) * a.ldx + valid) * sizeof(TX)));
+      yn = buf_load_scalar<TX>(rx, (uact && urow < valid) ? (unsigned)((uk * a.ldx + urow) * sizeof(TX)) : kOOR);
+    }
     if constexpr (PF < QW)  // the groups not prefetched, straight into their place
       load_tile_groups<TV, PF, QW, PF>(make_rsrc(Wb + (size_t)p * pbytes, tile_bytes), goff0, GBYTES, t);
     if constexpr (PF > 0) {
@@ -219,6 +231,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(bp_wave
 #pragma unroll
           for (int k = 0; k < BPK; ++k) s_red[par][wave][(rg * EPL + e) * BPK + k] = u[e][k];
       }
+      if (NEXT_Y && uact) s_w[par][urow * BPK + uk] = yn;
       __syncthreads();
 #pragma unroll
       for (int w2 = 0; w2 < NW; ++w2) us += s_red[par][w2][urow * BPK + uk];
@@ -229,8 +242,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(bp_wave
       buf_store_scalar<double>(wv, rz, uact ? (unsigned)((uk * PANEL + urow) * 8) : kOOR);
     }
     if (HAS_P2) {
-      if (uact) s_w[par][urow * BPK + uk] = wv;
-      __syncthreads();
+      if (!NEXT_Y) {
+        if (uact) s_w[par][urow * BPK + uk] = wv;
+        __syncthreads();
+      }
       if constexpr (sizeof(TV) == 4) {
 #pragma unroll
         for (int g = 0; g < QW; ++g)
@@ -280,7 +295,10 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(bp_wave
 
 // ---------------------------------------------------------------------------
 // Passes over the n x BPK block, one thread per row (rows grid-strided).
-// ZG_YNORM: partial ||y_k||^2 of the snapshots.  ZG_GRAM: the partial Gram
+// ZG_YNORM: partial ||y_k||^2 of the snapshots.  ZG_YNQ: the same and the
+// partial products q_c^T y_k of the previous block's new columns with the
+// snapshots (partq), when the sweep before formed V^T Y over the older
+// columns (BP_ZR).  ZG_GRAM: the partial Gram
 // matrix of Z T_0 .. T_{tlev-1} (T_t upper triangular, the inverses of the
 // Cholesky steps so far), formed row by row from Z, which is never
 // rewritten: the products are those a pass that stored Z T_0, then read it
@@ -298,7 +316,7 @@ __global__ __launch_bounds__(256) void k_zgram(BlockArgs a) {
   __shared__ double sT[3 * BPK * BPK];
   const int tid = threadIdx.x;
   const int tlev = a.tlev;
-  if (MODE != ZG_YNORM && tlev > 0) {
+  if (MODE != ZG_YNORM && MODE != ZG_YNQ && tlev > 0) {
     if (tid < tlev * BPK * BPK) sT[tid] = a.sm[SM_T + tid];
     __syncthreads();
   }
@@ -308,6 +326,38 @@ __global__ __launch_bounds__(256) void k_zgram(BlockArgs a) {
 #pragma unroll
     for (int l = 0; l < BPK; ++l) g[k][l] = 0.0;
   const int64_t npad = a.P * PANEL;
+  if constexpr (MODE == ZG_YNQ) {
+    // ||y_k||^2 and h[c][k] = q_c^T y_k for the previous block's new columns
+    // q_c = V(:, j - BPK + c): one row per grid stride
+    const TX *x = static_cast<const TX *>(a.x);
+    const TV *W = static_cast<const TV *>(a.W);
+    double h[BPK][BPK];
+#pragma unroll
+    for (int c = 0; c < BPK; ++c)
+#pragma unroll
+      for (int k = 0; k < BPK; ++k) h[c][k] = 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * 256 + tid; r < a.n; r += (int64_t)gridDim.x * 256) {
+      const TV *qr = W + ((r / PANEL) * a.n_max + (a.j - BPK)) * PANEL + r % PANEL;
+      double y[BPK], q[BPK];
+#pragma unroll
+      for (int k = 0; k < BPK; ++k) y[k] = (double)x[(int64_t)k * a.ldx + r];
+#pragma unroll
+      for (int c = 0; c < BPK; ++c) q[c] = (double)qr[c * PANEL];
+#pragma unroll
+      for (int k = 0; k < BPK; ++k) g[k][k] = fma(y[k], y[k], g[k][k]);
+#pragma unroll
+      for (int c = 0; c < BPK; ++c)
+#pragma unroll
+        for (int k = 0; k < BPK; ++k) h[c][k] = fma(q[c], y[k], h[c][k]);
+    }
+#pragma unroll
+    for (int c = 0; c < BPK; ++c)
+#pragma unroll
+      for (int k = 0; k < BPK; ++k) {
+        const double v = block_sum_256(h[c][k], sh);
+        if (tid == 0) a.partq[(size_t)blockIdx.x * GSLOT + c * BPK + k] = v;
+      }
+  }
   if constexpr (MODE == ZG_YNORM) {
     // the snapshots' rows, four grid strides in flight per thread (each sum
     // still takes its rows in the order of the plain loop below)
@@ -335,7 +385,8 @@ __global__ __launch_bounds__(256) void k_zgram(BlockArgs a) {
   }
   // the other passes take one row per grid stride (four in flight, as for
   // the snapshots above, measured 6-12% slower here)
-  for (int64_t r = (int64_t)blockIdx.x * 256 + tid; MODE != ZG_YNORM && r < npad; r += (int64_t)gridDim.x * 256) {
+  constexpr bool NORMS = MODE == ZG_YNORM || MODE == ZG_YNQ;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + tid; !NORMS && r < npad; r += (int64_t)gridDim.x * 256) {
     const int64_t p = r / PANEL;
     const int rr = (int)(r % PANEL);
     double z[BPK];
@@ -371,7 +422,7 @@ __global__ __launch_bounds__(256) void k_zgram(BlockArgs a) {
   for (int k = 0; k < BPK; ++k)
 #pragma unroll
     for (int l = 0; l < BPK; ++l) {
-      if (MODE == ZG_YNORM && k != l) continue;
+      if (NORMS && k != l) continue;
       const double s = block_sum_256(g[k][l], sh);
       if (tid == 0) a.partg[(size_t)blockIdx.x * GSLOT + k * BPK + l] = s;
     }
@@ -382,7 +433,10 @@ __global__ __launch_bounds__(256) void k_zgram(BlockArgs a) {
 // in a fixed order.  MODE 1 (after BP_R1): R = sigma o D, coef = sigma o R,
 // and (extra wavefronts) ||y_k||^2 from the ZG_YNORM partials.  MODE 2 (after
 // BP_Z1): R2 = sigma o D, R += R2, coef = sigma o R2.  MODE 3 (after BP_D):
-// R += sigma o D, coef = sigma o (sigma o D).
+// R += sigma o D, coef = sigma o (sigma o D).  MODE 1 with a.qy: D of the
+// columns before the previous block's from dnext (summed by MODE 4 during
+// that block), of the previous block's 4 from the ZG_YNQ partials.  MODE 4
+// (after BP_ZR): the raw sums D into dnext, for the next block.
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(256) void k_breduce(BlockArgs a) {
@@ -392,11 +446,24 @@ __global__ __launch_bounds__(256) void k_breduce(BlockArgs a) {
   const int npairs = a.j * BPK;
   if (wv < npairs) {
     const int c = wv / BPK, k = wv % BPK;
-    const double *pc = a.partb + (size_t)wv * a.ldg;
     double t = 0.0;
-    for (int g = lane; g < a.G; g += 64) t += pc[g];
+    if (MODE == 1 && a.qy && c < a.j - BPK) {
+      t = a.dnext[wv];
+    } else if (MODE == 1 && a.qy) {
+      const int e = (c - (a.j - BPK)) * BPK + k;
+      for (int g = lane; g < a.Gz; g += 64) t += a.partq[(size_t)g * GSLOT + e];
 #pragma unroll
-    for (int m = 1; m < 64; m <<= 1) t += xor_shfl(t, m);
+      for (int m = 1; m < 64; m <<= 1) t += xor_shfl(t, m);
+    } else {
+      const double *pc = a.partb + (size_t)wv * a.ldg;
+      for (int g = lane; g < a.G; g += 64) t += pc[g];
+#pragma unroll
+      for (int m = 1; m < 64; m <<= 1) t += xor_shfl(t, m);
+    }
+    if (MODE == 4) {
+      if (lane == 0) a.dnext[wv] = t;
+      return;
+    }
     if (lane == 0) {
       const double r = a.sigma[c] * t;
       const size_t idx = (size_t)c * BPK + k;
@@ -696,7 +763,7 @@ constexpr int bp_pf() {
   } else {
     if (QW == 8 && (MODE == BP_R1 || MODE == BP_D)) return 0;
     if (QW <= 8) return QW;
-    if (QW == 12) return MODE == BP_Z1 ? 6 : 12;
+    if (QW == 12) return (MODE == BP_Z1 || MODE == BP_ZR) ? 6 : 12;
     return MODE == BP_Z2 ? QW : 0;  // 14 and 16 groups
   }
 }
@@ -744,6 +811,7 @@ static hipError_t launch_bpass_m(int mode, int qw, int grid, const BlockArgs &a,
     case BP_ZD:
       if constexpr (sizeof(TV) == 8) return launch_bpass_q<TV, double, NW, BP_ZD>(qw, grid, a, s);
       return hipErrorInvalidValue;
+    case BP_ZR: return launch_bpass_q<TV, TX, NW, BP_ZR>(qw, grid, a, s);
     default: return launch_bpass_q<TV, double, NW, BP_Z2>(qw, grid, a, s);
   }
 }
@@ -770,6 +838,7 @@ static hipError_t launch_zgram_t(int mode, int grid, const BlockArgs &a, hipStre
   switch (mode) {
     case ZG_YNORM: hipLaunchKernelGGL((k_zgram<TV, TX, ZG_YNORM>), dim3(grid), dim3(256), 0, s, a); break;
     case ZG_GRAM: hipLaunchKernelGGL((k_zgram<TV, TX, ZG_GRAM>), dim3(grid), dim3(256), 0, s, a); break;
+    case ZG_YNQ: hipLaunchKernelGGL((k_zgram<TV, TX, ZG_YNQ>), dim3(grid), dim3(256), 0, s, a); break;
     default: hipLaunchKernelGGL((k_zgram<TV, TX, ZG_WRITEV>), dim3(grid), dim3(256), 0, s, a); break;
   }
   return hipGetLastError();
@@ -788,8 +857,10 @@ hipError_t launch_breduce(int mode, const BlockArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_breduce<1>, dim3(blocks), dim3(256), 0, s, a);
   else if (mode == 2)
     hipLaunchKernelGGL(k_breduce<2>, dim3(blocks), dim3(256), 0, s, a);
-  else
+  else if (mode == 3)
     hipLaunchKernelGGL(k_breduce<3>, dim3(blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_breduce<4>, dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

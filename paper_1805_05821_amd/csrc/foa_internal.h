@@ -184,6 +184,10 @@ struct BlockArgs {
   const int *gate;  // non-null: the kernel runs only while *gate is nonzero (third projection)
   int tlev;         // block passes: triangular factors T_0 .. T_{tlev-1} applied to each row of Z
   int c0;           // block row passes: first basis column of the window (j columns from it)
+  const void *xn;   // BP_ZR: first snapshot of the next block (same ldx and type as x)
+  double *dnext;    // raw column sums V^T Y of the next block over this block's j columns, [c * BPK + k]
+  double *partq;    // ZG_YNQ partials of (previous block's new columns)^T Y, [slot * BPK * BPK + c * BPK + k]
+  int qy;           // this block's V^T Y comes from dnext (old columns) and partq (the 4 newest)
   DevState *st;
   double *H, *beta, *sigma;
   int64_t n, P;
