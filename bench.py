@@ -12,10 +12,10 @@ q = 0.  The headline form stores the basis in FP32 with FP64 accumulation
 beside it, with the FP32-vs-FP64 error and kappa_2.
 
 Further legs (each reported in its own object of the JSON line): the blocked
-form on the same snapshots (4 snapshots per sweep of the basis; FP32 and FP64
-basis), the batched form on batched_256 (256 streams, one graph launch per
-step), the n = 1e8 run with its FP32-MFMA mode reconstruction, and the CPU
-oracle on a sample.
+form on the same snapshots (blocks of 4 snapshots, two sweeps of the basis per
+block; FP32 and FP64 basis), the batched form on batched_256 (256 streams, one
+graph launch per step), the n = 1e8 run with its FP32-MFMA mode
+reconstruction, and the CPU oracle on a sample.
 
 Output: one JSON line on stdout; progress on stderr.
 """
@@ -188,7 +188,7 @@ def run_indicator_log(X, n, N, every):
 
 
 def run_blocked(prec, X, n, N, warmup, steps):
-    """The blocked form (foa_push_blocked: 4 snapshots per sweep of the basis)
+    """The blocked form (foa_push_blocked: blocks of 4 snapshots)
     over the same snapshots, from q = 0; one step = one run over all N."""
     import torch
 
@@ -759,7 +759,7 @@ def main():
     if not args.no_blocked:
         try:
             rb = run_blocked("f32", X, n, N, args.warmup, args.steps)
-            blk = {"form": "fp32-basis, blocked (4 snapshots per basis sweep, block CGS2 + shifted CholeskyQR3)",
+            blk = {"form": "fp32-basis, blocked (blocks of 4 snapshots, two basis sweeps per block within a run, block CGS2 + shifted CholeskyQR3)",
                    "value": round(N / (rb["ms_per_step"] / 1e3), 3), "unit": "snapshots/s",
                    "ms_per_step": round(rb["ms_per_step"], 3), "q": rb["q"],
                    "speedup_vs_sequential_f32": round(r32["ms_per_step"] / rb["ms_per_step"], 3)}
@@ -782,7 +782,7 @@ def main():
                 eH = float(np.linalg.norm(Hb - H64, 2) / np.linalg.norm(H64, 2))
                 kap = out["error_f32_vs_f64"]["kappa2"]
                 out["blocked_form_f64"] = {
-                    "form": "fp64-basis, blocked (4 snapshots per basis sweep, column windows above 256)",
+                    "form": "fp64-basis, blocked (blocks of 4 snapshots, column windows above 256)",
                     "value": round(N / (rb["ms_per_step"] / 1e3), 3), "unit": "snapshots/s",
                     "ms_per_step": round(rb["ms_per_step"], 3), "q": rb["q"],
                     "speedup_vs_sequential_f64": round(r64["ms_per_step"] / rb["ms_per_step"], 3),
@@ -826,7 +826,7 @@ def main():
     # value stays the three-sweep form, the operation order of Algorithm 1)
     forms = [("three-sweep CGS2 (value)", out["value"])]
     for key, label in (("one_reduction_form", "one-reduction (delayed reorthogonalisation)"),
-                       ("blocked_form", "blocked (4 snapshots per sweep)")):
+                       ("blocked_form", "blocked (blocks of 4 snapshots)")):
         v = out.get(key, {}).get("value")
         if isinstance(v, (int, float)):
             forms.append((label, v))

@@ -141,7 +141,9 @@ foa_status foa_block_workspace_bytes(int64_t n, int32_t n_max, foa_prec prec, si
 /* Push p snapshots (rows of d_X, row stride ld >= n elements, x_dtype) in
  * blocks of 4: the factorisation X = V beta and H_bar of the modified FOA
  * (Section 2, eq. betacolumnupdate; the QR view of Section 3.1) reached with
- * three sweeps over the basis per block instead of per snapshot.  Per block:
+ * three sweeps over the basis per block instead of per snapshot, two within
+ * a run of blocks (a block's last sweep also forms the next block's V^T Y
+ * over the columns it sweeps).  Per block:
  * classical Gram-Schmidt of the whole block against V, twice, and a third
  * time where two passes may leave part of the block along V (a basis stored
  * in FP32 is orthonormal only to its rounding, which matters for snapshots

@@ -34,8 +34,8 @@ class FOAStream:
             F.foa_push_snapshot(self.ctx, X[k])
 
     def push_blocked(self, X):
-        """X: (p, n) tensor; blocked form (foa_push_blocked), 4 snapshots per
-        sweep of the basis.  The block workspace is allocated on first use."""
+        """X: (p, n) tensor; blocked form (foa_push_blocked), blocks of 4
+        snapshots.  The block workspace is allocated on first use."""
         import torch
 
         if getattr(self, "bws", None) is None:
