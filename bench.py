@@ -213,11 +213,14 @@ def run_blocked(prec, X, n, N, warmup, steps):
     ms = e0.elapsed_time(e1)
     st, q = s.sync()
     H, B, q, m = s.state()
-    log(f"[blocked {prec}] {steps} steps: {ms:.1f} ms, q={q}")
+    # truncated DMD of the last run at the storage precision's rank rule
+    r_tr, _ = s.truncate()
+    lam_tr, _ = s.indicators()
+    log(f"[blocked {prec}] {steps} steps: {ms:.1f} ms, q={q}, truncated rank {r_tr}")
     s.close()
     del s
     torch.cuda.empty_cache()
-    return dict(ms_per_step=ms / steps, q=q, H=H, m=m)
+    return dict(ms_per_step=ms / steps, q=q, H=H, beta=B, m=m, r_trunc=r_tr, lam_trunc=lam_tr)
 
 
 def _stream_gate(H32, lam32, r, H64, B64, m):
@@ -770,6 +773,7 @@ def main():
                 kap = out["error_f32_vs_f64"]["kappa2"]
                 blk["error_vs_f64_sequential"] = {"rel_H_2norm": eH, "bound_10_eps32_kappa": 10 * EPS32 * kap,
                                                   "within_bound": bool(eH <= 10 * EPS32 * kap)}
+                blk["error_vs_f64_sequential_truncated"] = truncated_gate(rb, r64)
             out["blocked_form"] = blk
         except Exception as e:  # reported, never silently dropped
             out["blocked_form"] = {"error": f"{type(e).__name__}: {e}"}

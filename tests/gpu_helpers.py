@@ -16,8 +16,10 @@ def announce(*parts):
 
 
 def run_gpu(X, prec="f64", tol=-1.0, snap_dtype=None, options=None, n_max=None, block=False, ws_fill=0xFF,
-            form="cgs2"):
-    """Push the columns of X (n x N NumPy) through the library; returns dict."""
+            form="cgs2", blocked=False):
+    """Push the columns of X (n x N NumPy) through the library; returns dict.
+    block: one foa_push_block call (the snapshots taken one at a time);
+    blocked: the blocked form (foa_push_blocked, blocks of 4 snapshots)."""
     import torch
 
     from paper_1805_05821_amd.stream import FOAStream
@@ -29,7 +31,9 @@ def run_gpu(X, prec="f64", tol=-1.0, snap_dtype=None, options=None, n_max=None, 
     s = FOAStream(n, n_max or N, prec=prec, breakdown_tol=tol, ws_fill=ws_fill, form=form)
     for k, v in (options or {}).items():
         s.set_option(k, v)
-    if block:
+    if blocked:
+        s.push_blocked(Xd)
+    elif block:
         s.push_block(Xd)
     else:
         s.push_all(Xd)

@@ -154,19 +154,46 @@ def test_headline_recipe_reduced_n(prec):
         assert worst <= 1.0
         assert ratio <= 1.0
     else:
-        orth = np.linalg.norm(np.eye(q) - _gram_gpu(g["stream"], q), 2)
-        announce(f"f32: kappa_2={kap:.2e} relH2={eH:.2e} (bound {10 * EPS32 * kap:.1e}, not binding) "
-                 f"||I-V^TV||={orth:.2e} (bound {10 * np.sqrt(q) * EPS32:.1e})")
-        assert eH <= 10 * EPS32 * kap
-        assert orth <= 10 * np.sqrt(q) * EPS32
-        # the default rank rule of the FP32 form picks the oracle's rank, with margin
-        r_g, sig_g = g["stream"].truncate()
-        r_o = oracle.truncation_rank(sig, st.q, "f32")
-        thr = st.q * oracle.spacing(sig[0], "f32")
-        margin = min(sig[r_o - 1] / thr, thr / sig[r_o] if r_o < len(sig) else np.inf)
-        announce(f"f32: default rank r={r_g} (oracle {r_o}, threshold margin x{margin:.2f})")
-        assert margin > 1.05 and r_g == r_o
-        _truncated_checks(g, st, r_o, EPS32, "f32 truncated (default rank)")
+        _f32_headline_checks(g, st, "f32")
+    g["stream"].close()
+
+
+def _f32_headline_checks(g, st, tag):
+    """FP32 basis on the throughput recipe: the untruncated bound (not
+    binding there), orthogonality, the default rank equal to the oracle's and
+    the binding truncated gates at that rank."""
+    q, m = g["q"], g["m"]
+    sig = PB.svals(st.beta[:m, :m])
+    kap = sig[0] / sig[-1]
+    H_o = st.H[:m, :m]
+    eH = np.linalg.norm(g["H"][:m, :m] - H_o, 2) / np.linalg.norm(H_o, 2)
+    orth = np.linalg.norm(np.eye(q) - _gram_gpu(g["stream"], q), 2)
+    announce(f"{tag}: kappa_2={kap:.2e} relH2={eH:.2e} (bound {10 * EPS32 * kap:.1e}, not binding) "
+             f"||I-V^TV||={orth:.2e} (bound {10 * np.sqrt(q) * EPS32:.1e})")
+    assert eH <= 10 * EPS32 * kap
+    assert orth <= 10 * np.sqrt(q) * EPS32
+    # the default rank rule of the FP32 form picks the oracle's rank, with margin
+    r_g, sig_g = g["stream"].truncate()
+    r_o = oracle.truncation_rank(sig, st.q, "f32")
+    thr = st.q * oracle.spacing(sig[0], "f32")
+    margin = min(sig[r_o - 1] / thr, thr / sig[r_o] if r_o < len(sig) else np.inf)
+    announce(f"{tag}: default rank r={r_g} (oracle {r_o}, threshold margin x{margin:.2f})")
+    assert margin > 1.05 and r_g == r_o
+    _truncated_checks(g, st, r_o, EPS32, f"{tag} truncated (default rank)")
+
+
+@pytest.mark.timeout(600)
+def test_headline_recipe_reduced_n_blocked():
+    """The blocked form (blocks of 4 snapshots, FP32 basis) on the same
+    recipe, n and gates as the sequential FP32 form, against the sequential
+    oracle: the fastest form on that workload is held to the same binding
+    truncated gates."""
+    w = datagen.get_workload("noisy_2p24x500").with_n(HEADLINE_ROWS)
+    X32, lam, b = datagen.snapshots_numpy(w)
+    st = oracle.foa_batch(X32.astype(np.float64))
+    g = run_gpu(X32, "f32", blocked=True)
+    assert g["q"] == st.q == w.N and g["m"] == oracle.projected_size(st)
+    _f32_headline_checks(g, st, "f32 blocked")
     g["stream"].close()
 
 
