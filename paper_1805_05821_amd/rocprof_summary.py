@@ -31,6 +31,13 @@
       the same per-launch HBM bytes for the kernels whose name starts with
       NAME_PREFIX, against the algorithmic bytes per launch that the
       benchmark's JSON line in BENCH_LOG holds under KEY.
+  python -m paper_1805_05821_amd.rocprof_summary counter_window FETCH_DIR WRITE_DIR \
+         FETCH_COPY_DIR WRITE_COPY_DIR COPY_BYTES PREFIX START COUNT
+      HBM bytes per dispatch (FETCH_SIZE and WRITE_SIZE scaled by the copy
+      calibration, as in kernel_traffic) averaged over the dispatches
+      START .. START+COUNT-1, in dispatch order, of the kernels whose name
+      starts with PREFIX: one kernel instance of one run in a counter pass
+      over several.
   python -m paper_1805_05821_amd.rocprof_summary batched_run DIR OCCURRENCE STEPS
       per-kernel time of one batched run in a kernel trace: the STEPS plan
       dispatches (k_batch_plan) that precede the OCCURRENCE-th FP64-basis
@@ -165,6 +172,29 @@ def kernel_traffic(fetch_dir, write_dir, fetch_copy, write_copy, copy_bytes, pre
     return {"kernels": prefix, "dispatches": [nf, nw], "fetch_bytes_per_launch": fetch_b,
             "write_bytes_per_launch": write_b, "traffic_bytes_per_launch": fetch_b + write_b,
             "alg_bytes_per_launch": alg, "traffic_over_alg": (fetch_b + write_b) / alg if alg else None,
+            "fetch_scale": f_scale, "write_scale": w_scale}
+
+
+def _prefix_window(d, counter, prefix, start, count):
+    per = defaultdict(float)
+    for f in _find(d, "counter_collection.csv"):
+        for r in csv.DictReader(open(f)):
+            if _col(r, "Counter_Name") == counter and _col(r, "Kernel_Name").startswith(prefix):
+                per[int(_col(r, "Dispatch_Id"))] += float(_col(r, "Counter_Value"))
+    ids = sorted(per)
+    sel = ids[int(start):int(start) + int(count)]
+    return sum(per[i] for i in sel) / max(len(sel), 1), len(sel), len(ids)
+
+
+def counter_window(fetch_dir, write_dir, fetch_copy, write_copy, copy_bytes, prefix, start, count):
+    copy_bytes = float(copy_bytes)
+    f_scale = copy_bytes / _copy_value(fetch_copy, "FETCH_SIZE")
+    w_scale = copy_bytes / _copy_value(write_copy, "WRITE_SIZE")
+    f_avg, nf, tf = _prefix_window(fetch_dir, "FETCH_SIZE", prefix, start, count)
+    w_avg, nw, tw = _prefix_window(write_dir, "WRITE_SIZE", prefix, start, count)
+    return {"kernels": prefix, "window": [int(start), int(count)], "dispatches": [nf, nw],
+            "of": [tf, tw], "fetch_bytes_per_launch": f_avg * f_scale, "write_bytes_per_launch": w_avg * w_scale,
+            "traffic_bytes_per_launch": f_avg * f_scale + w_avg * w_scale,
             "fetch_scale": f_scale, "write_scale": w_scale}
 
 
@@ -332,6 +362,10 @@ def main(argv):
         import json
 
         print(json.dumps(kernel_traffic(*argv[1:9]), indent=1))
+    elif len(argv) >= 9 and argv[0] == "counter_window":
+        import json
+
+        print(json.dumps(counter_window(*argv[1:9]), indent=1))
     elif len(argv) >= 4 and argv[0] == "batched_run":
         print(batched_run(argv[1], argv[2], argv[3]))
     elif len(argv) >= 6 and argv[0] == "batched":

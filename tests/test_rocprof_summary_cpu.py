@@ -88,3 +88,20 @@ def test_kernel_traffic_scales_by_the_copy(tmp_path):
     assert r["fetch_bytes_per_launch"] == pytest.approx(2000.0 * 2048)
     assert r["write_bytes_per_launch"] == pytest.approx(100.0 * 1024)
     assert r["traffic_over_alg"] == pytest.approx(1.0)
+
+
+def test_counter_window_picks_dispatches_in_order_and_scales(tmp_path):
+    copy_bytes = 4 << 30
+    _counters(str(tmp_path / "fc" / "c_counter_collection.csv"), [("__amd_rocclr_copyBuffer", "FETCH_SIZE", [2.0 ** 21])])
+    _counters(str(tmp_path / "wc" / "c_counter_collection.csv"), [("__amd_rocclr_copyBuffer", "WRITE_SIZE", [2.0 ** 22])])
+    # four dispatches of the kernel (two runs of two), another kernel in between
+    _counters(str(tmp_path / "f" / "k_counter_collection.csv"),
+              [("void foa::k_bpass<float, 1>", "FETCH_SIZE", [10.0, 20.0]), ("void foa::other", "FETCH_SIZE", [7.0]),
+               ("void foa::k_bpass<float, 1>", "FETCH_SIZE", [100.0, 300.0])])
+    _counters(str(tmp_path / "w" / "k_counter_collection.csv"),
+              [("void foa::k_bpass<float, 1>", "WRITE_SIZE", [1.0, 1.0, 4.0, 6.0])])
+    r = RS.counter_window(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "fc"), str(tmp_path / "wc"),
+                          copy_bytes, "void foa::k_bpass<float", 2, 2)
+    assert r["dispatches"] == [2, 2] and r["of"] == [4, 4]
+    assert r["fetch_bytes_per_launch"] == pytest.approx(200.0 * 2048)
+    assert r["write_bytes_per_launch"] == pytest.approx(5.0 * 1024)
